@@ -1,0 +1,488 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+The short-range sum (paper Sec. 2: direct particle-particle sums for the
+short-range part of a split force; Sec. 2.1: active particles receive forces,
+passive overload copies are sources only) is checked against:
+
+* the gradient of a potential energy written independently here (the
+  antiderivative of the pair kernel, differentiated by finite differences),
+  which fixes the kernel's powers, signs, filter indices, mass index and
+  direction;
+* textbook Newtonian and Plummer two-body forces, including across the
+  periodic face and exactly zero past the cutoff;
+* an all-pairs sum over explicit periodic images (no cells, no minimum image);
+* scipy's k-d tree pair count for the neighbour search;
+* Newton's third law, translation / image / permutation / cube-symmetry
+  invariance, locality and mass linearity;
+* for the adjoint: central finite differences of the forward oracle, the
+  symmetric-Jacobian identity of a gradient field and the adjoint dot test.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle
+from paper_1411_3396_amd import synth
+
+RNG = np.random.default_rng
+
+
+def prob(length, periodic=True, r_s=3.0, eps=0.05, poly=None, lo=None):
+    if poly is None:
+        poly = synth.filter_poly(3.0, 0.05) if (r_s == 3.0 and eps == 0.05) else (0,) * 6
+    if lo is None:
+        lo = (0.0, 0.0, 0.0)
+    return synth.Problem.make(lo, (length,) * 3 if np.isscalar(length) else length, periodic,
+                              r_s, eps, poly)
+
+
+def random_poly(rng, r_s=3.0):
+    """Coefficients whose terms are all O(1) at s ~ r_s^2."""
+    return tuple(float(np.float32(rng.uniform(-1, 1) * 0.05 / (r_s * r_s) ** k)) for k in range(6))
+
+
+def min_image(d, length, periodic):
+    if periodic:
+        d = d - length * np.round(d / length)
+    return d
+
+
+# ---------------------------------------------------------------- potential
+
+def potential(x, m, P):
+    """U = sum_{i<j, s<r_s^2} m_i m_j phi(s), phi(s) = -(s+eps^2)^-1/2 - sum c_k s^(k+1)/(2k+2)."""
+    n = x.shape[0]
+    L = np.array(P.len, np.float64)
+    d = x[None, :, :] - x[:, None, :]
+    d = min_image(d, L, P.periodic)
+    s = np.sum(d * d, axis=2)
+    iu = np.triu_indices(n, 1)
+    s = s[iu]
+    mm = (m[:, None] * m[None, :])[iu]
+    keep = s < P.r_s ** 2
+    e2 = float(P.eps) ** 2
+    phi = -1.0 / np.sqrt(s + e2)
+    for k, c in enumerate(P.poly):
+        phi = phi - c * s ** (k + 1) / (2.0 * (k + 1))
+    return float(np.sum((mm * phi)[keep]))
+
+
+def near_cutoff(x, P, h):
+    """Pairs whose separation lies within 3h of r_s (FD would straddle the cutoff)."""
+    L = np.array(P.len, np.float64)
+    d = min_image(x[None, :, :] - x[:, None, :], L, P.periodic)
+    r = np.sqrt(np.sum(d * d, axis=2))
+    np.fill_diagonal(r, 0.0)
+    return np.abs(r - P.r_s) < 3 * h
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("eps", [0.05, 0.3])
+def test_force_is_minus_gradient_of_potential(periodic, eps):
+    rng = RNG(11 + int(periodic) + int(eps * 10))
+    P = prob(10.0, periodic, 3.0, eps, random_poly(rng))
+    n = 48
+    x = rng.random((n, 3)) * 10.0
+    m = rng.uniform(0.5, 2.0, n)
+    acc, _ = oracle.force(x, m, n, P)
+    h = 1e-5
+    close = near_cutoff(x, P, h)
+    checked = 0
+    for i in range(0, n, 3):
+        if close[i].any():
+            continue
+        for a in range(3):
+            xp = x.copy()
+            xp[i, a] += h
+            xm = x.copy()
+            xm[i, a] -= h
+            dU = (potential(xp, m, P) - potential(xm, m, P)) / (2 * h)
+            fd = -dU / m[i]
+            assert abs(fd - acc[i, a]) <= 1e-6 * max(1.0, abs(acc[i, a])), (i, a, fd, acc[i, a])
+            checked += 1
+    assert checked >= 15
+
+
+# ---------------------------------------------------------------- two body
+
+def two_body(d, r_s=3.0, eps=0.0, length=32.0, periodic=False, m2=1.0, poly=(0,) * 6):
+    P = prob(length, periodic, r_s, eps, poly)
+    x1 = np.array([10.0, 11.0, 12.0])
+    x = np.stack([x1, x1 + np.asarray(d, np.float64)])
+    acc, _ = oracle.force(x, np.array([1.0, m2]), 2, P)
+    return acc, x[1] - x[0]
+
+
+@pytest.mark.parametrize("r", [1e-3, 0.05, 0.3, 1.0, 2.0, 2.9, 2.999])
+def test_two_body_newton(r):
+    # textbook Newtonian attraction: a_1 = m_2 (x_2 - x_1) / r^3
+    for direction in (np.array([1.0, 0, 0]), np.array([1.0, -2.0, 0.5]) / math.sqrt(5.25)):
+        acc, d = two_body(r * direction, m2=2.5)
+        r = np.linalg.norm(d)
+        expect = 2.5 * d / r ** 3
+        np.testing.assert_allclose(acc[0], expect, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(acc[1], -expect / 2.5, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("r", [0.01, 0.05, 0.5, 2.0])
+def test_two_body_plummer(r):
+    # textbook Plummer softening: a_1 = m_2 d / (r^2 + eps^2)^(3/2)
+    eps = float(np.float32(0.05))  # the problem carries float32 values
+    acc, d = two_body(np.array([0.0, r, 0.0]), eps=eps)
+    r = np.linalg.norm(d)
+    np.testing.assert_allclose(acc[0], d / (r * r + eps * eps) ** 1.5, rtol=1e-12)
+
+
+def test_constant_filter_is_a_linear_spring():
+    # poly = c0 only: the filter part subtracts m_2 c0 d (a harmonic pull the other way)
+    c0 = 0.125
+    acc, d = two_body(np.array([0.7, -0.2, 0.4]), poly=(c0, 0, 0, 0, 0, 0))
+    r = np.linalg.norm(d)
+    np.testing.assert_allclose(acc[0], d / r ** 3 - c0 * d, rtol=1e-12)
+
+
+@pytest.mark.parametrize("r", [3.0, 3.001, 4.0, 15.9])
+def test_zero_past_cutoff(r):
+    for eps in (0.0, 0.05):
+        acc, _ = two_body(np.array([0.0, 0.0, r]), eps=eps, periodic=True,
+                       poly=synth.filter_poly(3.0, 0.05))
+        assert np.all(acc == 0.0)
+
+
+def test_two_body_across_periodic_face():
+    L = 32.0
+    P = prob(L, True, 3.0, 0.0, (0,) * 6)
+    x = np.array([[0.4, 5.0, 5.0], [L - 0.6, 5.0, 5.0]])
+    acc, pairs = oracle.force(x, np.ones(2), 2, P)
+    # minimum image: x_2 - x_1 = -1 along x
+    np.testing.assert_allclose(acc[0], [-1.0, 0, 0], rtol=1e-12)
+    np.testing.assert_allclose(acc[1], [1.0, 0, 0], rtol=1e-12)
+    assert pairs == 2
+
+
+def test_coincident_pair_contributes_nothing():
+    P = prob(16.0, True, 3.0, 0.0, (0,) * 6)
+    x = np.array([[1.0, 2.0, 3.0], [1.0, 2.0, 3.0], [2.0, 2.0, 3.0]])
+    acc, pairs = oracle.force(x, np.ones(3), 3, P)
+    np.testing.assert_allclose(acc[0], [1.0, 0, 0])
+    np.testing.assert_allclose(acc[2], [-2.0, 0, 0])
+    assert pairs == 4
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("n", [2, 3, 64, 512, 2048])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_cell_list_equals_all_images(n, periodic):
+    rng = RNG(n + 7 * periodic)
+    L = 12.0 if n <= 64 else 20.0
+    P = prob(L, periodic, 3.0, 0.05, random_poly(rng))
+    x = rng.random((n, 3)) * L
+    if not periodic:
+        x = x - 1.5  # some particles outside the nominal extent
+    m = rng.uniform(0.5, 2.0, n)
+    n_act = max(1, (3 * n) // 4)
+    a_cell, _ = oracle.force(x, m, n_act, P)
+    a_brute = oracle.force_brute(x, m, n_act, P)
+    scale = np.max(np.abs(a_brute)) + 1e-300
+    assert np.max(np.abs(a_cell - a_brute)) <= 1e-13 * scale
+
+
+def test_pair_count_matches_kdtree():
+    w = synth.uniform_box(4096, 16.0, 5)
+    _, pairs = oracle.force(w.pos, w.mass, w.n, w.problem)
+    tree = cKDTree(w.pos.astype(np.float64), boxsize=16.0)
+    assert pairs == 2 * len(tree.query_pairs(3.0))
+
+
+def test_target_subset_equals_full_rows():
+    w = synth.clustered_box(20000, 24.0, 20, 3)
+    full, pairs_all = oracle.force(w.pos, w.mass, w.n, w.problem)
+    idx = synth.sample_indices(w.n, 500, 1)
+    sub, _ = oracle.force(w.pos, w.mass, w.n, w.problem, targets=idx)
+    np.testing.assert_array_equal(sub, full[idx])
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_newton_third_law_periodic():
+    rng = RNG(3)
+    P = prob(20.0, True)
+    n = 3000
+    x = rng.random((n, 3)) * 20.0
+    m = rng.uniform(0.1, 3.0, n)
+    acc, _ = oracle.force(x, m, n, P)
+    mom = np.sum(m[:, None] * acc, axis=0)
+    assert np.linalg.norm(mom) <= 1e-12 * np.sum(m[:, None] * np.abs(acc))
+
+
+def test_translation_and_image_invariance():
+    rng = RNG(4)
+    P = prob(18.0, True)
+    x = rng.random((1500, 3)) * 18.0
+    m = rng.uniform(0.5, 2.0, 1500)
+    a0, _ = oracle.force(x, m, 1500, P)
+    t = np.array([5.25, -7.5, 11.125])
+    a1, _ = oracle.force(np.mod(x + t, 18.0), m, 1500, P)
+    np.testing.assert_allclose(a1, a0, rtol=0, atol=1e-11 * np.abs(a0).max())
+    x2 = x.copy()
+    x2[::7, 0] += 18.0
+    x2[::5, 2] -= 18.0
+    a2, _ = oracle.force(x2, m, 1500, P)
+    np.testing.assert_allclose(a2, a0, rtol=0, atol=1e-11 * np.abs(a0).max())
+
+
+def test_permutation_invariance():
+    w = synth.clustered_box(6000, 16.0, 8, 9)
+    a0, _ = oracle.force(w.pos, w.mass, w.n, w.problem)
+    p = RNG(1).permutation(w.n)
+    a1, _ = oracle.force(w.pos[p], w.mass[p], w.n, w.problem)
+    np.testing.assert_allclose(a1, a0[p], rtol=0, atol=1e-12 * np.abs(a0).max())
+
+
+def test_cube_symmetries():
+    rng = RNG(5)
+    L = 15.0
+    P = prob(L, True)
+    x = rng.random((1200, 3)) * L
+    m = rng.uniform(0.5, 2.0, 1200)
+    a0, _ = oracle.force(x, m, 1200, P)
+    tol = 1e-11 * np.abs(a0).max()
+    # axis permutation (x, y, z) -> (z, x, y)
+    a1, _ = oracle.force(x[:, [2, 0, 1]], m, 1200, P)
+    np.testing.assert_allclose(a1, a0[:, [2, 0, 1]], rtol=0, atol=tol)
+    # reflection of y: y -> L - y flips a_y
+    xr = x.copy()
+    xr[:, 1] = L - xr[:, 1]
+    a2, _ = oracle.force(xr, m, 1200, P)
+    np.testing.assert_allclose(a2, a0 * np.array([1, -1, 1]), rtol=0, atol=tol)
+
+
+def test_far_particle_changes_nothing_and_mass_is_linear():
+    rng = RNG(6)
+    P = prob(40.0, False, lo=(0, 0, 0))
+    x = rng.random((800, 3)) * 10.0
+    m = rng.uniform(0.5, 2.0, 800)
+    a0, _ = oracle.force(x, m, 800, P)
+    x1 = np.concatenate([x, [[30.0, 30.0, 30.0]]])
+    a1, _ = oracle.force(x1, np.concatenate([m, [5.0]]), 801, P)
+    np.testing.assert_array_equal(a1[:800], a0)
+    assert np.all(a1[800] == 0.0)
+    a2, _ = oracle.force(x, 3.0 * m, 800, P)
+    np.testing.assert_allclose(a2, 3.0 * a0, rtol=1e-14, atol=1e-14 * np.abs(a0).max())
+
+
+def test_passive_particles_are_sources_only():
+    rng = RNG(8)
+    P = prob(12.0, False)
+    x = rng.random((300, 3)) * 12.0
+    m = rng.uniform(0.5, 2.0, 300)
+    a_all, _ = oracle.force(x, m, 300, P)
+    a_act, _ = oracle.force(x, m, 200, P)
+    np.testing.assert_array_equal(a_act, a_all[:200])
+
+
+def test_empty_and_degenerate_inputs():
+    P = prob(12.0, True)
+    acc, pairs = oracle.force(np.zeros((0, 3)), np.zeros(0), 0, P)
+    assert acc.shape == (0, 3) and pairs == 0
+    acc, pairs = oracle.force(np.array([[1.0, 1.0, 1.0]]), np.ones(1), 1, P)
+    assert np.all(acc == 0.0) and pairs == 0
+    with pytest.raises(ValueError):
+        oracle.force(np.zeros((2, 3)), np.ones(2), 2, prob(5.0, True))  # L < 3 r_s
+
+
+# ---------------------------------------------------------------- adjoint
+
+def _loss_grad_fd(x, m, n_act, P, g, idx, h):
+    out = np.zeros((len(idx), 3))
+    for q, k in enumerate(idx):
+        for a in range(3):
+            xp = x.copy()
+            xp[k, a] += h
+            xm = x.copy()
+            xm[k, a] -= h
+            ap, _ = oracle.force(xp, m, n_act, P)
+            am, _ = oracle.force(xm, m, n_act, P)
+            out[q, a] = np.sum(g * (ap - am)) / (2 * h)
+    return out
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_vjp_matches_finite_differences(periodic):
+    rng = RNG(21 + periodic)
+    P = prob(12.0, periodic, 3.0, 0.05, random_poly(rng))
+    n = 400
+    n_act = n if periodic else 300
+    x = rng.random((n, 3)) * 12.0
+    m = rng.uniform(0.5, 2.0, n)
+    g = rng.standard_normal((n_act, 3))
+    h = 1e-6
+    close = near_cutoff(x, P, h)
+    idx = [k for k in range(0, n, 13) if not close[k].any()][:20]
+    fd = _loss_grad_fd(x, m, n_act, P, g, idx, h)
+    vj = oracle.vjp(x, m, n_act, P, g, targets=np.array(idx))
+    assert oracle.rms_rel(vj, fd) < 1e-6
+
+
+def test_vjp_equals_jvp_for_equal_masses():
+    # equal masses, all active: the force is a gradient field, so its Jacobian
+    # is symmetric and J^T g = J g = (a(x + h g) - a(x - h g)) / 2h
+    rng = RNG(31)
+    P = prob(14.0, True)
+    n = 600
+    x = rng.random((n, 3)) * 14.0
+    m = np.ones(n)
+    g = rng.standard_normal((n, 3))
+    h = 1e-6
+    ap, _ = oracle.force(x + h * g, m, n, P)
+    am, _ = oracle.force(x - h * g, m, n, P)
+    jvp = (ap - am) / (2 * h)
+    vjp = oracle.vjp(x, m, n, P, g)
+    assert oracle.rms_rel(vjp, jvp) < 1e-5
+
+
+def test_vjp_dot_test_with_passive():
+    rng = RNG(41)
+    P = prob(12.0, False)
+    n, n_act = 500, 350
+    x = rng.random((n, 3)) * 12.0
+    m = rng.uniform(0.5, 2.0, n)
+    g = rng.standard_normal((n_act, 3))
+    v = rng.standard_normal((n, 3))
+    h = 1e-6
+    ap, _ = oracle.force(x + h * v, m, n_act, P)
+    am, _ = oracle.force(x - h * v, m, n_act, P)
+    lhs = np.sum(g * (ap - am) / (2 * h))
+    rhs = np.sum(oracle.vjp(x, m, n_act, P, g) * v)
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_vjp_cell_list_equals_all_images(periodic):
+    rng = RNG(51 + periodic)
+    P = prob(11.0, periodic, 3.0, 0.05, random_poly(rng))
+    n = 256
+    n_act = 200
+    x = rng.random((n, 3)) * 11.0
+    m = rng.uniform(0.5, 2.0, n)
+    g = rng.standard_normal((n_act, 3))
+    a = oracle.vjp(x, m, n_act, P, g)
+    b = oracle.vjp_brute(x, m, n_act, P, g)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+def test_two_body_jacobian():
+    # d a_1 / d x_2 = m_2 [f I + 2 f' d d^T]; check its column along d by FD of the
+    # closed Newtonian form (poly 0, eps 0): f = r^-3, f' = -1.5 r^-5
+    d = np.array([0.6, 0.3, -0.9])
+    r = np.linalg.norm(d)
+    P = prob(32.0, False, 3.0, 0.0, (0,) * 6)
+    x = np.array([[5.0, 5.0, 5.0], 5.0 + d])
+    g = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])  # only a_1 . e_x in the loss
+    grad = oracle.vjp(x, np.array([1.0, 1.0]), 2, P, g)
+    jac = (r ** -3) * np.eye(3) - 3.0 * r ** -5 * np.outer(d, d)
+    np.testing.assert_allclose(grad[1], jac[0], rtol=1e-12)
+    np.testing.assert_allclose(grad[0], -jac[0], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- binning rule
+
+def _check_bins(pos, P, res):
+    n = pos.shape[0]
+    nc = res["nc"].astype(np.int64)
+    cell_of = res["cell_of"].astype(np.int64)
+    perm = res["perm"].astype(np.int64)
+    start = res["cell_start"].astype(np.int64)
+    ncell = int(np.prod(nc))
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    assert np.array_equal(perm, np.argsort(cell_of, kind="stable"))
+    assert np.array_equal(start, np.concatenate([[0], np.cumsum(np.bincount(cell_of, minlength=ncell))]))
+    # geometry, in float64: the cell brackets the (wrapped) coordinate up to rounding
+    L = np.array(P.len, np.float64)
+    lo = np.array(P.lo, np.float64)
+    h = L / nc
+    x = pos.astype(np.float64)
+    if P.periodic:
+        x = np.mod(x, L)
+    u = (x - lo) / h
+    iz = cell_of % nc[2]
+    iy = (cell_of // nc[2]) % nc[1]
+    ix = cell_of // (nc[2] * nc[1])
+    idx = np.stack([ix, iy, iz], axis=1)
+    inside = (u >= 0) & (u < nc)
+    clamped = np.clip(np.floor(u), 0, nc - 1)
+    ok = (idx == clamped) | (np.abs(u - np.round(u)) < 1e-5 * np.maximum(1.0, u))
+    ok |= P.periodic & (np.abs(u - nc) < 1e-5 * nc)
+    assert np.all(ok | ~np.isfinite(u))
+    # offsets from the cell centre, in binned order
+    centre = lo + (idx + 0.5) * h
+    off64 = (x - centre)[perm]
+    wrapdiff = np.abs(res["off"].astype(np.float64) - off64)
+    if P.periodic:
+        wrapdiff = np.minimum(wrapdiff, np.abs(wrapdiff - L))
+    assert np.all(wrapdiff <= 4e-7 * np.maximum(1.0, np.abs(x[perm])) + 1e-6 * h)
+    assert np.all(np.abs(res["off"][inside.all(axis=1)[perm]]) <= 0.5 * h * (1 + 1e-5))
+
+
+@pytest.mark.parametrize("name", ["uniform", "clustered", "slab"])
+def test_bin_reference_rules(name):
+    if name == "uniform":
+        w = synth.uniform_box(30000, 32.0, 1)
+    elif name == "clustered":
+        w = synth.clustered_box(40000, 30.0, 40, 2)
+    else:
+        w = synth.slab_with_ghosts(30, 3.0, 50, 3)
+    res = oracle.bin_reference(w.pos, w.problem)
+    _check_bins(w.pos, w.problem, res)
+    assert res["flags"] == 0
+
+
+def test_bin_reference_adversarial():
+    L = 32.0
+    P = prob(L, True)
+    h = np.float32(3.2)
+    ulp = np.spacing(np.float32(L))
+    pts = [0.0, L - ulp, -0.0, h, 2 * h, 9 * h, L - h, np.float32(L) - np.float32(1e-7),
+           np.float32(1.5), np.float32(-1e-8), np.float32(L + 0.5), np.float32(-3 * L + 1.0)]
+    pos = np.array([[a, b, c] for a in pts for b in pts[:4] for c in pts[3:7]], np.float32)
+    pos = np.concatenate([pos, np.repeat(pos[:5], 3, axis=0)])  # coincident points
+    res = oracle.bin_reference(pos, P)
+    _check_bins(pos, P, res)
+    # the whole set in one cell
+    one = np.full((100, 3), 1.25, np.float32)
+    one[:, 0] += np.linspace(0, 1, 100, dtype=np.float32)
+    res = oracle.bin_reference(one, P)
+    assert np.all(res["cell_of"] == 0) and np.array_equal(res["perm"], np.arange(100))
+
+
+def test_bin_reference_flags_open_domain():
+    P = prob(30.0, False, lo=(-3, -3, -3))
+    pos = np.array([[0, 0, 0], [-3.5, 0, 0], [0, 27.5, 0], [np.nan, 0, 0]], np.float32)
+    res = oracle.bin_reference(pos, P)
+    assert res["flags"] == oracle.NONFINITE | oracle.OUT_OF_DOMAIN
+    assert res["cell_of"][1] // 100 == 0 and (res["cell_of"][2] // 10) % 10 == 9
+
+
+def test_bin_reference_float32_formula():
+    # consistency with the written rule, evaluated with numpy float32 (no fused ops)
+    w = synth.uniform_box(5000, 27.0, 12)
+    res = oracle.bin_reference(w.pos, w.problem)
+    f = np.float32
+    L = f(27.0)
+    nc = res["nc"]
+    inv_len = f(1.0) / L
+    inv_h = f(nc[0]) / L
+    h = L / f(nc[0])
+    x = w.pos
+    k = np.floor(x * inv_len).astype(np.float32)
+    wv = (x - (k * L).astype(np.float32)).astype(np.float32)
+    fi = np.floor(wv * inv_h)
+    i = np.clip(fi, 0, nc[0] - 1).astype(np.int64)
+    c = ((i.astype(np.float32) + f(0.5)) * h).astype(np.float32)
+    off = (wv - c).astype(np.float32)
+    cell = (i[:, 0] * nc[1] + i[:, 1]) * nc[2] + i[:, 2]
+    assert np.array_equal(res["cell_of"], cell)
+    assert np.array_equal(res["off"], off[res["perm"]])

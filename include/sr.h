@@ -1,0 +1,214 @@
+/*
+ * sr.h -- C ABI of the short-range particle-particle force library (libsr).
+ *
+ * The library computes the short-range half of a split gravitational force
+ * (paper Sec. 2: the long-range part is solved on a spectrally filtered
+ * particle-mesh grid, the short-range part by direct particle-particle sums on
+ * the accelerator).  For every active particle i
+ *
+ *     a_i = sum_{j != i, 0 < s_ij < r_s^2}  m_j d_ij f_SR(s_ij)
+ *     d_ij = x_j - x_i (minimum image when periodic),  s = |d|^2
+ *     f_SR(s) = (s + eps^2)^(-3/2) - sum_{k=0..5} poly[k] s^k
+ *
+ * in units with G = 1 and lengths in grid cells.  Active particles are the
+ * first n_active rows; the remaining rows are passive copies (the overload
+ * or ghost zone of Sec. 2 and the passive block particles of Sec. 2.1) that
+ * act only as sources.  The filter polynomial and its coefficients are not
+ * printed in the paper (it defers them to the HACC method papers), so they
+ * are an argument.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless marked (host).  Arrays are row-major
+ *    float32: positions [n][3], masses [n], accelerations [n_active][3].
+ *  - The caller owns all device memory.  The library never allocates device
+ *    memory and never synchronises, except where stated (sr_ws_flags, plan
+ *    creation and the first run of a batch plan).  Work is enqueued on
+ *    `stream` (a hipStream_t passed as an opaque pointer; NULL is the null
+ *    stream) and the call returns at once.
+ *  - The workspace is caller-allocated scratch of at least the size
+ *    reported by sr_workspace_bytes / sr_batch_plan_create, aligned to 256 B.
+ *    Two calls that run concurrently must use different workspaces.
+ *  - Argument errors are detected on the host and returned before anything
+ *    is enqueued (no partial work).  n == 0 is a valid no-op.
+ *  - Conditions found on the device (non-finite positions, positions outside
+ *    an open domain) set bits in the workspace, read by sr_ws_flags.
+ *  - All functions are thread-safe except that one batch plan must not be
+ *    used from two threads at once.
+ */
+#ifndef SR_H
+#define SR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SR_ABI_VERSION 1
+
+typedef enum sr_status {
+    SR_OK = 0,
+    SR_E_ARG = 1,         /* invalid argument (null pointer, bad size, bad problem) */
+    SR_E_WORKSPACE = 2,   /* workspace missing, misaligned or too small */
+    SR_E_DEVICE = 3,      /* a HIP runtime call failed */
+    SR_E_PLAN = 4,        /* batch plan invalid or used with other sizes */
+    SR_E_UNSUPPORTED = 5  /* valid request outside what this build supports */
+} sr_status;
+
+/* sr_force / sr_force_vjp flags */
+#define SR_REUSE_BINS 1u /* the workspace already holds the bins of exactly these
+                            pos/mass/n/n_active/problem (from sr_bin or an earlier
+                            call); skips binning.  The caller guarantees it. */
+
+/* sr_batch_force flags */
+#define SR_BATCH_PER_SUBVOLUME 1u /* reference mode: one sr_force per subvolume */
+#define SR_BATCH_EAGER 2u         /* batched kernels launched directly, no graph */
+
+/* sr_ws_flags bits */
+#define SR_FLAG_NONFINITE 1u     /* some position was NaN or infinite */
+#define SR_FLAG_OUT_OF_DOMAIN 2u /* open domain: some position outside [lo, lo+len) */
+#define SR_FLAG_NOT_BINNED 4u    /* SR_REUSE_BINS on a workspace without bins for these
+                                    sizes: nothing was computed */
+
+/* One short-range problem (paper Sec. 2; softening length from Sec. 3.1).
+ *  lo, len   domain origin and extent per dimension.  Periodic boxes need
+ *            lo = 0 and len >= 3 r_s (at least three cells of side >= r_s
+ *            per dimension, so the minimum image is the only image inside
+ *            the cutoff).  Open domains accept particles anywhere; those
+ *            outside [lo, lo+len) still interact correctly but set
+ *            SR_FLAG_OUT_OF_DOMAIN.
+ *  periodic  1: minimum-image periodic box; 0: open domain.
+ *  r_s       cutoff radius (> 0).
+ *  eps       Plummer softening length (>= 0); eps^2 is added to s.
+ *  poly      filter polynomial coefficients poly[k] of s^k. */
+typedef struct sr_problem {
+    float lo[3];
+    float len[3];
+    int32_t periodic;
+    float r_s;
+    float eps;
+    float poly[6];
+} sr_problem;
+
+/* Device arrays of a binned workspace (all in binned order unless noted).
+ * Binning rule (float32, round to nearest, no fused operations):
+ *   nc_d = floor(len_d / r_s) (>= 1; >= 3 required when periodic)
+ *   periodic: w = x - floor(x * (1/len)) * len;  open: w = x, u = x - lo
+ *   i_d = clamp(floor(u * (nc/len)), 0, nc-1)   (u = w when periodic; NaN -> 0)
+ *   cell = (i_x * nc_y + i_y) * nc_z + i_z
+ *   offset = w - (lo + (i + 0.5) * (len/nc))    (distance from the cell centre)
+ * Particles are ordered by (cell, input index). */
+typedef struct sr_bin_layout {
+    int32_t nc[3];
+    int64_t ncell;
+    const int32_t *cell_of;    /* [n] cell of each particle, input order */
+    const int32_t *cell_start; /* [ncell+1] first binned slot of each cell */
+    const int32_t *cell_nact;  /* [ncell] active particles per cell (they come first) */
+    const int32_t *perm;       /* [n] binned slot -> input index */
+    const float *off_x;        /* [n] offsets from the cell centre */
+    const float *off_y;
+    const float *off_z;
+    const float *mass;         /* [n] masses */
+} sr_bin_layout;
+
+typedef struct sr_batch_plan sr_batch_plan;
+
+int sr_abi_version(void);
+const char *sr_status_str(int status);
+
+/* Host only.  Cells per dimension for a problem (the rule above). */
+sr_status sr_grid(const sr_problem *prob /*host*/, int32_t nc[3] /*host out*/);
+
+/* Host only.  Workspace bytes for sr_bin/sr_force/sr_force_vjp/sr_count_pairs/
+ * sr_momentum with n particles of this problem. */
+sr_status sr_workspace_bytes(int64_t n, const sr_problem *prob /*host*/, size_t *bytes /*host out*/);
+
+/* Bin the particles into the chaining mesh: cell of each particle, stable
+ * counting sort by cell, binned offsets and masses (the layout above).
+ * pos [n][3], mass [n]; 0 <= n_active <= n < 2^31. */
+sr_status sr_bin(const float *pos, const float *mass, int64_t n, int64_t n_active,
+                 const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, void *stream);
+
+/* Host only, no device access.  Device pointers into a workspace binned for
+ * (n, prob). */
+sr_status sr_bin_view(const void *ws, int64_t n, const sr_problem *prob /*host*/,
+                      sr_bin_layout *out /*host out*/);
+
+/* Short-range accelerations of the active particles: acc [n_active][3], in
+ * input order, overwritten.  Bins first unless flags has SR_REUSE_BINS. */
+sr_status sr_force(const float *pos, const float *mass, int64_t n, int64_t n_active,
+                   const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, unsigned flags,
+                   float *acc, void *stream);
+
+/* Vector-Jacobian product of the accelerations with respect to the
+ * positions: for L = sum_{i < n_active} g_i . a_i,
+ *   grad_pos[k] = dL/dx_k = sum_{j != k, 0 < s < r_s^2} [ f u + 2 f' (u.d) d ],
+ *   d = x_j - x_k, u = m_k g_j - m_j g_k (g = 0 on passive rows),
+ * f = f_SR(s), f' = df_SR/ds.  Masses are constants; the jump of the cutoff
+ * is not differentiated.  g [n_active][3]; grad_pos [n][3] (passive
+ * particles receive gradient as sources), overwritten.  Pair terms are
+ * recomputed, not stored.  Bins first unless flags has SR_REUSE_BINS. */
+sr_status sr_force_vjp(const float *pos, const float *mass, int64_t n, int64_t n_active,
+                       const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, unsigned flags,
+                       const float *g, float *grad_pos, void *stream);
+
+/* Number of ordered pairs (i active, j) with 0 < s_ij < r_s^2, decided with
+ * the same float32 arithmetic as sr_force, written to *pairs (device int64).
+ * Needs a workspace binned for these inputs. */
+sr_status sr_count_pairs(int64_t n, int64_t n_active, const sr_problem *prob /*host*/, void *ws,
+                         size_t ws_bytes, int64_t *pairs, void *stream);
+
+/* Momentum check: out[0..2] = sum_{i < n_rows} mass[i] * acc[i] in float64
+ * (device double[3]), summed in a fixed order.  Uses the workspace as
+ * scratch (size from sr_workspace_bytes for at least n_rows particles). */
+sr_status sr_momentum(const float *acc, const float *mass, int64_t n_rows, void *ws,
+                      size_t ws_bytes, double *out, void *stream);
+
+/* Copy the device condition bits of a workspace to *flags (host).  Waits for
+ * `stream`. */
+sr_status sr_ws_flags(const void *ws, void *stream, uint32_t *flags /*host out*/);
+
+/* Batches: B independent problems stored back to back (the independent
+ * overlapping blocks of Sec. 2.1, each with its own active and passive
+ * particles).  Subvolume b owns input rows [offsets[b], offsets[b+1]); its
+ * first n_active[b] rows are active.  Its accelerations are written to rows
+ * [A_b, A_b + n_active[b]) of acc, A_b = sum_{c<b} n_active[c].
+ *
+ * sr_batch_plan_create (host) validates the batch, lays out the workspace
+ * and reports its size in *ws_bytes.  tune_cache (host, nullable) names a
+ * JSON file in which launch parameters measured on the first run are kept.
+ * The plan owns only host memory, one HIP stream and, after the first run,
+ * a captured HIP graph of the whole bin-then-force sequence bound to the
+ * pointers of that run; a later run with other pointers captures again. */
+sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets /*host [B+1]*/,
+                               const int64_t *n_active /*host [B]*/,
+                               const sr_problem *probs /*host [B]*/, const char *tune_cache,
+                               sr_batch_plan **plan /*host out*/, size_t *ws_bytes /*host out*/);
+
+/* Run a batch: acc [sum n_active][3]; momentum (nullable) [B][3] float64 =
+ * sum over active rows of mass * acc per subvolume.  flags:
+ * SR_BATCH_PER_SUBVOLUME (one sr_force per subvolume, the reference mode),
+ * SR_BATCH_EAGER (batched kernels without a graph), 0 (graph replay). */
+sr_status sr_batch_force(sr_batch_plan *plan, const float *pos, const float *mass, void *ws,
+                         size_t ws_bytes, float *acc, double *momentum, unsigned flags,
+                         void *stream);
+
+sr_status sr_batch_plan_destroy(sr_batch_plan *plan);
+
+/* Host-side description of a plan: B, total particles, launch parameters
+ * chosen by the tuner (writes a NUL-terminated JSON string). */
+sr_status sr_batch_plan_info(const sr_batch_plan *plan, char *buf /*host*/, size_t buf_bytes);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of the pair kernels ("force", "vjp").  sr_timing_enable(1) clears
+ * and starts recording; sr_timing_read waits for the recorded events and
+ * returns the summed milliseconds and the launch count of one kernel. */
+sr_status sr_timing_enable(int on);
+sr_status sr_timing_read(const char *kernel, double *total_ms /*host out*/,
+                         int64_t *launches /*host out*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SR_H */

@@ -1,0 +1,361 @@
+"""ctypes binding of libsr (argument marshalling only).
+
+Every step of the force path runs in the library's HIP kernels; torch
+supplies device memory (inputs, outputs, workspaces) and the current stream.
+The binding raises if the library or a GPU is missing: there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsr.so")
+
+SR_OK = 0
+STATUS = {0: "SR_OK", 1: "SR_E_ARG", 2: "SR_E_WORKSPACE", 3: "SR_E_DEVICE", 4: "SR_E_PLAN",
+          5: "SR_E_UNSUPPORTED"}
+REUSE_BINS = 1
+BATCH_PER_SUBVOLUME = 1
+BATCH_EAGER = 2
+FLAG_NONFINITE = 1
+FLAG_OUT_OF_DOMAIN = 2
+
+# the exported names of sr.h, in declaration order
+EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "sr_bin",
+           "sr_bin_view", "sr_force", "sr_force_vjp", "sr_count_pairs", "sr_momentum",
+           "sr_ws_flags", "sr_batch_plan_create", "sr_batch_force", "sr_batch_plan_destroy",
+           "sr_batch_plan_info", "sr_timing_enable", "sr_timing_read")
+
+
+class SRError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = int(code)
+        super().__init__(f"{what}: {STATUS.get(self.code, self.code)}")
+
+
+class Problem(C.Structure):
+    _fields_ = [("lo", C.c_float * 3), ("len", C.c_float * 3), ("periodic", C.c_int32),
+                ("r_s", C.c_float), ("eps", C.c_float), ("poly", C.c_float * 6)]
+
+
+class BinLayout(C.Structure):
+    _fields_ = [("nc", C.c_int32 * 3), ("ncell", C.c_int64), ("cell_of", C.c_void_p),
+                ("cell_start", C.c_void_p), ("cell_nact", C.c_void_p), ("perm", C.c_void_p),
+                ("off_x", C.c_void_p), ("off_y", C.c_void_p), ("off_z", C.c_void_p),
+                ("mass", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsr.so; raise if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libsr.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        p, i64, u = C.c_void_p, C.c_int64, C.c_uint
+        L.sr_abi_version.restype = C.c_int
+        L.sr_status_str.restype = C.c_char_p
+        L.sr_status_str.argtypes = [C.c_int]
+        L.sr_grid.argtypes = [p, p]
+        L.sr_workspace_bytes.argtypes = [i64, p, p]
+        L.sr_bin.argtypes = [p, p, i64, i64, p, p, C.c_size_t, p]
+        L.sr_bin_view.argtypes = [p, i64, p, p]
+        L.sr_force.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p]
+        L.sr_force_vjp.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p, p]
+        L.sr_count_pairs.argtypes = [i64, i64, p, p, C.c_size_t, p, p]
+        L.sr_momentum.argtypes = [p, p, i64, p, C.c_size_t, p, p]
+        L.sr_ws_flags.argtypes = [p, p, p]
+        L.sr_batch_plan_create.argtypes = [C.c_int32, p, p, p, C.c_char_p, p, p]
+        L.sr_batch_force.argtypes = [p, p, p, p, C.c_size_t, p, p, u, p]
+        L.sr_batch_plan_destroy.argtypes = [p]
+        L.sr_batch_plan_info.argtypes = [p, p, C.c_size_t]
+        L.sr_timing_enable.argtypes = [C.c_int]
+        L.sr_timing_read.argtypes = [C.c_char_p, p, p]
+        for name in EXPORTS:
+            if name not in ("sr_abi_version", "sr_status_str"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code: int, what: str) -> None:
+    if code != SR_OK:
+        raise SRError(code, what)
+
+
+def as_problem(prob) -> Problem:
+    """Problem struct from an object with lo, len, periodic, r_s, eps, poly."""
+    if isinstance(prob, Problem):
+        return prob
+    s = Problem()
+    for d in range(3):
+        s.lo[d] = float(prob.lo[d])
+        s.len[d] = float(prob.len[d])
+    s.periodic = 1 if prob.periodic else 0
+    s.r_s = float(prob.r_s)
+    s.eps = float(prob.eps)
+    for k in range(6):
+        s.poly[k] = float(prob.poly[k])
+    return s
+
+
+def _stream(stream=None) -> C.c_void_p:
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(st.cuda_stream)
+
+
+def _dev_f32(t: torch.Tensor, name: str, shape: Sequence[int]) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.contiguous()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def grid(prob):
+    nc = (C.c_int32 * 3)()
+    _check(lib().sr_grid(C.byref(as_problem(prob)), nc), "sr_grid")
+    return tuple(nc)
+
+
+def workspace_bytes(n: int, prob) -> int:
+    b = C.c_size_t()
+    _check(lib().sr_workspace_bytes(int(n), C.byref(as_problem(prob)), C.byref(b)),
+           "sr_workspace_bytes")
+    return int(b.value)
+
+
+def new_workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace allocation is not 256-byte aligned")
+    return ws
+
+
+def bin(pos, mass, prob, n_active=None, ws=None, stream=None):  # noqa: A001 (paper's verb)
+    n = int(pos.shape[0])
+    n_active = n if n_active is None else int(n_active)
+    pos = _dev_f32(pos, "pos", (n, 3))
+    mass = _dev_f32(mass, "mass", (n,))
+    P = as_problem(prob)
+    if ws is None:
+        ws = new_workspace(workspace_bytes(n, P), pos.device)
+    _check(lib().sr_bin(_ptr(pos), _ptr(mass), n, n_active, C.byref(P), _ptr(ws), ws.numel(),
+                        _stream(stream)), "sr_bin")
+    return ws
+
+
+def bin_view(ws: torch.Tensor, n: int, prob) -> dict:
+    """Views of the binned arrays inside a workspace (int32/float32 tensors)."""
+    out = BinLayout()
+    P = as_problem(prob)
+    _check(lib().sr_bin_view(_ptr(ws), int(n), C.byref(P), C.byref(out)), "sr_bin_view")
+    base = ws.data_ptr()
+
+    def view(ptr, count, dtype):
+        off = int(ptr) - base
+        return ws[off: off + 4 * count].view(dtype)
+
+    ncell = int(out.ncell)
+    return {"nc": tuple(out.nc), "ncell": ncell,
+            "cell_of": view(out.cell_of, n, torch.int32),
+            "cell_start": view(out.cell_start, ncell + 1, torch.int32),
+            "cell_nact": view(out.cell_nact, ncell, torch.int32),
+            "perm": view(out.perm, n, torch.int32),
+            "off_x": view(out.off_x, n, torch.float32),
+            "off_y": view(out.off_y, n, torch.float32),
+            "off_z": view(out.off_z, n, torch.float32),
+            "mass": view(out.mass, n, torch.float32)}
+
+
+def force(pos, mass, prob, n_active=None, ws=None, reuse_bins=False, out=None, stream=None):
+    """Short-range accelerations of the first n_active particles, [n_active, 3]."""
+    n = int(pos.shape[0])
+    n_active = n if n_active is None else int(n_active)
+    pos = _dev_f32(pos, "pos", (n, 3))
+    mass = _dev_f32(mass, "mass", (n,))
+    P = as_problem(prob)
+    if ws is None:
+        if reuse_bins:
+            raise ValueError("reuse_bins needs the binned workspace")
+        ws = new_workspace(workspace_bytes(n, P), pos.device)
+    if out is None:
+        out = torch.empty((n_active, 3), dtype=torch.float32, device=pos.device)
+    else:
+        out = _dev_f32(out, "out", (n_active, 3))
+    _check(lib().sr_force(_ptr(pos), _ptr(mass), n, n_active, C.byref(P), _ptr(ws), ws.numel(),
+                          REUSE_BINS if reuse_bins else 0, _ptr(out), _stream(stream)), "sr_force")
+    return out
+
+
+def force_vjp(pos, mass, prob, g, n_active=None, ws=None, reuse_bins=False, out=None, stream=None):
+    """Gradient of sum_i g_i . a_i with respect to the positions, [n, 3]."""
+    n = int(pos.shape[0])
+    n_active = n if n_active is None else int(n_active)
+    pos = _dev_f32(pos, "pos", (n, 3))
+    mass = _dev_f32(mass, "mass", (n,))
+    g = _dev_f32(g, "g", (n_active, 3))
+    P = as_problem(prob)
+    if ws is None:
+        if reuse_bins:
+            raise ValueError("reuse_bins needs the binned workspace")
+        ws = new_workspace(workspace_bytes(n, P), pos.device)
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+    else:
+        out = _dev_f32(out, "out", (n, 3))
+    _check(lib().sr_force_vjp(_ptr(pos), _ptr(mass), n, n_active, C.byref(P), _ptr(ws), ws.numel(),
+                              REUSE_BINS if reuse_bins else 0, _ptr(g), _ptr(out), _stream(stream)),
+           "sr_force_vjp")
+    return out
+
+
+def count_pairs(ws, n, prob, n_active=None, stream=None) -> torch.Tensor:
+    """Device int64 scalar: ordered pairs (active i, j) with 0 < s < r_s^2."""
+    n_active = int(n) if n_active is None else int(n_active)
+    out = torch.zeros(1, dtype=torch.int64, device=ws.device)
+    P = as_problem(prob)
+    _check(lib().sr_count_pairs(int(n), n_active, C.byref(P), _ptr(ws), ws.numel(), _ptr(out),
+                                _stream(stream)), "sr_count_pairs")
+    return out
+
+
+def momentum(acc, mass, ws=None, stream=None) -> torch.Tensor:
+    """float64 [3]: sum_i mass[i] * acc[i] over the rows of acc."""
+    rows = int(acc.shape[0])
+    acc = _dev_f32(acc, "acc", (rows, 3))
+    mass = _dev_f32(mass[:rows], "mass", (rows,))
+    if ws is None:
+        ws = new_workspace(8 * (3 * (rows // 65536 + 2) + 3) + 1024, acc.device)
+    out = torch.empty(3, dtype=torch.float64, device=acc.device)
+    _check(lib().sr_momentum(_ptr(acc), _ptr(mass), rows, _ptr(ws), ws.numel(), _ptr(out),
+                             _stream(stream)), "sr_momentum")
+    return out
+
+
+def ws_flags(ws, stream=None) -> int:
+    v = C.c_uint32()
+    _check(lib().sr_ws_flags(_ptr(ws), _stream(stream), C.byref(v)), "sr_ws_flags")
+    return int(v.value)
+
+
+class SRForce(torch.autograd.Function):
+    """Differentiable short-range force: gradient with respect to positions only."""
+
+    @staticmethod
+    def forward(ctx, pos, mass, prob, n_active=None):
+        n = int(pos.shape[0])
+        n_act = n if n_active is None else int(n_active)
+        ws = new_workspace(workspace_bytes(n, prob), pos.device)
+        acc = force(pos, mass, prob, n_act, ws=ws)
+        ctx.save_for_backward(pos, mass)
+        ctx.ws = ws
+        ctx.prob = prob
+        ctx.n_active = n_act
+        return acc
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, g):
+        pos, mass = ctx.saved_tensors
+        grad = force_vjp(pos, mass, ctx.prob, g.contiguous().float(), ctx.n_active, ws=ctx.ws,
+                         reuse_bins=True)
+        return grad, None, None, None
+
+
+def sr_force(pos, mass, prob, n_active=None):
+    return SRForce.apply(pos, mass, prob, n_active)
+
+
+class BatchPlan:
+    """A plan for B independent problems stored back to back."""
+
+    def __init__(self, offsets, n_active, problems, tune_cache: Optional[str] = None):
+        import numpy as np
+
+        offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        n_active = np.ascontiguousarray(np.asarray(n_active, dtype=np.int64))
+        B = len(problems)
+        if offsets.shape != (B + 1,) or n_active.shape != (B,):
+            raise ValueError("offsets must have B+1 entries and n_active B")
+        arr = (Problem * B)(*[as_problem(p) for p in problems])
+        self._plan = C.c_void_p()
+        nb = C.c_size_t()
+        cache = tune_cache.encode() if tune_cache else None
+        _check(lib().sr_batch_plan_create(B, offsets.ctypes.data_as(C.c_void_p),
+                                          n_active.ctypes.data_as(C.c_void_p), arr, cache,
+                                          C.byref(self._plan), C.byref(nb)), "sr_batch_plan_create")
+        self.B = B
+        self.offsets = offsets
+        self.n_active = n_active
+        self.ws_bytes = int(nb.value)
+        self.total_active = int(n_active.sum())
+
+    def run(self, pos, mass, ws, acc, momentum=None, mode: str = "graph", stream=None):
+        flags = {"graph": 0, "eager": BATCH_EAGER, "per_subvolume": BATCH_PER_SUBVOLUME}[mode]
+        n = int(self.offsets[-1])
+        pos = _dev_f32(pos, "pos", (n, 3))
+        mass = _dev_f32(mass, "mass", (n,))
+        acc = _dev_f32(acc, "acc", (self.total_active, 3))
+        if momentum is not None and (momentum.dtype != torch.float64 or momentum.numel() != 3 * self.B):
+            raise ValueError("momentum must be float64 [B, 3]")
+        _check(lib().sr_batch_force(self._plan, _ptr(pos), _ptr(mass), _ptr(ws), ws.numel(), _ptr(acc),
+                                    _ptr(momentum), flags, _stream(stream)), "sr_batch_force")
+
+    def info(self) -> dict:
+        import json
+
+        buf = C.create_string_buffer(1024)
+        _check(lib().sr_batch_plan_info(self._plan, buf, 1024), "sr_batch_plan_info")
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._plan:
+            lib().sr_batch_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_force(pos, mass, offsets, problems, n_active=None, mode="graph", momentum=False,
+                tune_cache=None):
+    import numpy as np
+
+    offsets = np.asarray(offsets, dtype=np.int64)
+    if n_active is None:
+        n_active = np.diff(offsets)
+    plan = BatchPlan(offsets, n_active, problems, tune_cache)
+    ws = new_workspace(plan.ws_bytes, pos.device)
+    acc = torch.empty((plan.total_active, 3), dtype=torch.float32, device=pos.device)
+    mom = torch.empty((plan.B, 3), dtype=torch.float64, device=pos.device) if momentum else None
+    plan.run(pos, mass, ws, acc, mom, mode)
+    plan.close()
+    return (acc, mom) if momentum else acc
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(lib().sr_timing_enable(1 if on else 0), "sr_timing_enable")
+
+
+def timing_read(kernel: str):
+    ms = C.c_double()
+    cnt = C.c_int64()
+    _check(lib().sr_timing_read(kernel.encode(), C.byref(ms), C.byref(cnt)), "sr_timing_read")
+    return float(ms.value), int(cnt.value)

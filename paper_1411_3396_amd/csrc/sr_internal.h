@@ -1,0 +1,118 @@
+// Internal declarations shared by the device kernels (sr_kernels.hip) and the
+// host library (sr_api.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sr.h"
+
+namespace sr {
+
+constexpr int kWave = 64;
+constexpr int kTargetsPerItem = 64;  // one target per lane in a dense cell
+constexpr int kQueues = 8;           // one work queue per XCD
+constexpr int kQueueBlock = 32;      // consecutive items a queue takes from the list
+constexpr int kClasses = 32;         // cost classes (floor log2 of the per-lane pair count)
+constexpr int kRadixTile = 2048;     // elements per radix-sort tile
+constexpr int kScanBlock = 2048;     // elements per scan block (256 threads x 8)
+constexpr int kMomTile = 65536;      // rows per momentum partial
+
+// Constants of the pair kernel, evaluated in t = s + eps^2:
+//   f_SR = t^-3/2 - Q(t),  Q(t) = sum_k q[k] t^k = sum_k poly[k] (t - eps^2)^k,
+//   2 f_SR' = -3 t^-5/2 - D(t),  D(t) = sum_k dq[k] t^k = 2 Q'(t).
+struct PairConsts {
+    float eps2;   // eps * eps
+    float tc2;    // r_s^2 + eps^2: pairs with t < tc2 interact
+    float q[6];
+    float dq[5];
+    int32_t softened;  // eps > 0
+};
+
+// One problem of a batch (a single problem is a batch of one).
+struct SegParams {
+    float lo[3];
+    float len[3];
+    float h[3];       // len / nc
+    float inv_h[3];   // nc / len
+    float inv_len[3]; // 1 / len
+    int32_t nc[3];
+    int32_t periodic;
+    int32_t cell_off;  // first global cell
+    int32_t part_off;  // first particle (input row)
+    int32_t n;
+    int32_t n_active;
+    int32_t out_off;   // first output row of its accelerations
+    int32_t tile_off;  // first momentum partial
+    PairConsts pc;
+    int32_t pad[1];
+};
+static_assert(sizeof(SegParams) % 16 == 0, "SegParams must stay 16-byte sized");
+
+// Workspace header words (uint32 offsets into the header block).
+enum HdrWord : int {
+    kHdrFlags = 0,
+    kHdrNItems = 1,
+    kHdrMagic = 2,          // written by the last binning kernel: bins are ready
+    kHdrBucketCount = 64,   // [32]
+    kHdrBucketBase = 128,   // [33]
+    kHdrBucketCursor = 192, // [32]
+    kHdrQueue = 256,        // queue q at kHdrQueue + 32*q (separate 128-byte lines)
+    kHdrPairs = 512,        // int64 pair counter (2 words)
+    kHdrWords = 1024
+};
+
+// Byte offsets of every buffer inside a workspace.
+struct Layout {
+    int64_t N = 0;     // particles (all segments)
+    int64_t NC = 0;    // cells (all segments)
+    int32_t B = 1;     // segments
+    int32_t passes = 0, digit_bits = 0;
+    int64_t ntiles = 0;     // radix tiles
+    int64_t table = 0;      // radix table entries (R * ntiles)
+    int64_t item_cap = 0;   // upper bound on work items
+    int64_t mom_tiles = 0;  // momentum partials
+    size_t hdr = 0, seg = 0, cell_of = 0, keys[2] = {0, 0}, vals[2] = {0, 0};
+    size_t tab = 0, tabx = 0, count = 0, nact = 0, start = 0, scan_tmp = 0;
+    size_t bx = 0, by = 0, bz = 0, bm = 0, out_row = 0, gx = 0, gy = 0, gz = 0;
+    size_t items = 0, info = 0, mom = 0;
+    size_t total = 0;
+    size_t perm() const { return vals[(passes - 1) & 1]; }
+    // Tag of a binned workspace for these sizes (never zero).
+    uint32_t magic() const
+    {
+        uint32_t m = 0x9E3779B9u * (uint32_t)N ^ 0x85EBCA6Bu * (uint32_t)NC ^ 0xC2B2AE35u * (uint32_t)B;
+        return m ? m : 1u;
+    }
+};
+
+// Sizes of the scan scratch for an array of m elements.
+int64_t scan_scratch_elems(int64_t m);
+
+// Device-path entry points implemented in sr_kernels.hip.  All enqueue on
+// `st` and return hipSuccess or the first launch error.
+struct DevArgs {
+    char *ws;
+    const Layout *L;
+    const SegParams *seg_host;  // single segment: by value in kernel args
+    const SegParams *seg_dev;   // batch: device table (nullptr for single)
+    hipStream_t st;
+    int waves_per_cu;
+    int num_cu;
+    int n_rows;  // rows of the force output (sum of n_active)
+};
+
+hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass);
+hipError_t dev_force(const DevArgs &a, float *acc);
+hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad);
+hipError_t dev_count_pairs(const DevArgs &a, int64_t *pairs);
+hipError_t dev_zero(void *p, int64_t words, hipStream_t st);
+hipError_t dev_momentum(const DevArgs &a, const float *acc, const float *mass, double *out);
+
+// Event timing hooks (sr_api.cpp).
+void timing_begin(const char *name, hipStream_t st, void **token);
+void timing_end(void *token, hipStream_t st);
+
+}  // namespace sr

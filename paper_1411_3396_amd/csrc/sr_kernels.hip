@@ -1,0 +1,1111 @@
+// Device kernels of the short-range force library, written for gfx950
+// (CDNA4: 64-wide waves, 160 KB LDS per CU, 8 XCDs with private L2).
+//
+// Path (paper Sec. 2: accelerators sum the short-range part of the split
+// force directly over particle pairs; Sec. 2.1: every block of particles is
+// solved independently, active particles receiving forces and passive ones
+// acting only as sources):
+//
+//   bin      cell index per particle (float32 rule of sr.h), stable LSD radix
+//            sort of (cell, input index), cell starts, and a gather of offsets
+//            from the cell centre and masses into structure-of-arrays order;
+//   items    one work item per home cell and chunk of up to 64 targets,
+//            grouped by cost class, heaviest first;
+//   pairs    a persistent kernel: each 64-lane wave pulls items from one of
+//            eight queues (one per XCD, stealing from the others when its own
+//            runs dry), stages the 27 neighbour cells' particles in LDS
+//            relative to the home-cell centre and sums the pair terms in
+//            float32 registers; sparse cells give each target several lanes
+//            and reduce them with cross-lane shuffles.
+//
+// Everything is integer-deterministic or summed in a fixed order: no float
+// atomics, so results are bitwise reproducible run to run.
+#include "sr_internal.h"
+
+namespace sr {
+namespace {
+
+constexpr float kFar = 1.0e6f;  // position of padding sources (masked out)
+
+// --------------------------------------------------------------- segments
+
+struct OneSeg {
+    SegParams p;
+    __device__ __forceinline__ int seg_of_particle(int) const { return 0; }
+    __device__ __forceinline__ int seg_of_cell(int) const { return 0; }
+    __device__ __forceinline__ int seg_of_tile(int) const { return 0; }
+    __device__ __forceinline__ const SegParams &get(int) const { return p; }
+};
+
+struct ManySeg {
+    const SegParams *__restrict__ tab;
+    int B;
+    // largest s with key(s) <= x; keys are non-decreasing
+    template <int kField>
+    __device__ __forceinline__ int search(int x) const
+    {
+        int lo = 0, hi = B - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            const SegParams &s = tab[mid];
+            const int key = kField == 0 ? s.part_off : (kField == 1 ? s.cell_off : s.tile_off);
+            if (key <= x)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ __forceinline__ int seg_of_particle(int i) const { return search<0>(i); }
+    __device__ __forceinline__ int seg_of_cell(int c) const { return search<1>(c); }
+    __device__ __forceinline__ int seg_of_tile(int t) const { return search<2>(t); }
+    __device__ __forceinline__ const SegParams &get(int s) const { return tab[s]; }
+};
+
+// --------------------------------------------------------------- binning rule
+
+__device__ __forceinline__ float cell_centre(int i, float lo, float h)
+{
+#pragma clang fp contract(off)
+    const float t = (float)i + 0.5f;
+    const float c = t * h;
+    return lo + c;
+}
+
+// One coordinate of the binning rule of sr.h (float32, no fused operations).
+__device__ __forceinline__ int bin_coord(float x, float lo, float len, float inv_len, float h,
+                                         float inv_h, int nc, int periodic, float &off,
+                                         uint32_t &fl)
+{
+#pragma clang fp contract(off)
+    const bool fin = __builtin_isfinite(x);
+    if (!fin) fl |= SR_FLAG_NONFINITE;
+    float w, u;
+    if (periodic) {
+        const float k = floorf(x * inv_len);
+        const float p = k * len;
+        w = x - p;
+        u = w;
+    } else {
+        w = x;
+        u = x - lo;
+    }
+    const float fi = floorf(u * inv_h);
+    int i;
+    if (!(fi >= 0.0f)) {
+        i = 0;
+        if (!periodic && fin) fl |= SR_FLAG_OUT_OF_DOMAIN;
+    } else if (fi > (float)(nc - 1)) {
+        i = nc - 1;
+        if (!periodic && fin) fl |= SR_FLAG_OUT_OF_DOMAIN;
+    } else {
+        i = (int)fi;
+    }
+    off = w - cell_centre(i, lo, h);
+    return i;
+}
+
+// Neighbour j = i + d in one dimension: false if outside an open domain.
+// shift = centre(j) (+/- len when wrapped) - centre(i).
+__device__ __forceinline__ bool neighbour(int i, int d, int nc, float lo, float h, float len,
+                                          int periodic, int &j, float &shift)
+{
+#pragma clang fp contract(off)
+    j = i + d;
+    float wrap = 0.0f;
+    if (j < 0) {
+        if (!periodic) return false;
+        j += nc;
+        wrap = -len;
+    } else if (j >= nc) {
+        if (!periodic) return false;
+        j -= nc;
+        wrap = len;
+    }
+    const float cj = cell_centre(j, lo, h) + wrap;
+    shift = cj - cell_centre(i, lo, h);
+    return true;
+}
+
+__device__ __forceinline__ void decode_cell(const SegParams &S, int cell, int &ix, int &iy, int &iz)
+{
+    const int local = cell - S.cell_off;
+    iz = local % S.nc[2];
+    const int r = local / S.nc[2];
+    iy = r % S.nc[1];
+    ix = r / S.nc[1];
+}
+
+// --------------------------------------------------------------- utilities
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((uint32_t *)p, n, v);
+    return hipGetLastError();
+}
+
+// Exclusive scan over a 256-thread block; returns this thread's prefix and
+// the block total.  lds: 4 ints.
+__device__ __forceinline__ int block_excl_scan(int v, int &total, int *lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds[w] = x;
+    __syncthreads();
+    int woff = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int s = lds[k];
+        if (k < w) woff += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return woff + x - v;
+}
+
+constexpr int kScanItems = kScanBlock / 256;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const int *__restrict__ in, int64_t m,
+                                                     int *__restrict__ sums)
+{
+    __shared__ int lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) s += in[base + k];
+    int total;
+    block_excl_scan(s, total, lds);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// out[i] = offs[block] + sum_{k<i in block} in[k]; the last block also writes out[m].
+__global__ __launch_bounds__(256) void k_scan_apply(const int *__restrict__ in, int64_t m,
+                                                    const int *__restrict__ offs,
+                                                    int *__restrict__ out)
+{
+    __shared__ int lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < m) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_excl_scan(s, total, lds) + (offs ? offs[blockIdx.x] : 0);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) out[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        out[m] = (offs ? offs[blockIdx.x] : 0) + total;
+}
+
+// Exclusive scan of in[0..m) into out[0..m] (out[m] = total).  tmp holds
+// scan_scratch_elems(m) ints.
+hipError_t scan_i32(const int *in, int *out, int64_t m, int *tmp, hipStream_t st)
+{
+    const int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+    if (nb <= 1) {
+        k_scan_apply<<<1, 256, 0, st>>>(in, m, nullptr, out);
+        return hipGetLastError();
+    }
+    int *sums = tmp;
+    int *sums_x = tmp + nb;
+    int *next = sums_x + nb + 1;
+    k_scan_reduce<<<(unsigned)nb, 256, 0, st>>>(in, m, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_i32(sums, sums_x, nb, next, st);
+    if (e != hipSuccess) return e;
+    k_scan_apply<<<(unsigned)nb, 256, 0, st>>>(in, m, sums_x, out);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- A1: cell index
+
+template <class Acc>
+__global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restrict__ pos, int N,
+                                                   int *__restrict__ cell_of, int *count,
+                                                   int *nact, uint32_t *hdr)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const SegParams &S = acc.get(acc.seg_of_particle(i));
+    uint32_t fl = 0;
+    float o;
+    const int64_t p = 3 * (int64_t)i;
+    const int ix = bin_coord(pos[p], S.lo[0], S.len[0], S.inv_len[0], S.h[0], S.inv_h[0], S.nc[0],
+                             S.periodic, o, fl);
+    const int iy = bin_coord(pos[p + 1], S.lo[1], S.len[1], S.inv_len[1], S.h[1], S.inv_h[1],
+                             S.nc[1], S.periodic, o, fl);
+    const int iz = bin_coord(pos[p + 2], S.lo[2], S.len[2], S.inv_len[2], S.h[2], S.inv_h[2],
+                             S.nc[2], S.periodic, o, fl);
+    const int cell = S.cell_off + (ix * S.nc[1] + iy) * S.nc[2] + iz;
+    cell_of[i] = cell;
+    atomicAdd(&count[cell], 1);
+    if (i - S.part_off < S.n_active) atomicAdd(&nact[cell], 1);
+    if (fl) atomicOr(&hdr[kHdrFlags], fl);
+}
+
+// --------------------------------------------------------------- A2: stable radix sort
+
+// Digit histogram of one tile: table[d * ntiles + tile].
+__global__ __launch_bounds__(256) void k_radix_hist(const int *__restrict__ keys, int N, int shift,
+                                                    int bits, int *__restrict__ table, int ntiles)
+{
+    __shared__ int h[256];
+    const int R = 1 << bits;
+    for (int d = threadIdx.x; d < R; d += 256) h[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int e = threadIdx.x; e < kRadixTile; e += 256) {
+        const int64_t k = base + e;
+        if (k < N) atomicAdd(&h[(keys[k] >> shift) & (R - 1)], 1);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < R; d += 256) table[(int64_t)d * ntiles + blockIdx.x] = h[d];
+}
+
+// Stable scatter of one tile by one wave.  Elements are taken 64 at a time in
+// input order; lanes holding the same digit find each other with one ballot
+// per digit bit, rank by lane order and advance the digit's running offset.
+__global__ __launch_bounds__(64) void k_radix_scatter(const int *__restrict__ keys_in,
+                                                      const int *__restrict__ vals_in, int N,
+                                                      int shift, int bits,
+                                                      const int *__restrict__ table_x, int ntiles,
+                                                      int *__restrict__ keys_out,
+                                                      int *__restrict__ vals_out)
+{
+    __shared__ int run[256];
+    const int lane = threadIdx.x;
+    const int R = 1 << bits;
+    const int tile = blockIdx.x;
+    for (int d = lane; d < R; d += 64) run[d] = table_x[(int64_t)d * ntiles + tile];
+    __syncthreads();
+    const int64_t base = (int64_t)tile * kRadixTile;
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < kRadixTile / 64; ++r) {
+        const int64_t e = base + r * 64 + lane;
+        const bool valid = e < N;
+        int key = 0, val = 0;
+        if (valid) {
+            key = keys_in[e];
+            val = vals_in ? vals_in[e] : (int)e;
+        }
+        const int d = (key >> shift) & (R - 1);
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & below);
+        const int cnt = __popcll(peers);
+        const int start = run[d];
+        __syncthreads();
+        if (valid) {
+            const int dest = start + rank;
+            if (keys_out) keys_out[dest] = key;
+            vals_out[dest] = val;
+            if (rank == 0) run[d] = start + cnt;
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------- A3: gather
+
+template <class Acc>
+__global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__restrict__ perm,
+                                                const float *__restrict__ pos,
+                                                const float *__restrict__ mass,
+                                                float *__restrict__ bx, float *__restrict__ by,
+                                                float *__restrict__ bz, float *__restrict__ bm,
+                                                int *__restrict__ out_row, uint32_t *hdr,
+                                                uint32_t magic)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b == 0) hdr[kHdrMagic] = magic;
+    if (b >= N) return;
+    const int i = perm[b];
+    const SegParams &S = acc.get(acc.seg_of_particle(i));
+    uint32_t fl = 0;
+    float ox, oy, oz;
+    const int64_t p = 3 * (int64_t)i;
+    bin_coord(pos[p], S.lo[0], S.len[0], S.inv_len[0], S.h[0], S.inv_h[0], S.nc[0], S.periodic, ox,
+              fl);
+    bin_coord(pos[p + 1], S.lo[1], S.len[1], S.inv_len[1], S.h[1], S.inv_h[1], S.nc[1], S.periodic,
+              oy, fl);
+    bin_coord(pos[p + 2], S.lo[2], S.len[2], S.inv_len[2], S.h[2], S.inv_h[2], S.nc[2], S.periodic,
+              oz, fl);
+    bx[b] = ox;
+    by[b] = oy;
+    bz[b] = oz;
+    bm[b] = mass[i];
+    const int li = i - S.part_off;
+    out_row[b] = li < S.n_active ? S.out_off + li : -1;
+}
+
+// Cotangent rows in binned order (zero on passive particles).
+__global__ __launch_bounds__(256) void k_gather_g(int N, int n_rows,
+                                                  const int *__restrict__ out_row,
+                                                  const float *__restrict__ g,
+                                                  float *__restrict__ gx, float *__restrict__ gy,
+                                                  float *__restrict__ gz)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= N) return;
+    const int r = out_row[b];
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (r >= 0 && r < n_rows) {
+        const int64_t q = 3 * (int64_t)r;
+        x = g[q];
+        y = g[q + 1];
+        z = g[q + 2];
+    }
+    gx[b] = x;
+    gy[b] = y;
+    gz[b] = z;
+}
+
+// --------------------------------------------------------------- work items
+
+// Per home cell: number of items and cost class (floor log2 of the pairs one
+// lane evaluates); counts items per class.
+template <class Acc, bool kActiveOnly>
+__global__ __launch_bounds__(256) void k_items_count(Acc acc, int NC, const int *__restrict__ start,
+                                                     const int *__restrict__ nact,
+                                                     uint32_t *__restrict__ info, uint32_t *hdr,
+                                                     uint32_t magic, int N)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= NC) return;
+    if (hdr[kHdrMagic] != magic) {
+        info[c] = 0;
+        if (c == 0) atomicOr(&hdr[kHdrFlags], (uint32_t)SR_FLAG_NOT_BINNED);
+        return;
+    }
+    const int nt = kActiveOnly ? nact[c] : (start[c + 1] - start[c]);
+    if (nt <= 0 || nt > N) {
+        info[c] = 0;
+        return;
+    }
+    const SegParams &S = acc.get(acc.seg_of_cell(c));
+    int ix, iy, iz;
+    decode_cell(S, c, ix, iy, iz);
+    int64_t src = 0;
+    for (int dx = -1; dx <= 1; ++dx) {
+        int jx = ix + dx;
+        if (jx < 0 || jx >= S.nc[0]) {
+            if (!S.periodic) continue;
+            jx = (jx + S.nc[0]) % S.nc[0];
+        }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int jy = iy + dy;
+            if (jy < 0 || jy >= S.nc[1]) {
+                if (!S.periodic) continue;
+                jy = (jy + S.nc[1]) % S.nc[1];
+            }
+            for (int dz = -1; dz <= 1; ++dz) {
+                int jz = iz + dz;
+                if (jz < 0 || jz >= S.nc[2]) {
+                    if (!S.periodic) continue;
+                    jz = (jz + S.nc[2]) % S.nc[2];
+                }
+                const int cc = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
+                src += start[cc + 1] - start[cc];
+            }
+        }
+    }
+    const int lk = nt >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / nt));
+    const int n_items = nt >= kTargetsPerItem ? (nt + kTargetsPerItem - 1) / kTargetsPerItem : 1;
+    int64_t cost = (src + (1 << lk) - 1) >> lk;
+    if (cost < 1) cost = 1;
+    const int cls = 63 - __clzll((unsigned long long)cost);
+    info[c] = ((uint32_t)n_items << 5) | (uint32_t)(cls > 31 ? 31 : cls);
+    atomicAdd(&hdr[kHdrBucketCount + (cls > 31 ? 31 : cls)], (uint32_t)n_items);
+}
+
+// Class bases, heaviest class first; resets cursors and queue counters.
+__global__ void k_items_base(uint32_t *hdr, uint32_t magic)
+{
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int cls = kClasses - 1; cls >= 0; --cls) {
+            hdr[kHdrBucketBase + cls] = run;
+            run += hdr[kHdrBucketCount + cls];
+        }
+        hdr[kHdrNItems] = hdr[kHdrMagic] == magic ? run : 0u;
+    }
+    if (threadIdx.x < kClasses) hdr[kHdrBucketCursor + threadIdx.x] = 0;
+    if (threadIdx.x < kQueues) hdr[kHdrQueue + 32 * threadIdx.x] = 0;
+}
+
+template <class Acc, bool kActiveOnly>
+__global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int *__restrict__ start,
+                                                     const int *__restrict__ nact,
+                                                     const uint32_t *__restrict__ info,
+                                                     uint32_t *hdr, int4 *__restrict__ items)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= NC) return;
+    const uint32_t inf = info[c];
+    if (inf == 0) return;
+    const int n_items = (int)(inf >> 5);
+    const int cls = (int)(inf & 31);
+    const int nt = kActiveOnly ? nact[c] : (start[c + 1] - start[c]);
+    const int lk = nt >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / nt));
+    const int seg = acc.seg_of_cell(c);
+    const uint32_t at = hdr[kHdrBucketBase + cls] + atomicAdd(&hdr[kHdrBucketCursor + cls], (uint32_t)n_items);
+    const int s0 = start[c];
+    for (int k = 0; k < n_items; ++k) {
+        const int t0 = k * kTargetsPerItem;
+        const int cnt = min(kTargetsPerItem, nt - t0);
+        items[at + k] = make_int4(c, s0 + t0, cnt, lk | (seg << 4));
+    }
+}
+
+// --------------------------------------------------------------- pair kernels
+
+// The 27 neighbour cells of a home cell, one per lane (lanes 0..26): first
+// binned slot, count, exclusive prefix of counts, centre shift.
+struct Stencil {
+    int nstart, excl;
+    float sx, sy, sz;
+    int total;
+};
+
+__device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
+                                              const int *__restrict__ start, int lane,
+                                              Stencil &st)
+{
+    int ix, iy, iz;
+    decode_cell(S, cell, ix, iy, iz);
+    int cnt = 0;
+    st.nstart = 0;
+    st.sx = st.sy = st.sz = 0.f;
+    if (lane < 27) {
+        const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
+        int jx, jy, jz;
+        const bool ok = neighbour(ix, dx, S.nc[0], S.lo[0], S.h[0], S.len[0], S.periodic, jx, st.sx) &&
+                        neighbour(iy, dy, S.nc[1], S.lo[1], S.h[1], S.len[1], S.periodic, jy, st.sy) &&
+                        neighbour(iz, dz, S.nc[2], S.lo[2], S.h[2], S.len[2], S.periodic, jz, st.sz);
+        if (ok) {
+            const int c = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
+            st.nstart = start[c];
+            cnt = start[c + 1] - st.nstart;
+        }
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    st.excl = incl - cnt;
+    st.total = __shfl(incl, 26);
+}
+
+// Source v of the stencil's virtual concatenation: binned slot and shift.
+// Every lane must call it (cross-lane reads); v is clamped to the last source.
+__device__ __forceinline__ int stencil_locate(const Stencil &st, int v, float &sx, float &sy,
+                                              float &sz)
+{
+    const int vv = min(v, st.total - 1);
+    int q = 0;
+#pragma unroll
+    for (int step = 16; step >= 1; step >>= 1) {
+        const int cand = q + step;
+        const int e = __shfl(st.excl, min(cand, 26));
+        if (cand <= 26 && e <= vv) q = cand;
+    }
+    sx = __shfl(st.sx, q);
+    sy = __shfl(st.sy, q);
+    sz = __shfl(st.sz, q);
+    return __shfl(st.nstart, q) + (vv - __shfl(st.excl, q));
+}
+
+struct Src {
+    const float *__restrict__ x;
+    const float *__restrict__ y;
+    const float *__restrict__ z;
+    const float *__restrict__ m;
+};
+
+__device__ __forceinline__ float4 fetch_pos(const Stencil &st, int v, const Src &s)
+{
+    float sx, sy, sz;
+    const int j = stencil_locate(st, v, sx, sy, sz);
+    float4 r;
+    r.x = s.x[j] + sx;
+    r.y = s.y[j] + sy;
+    r.z = s.z[j] + sz;
+    r.w = s.m[j];
+    if (v >= st.total) r = make_float4(kFar, kFar, kFar, 0.f);
+    return r;
+}
+
+// Pull the next work item: queues are interleaved blocks of kQueueBlock
+// items of the cost-ordered list; a wave drains the queue of its XCD first.
+__device__ __forceinline__ int64_t next_item(uint32_t *hdr, int q, int lane)
+{
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(&hdr[kHdrQueue + 32 * q], 1u);
+    c = __builtin_amdgcn_readfirstlane(c);
+    return ((int64_t)(c / kQueueBlock) * kQueues + q) * kQueueBlock + (c % kQueueBlock);
+}
+
+__device__ __forceinline__ float horner5(const float *q, float t)
+{
+    float p = fmaf(q[5], t, q[4]);
+    p = fmaf(p, t, q[3]);
+    p = fmaf(p, t, q[2]);
+    p = fmaf(p, t, q[1]);
+    return fmaf(p, t, q[0]);
+}
+
+__device__ __forceinline__ float horner4(const float *q, float t)
+{
+    float p = fmaf(q[4], t, q[3]);
+    p = fmaf(p, t, q[2]);
+    p = fmaf(p, t, q[1]);
+    return fmaf(p, t, q[0]);
+}
+
+// Forward: acc[out_row] = sum over the stencil of m_j d f_SR.
+template <class Acc, bool kSoft>
+__global__ __launch_bounds__(64) void k_force(Acc acc, const int4 *__restrict__ items,
+                                              uint32_t *hdr, const int *__restrict__ start, Src src,
+                                              const int *__restrict__ out_row,
+                                              float *__restrict__ out, int n_out)
+{
+    __shared__ float4 stage[kWave];
+    const int lane = threadIdx.x;
+    const int64_t n_items = hdr[kHdrNItems];
+    const int q0 = blockIdx.x & (kQueues - 1);
+    for (int qq = 0; qq < kQueues; ++qq) {
+        const int q = (q0 + qq) & (kQueues - 1);
+        for (;;) {
+            const int64_t g = next_item(hdr, q, lane);
+            if (g >= n_items) break;
+            const int4 it = items[g];
+            const int t0 = it.y, nt = it.z, lk = it.w & 15;
+            const SegParams &S = acc.get(it.w >> 4);
+            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
+            float cq[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
+            Stencil st;
+            stencil_setup(S, it.x, start, lane, st);
+            const int kl = 1 << lk;
+            const int t = lane >> lk, sub = lane & (kl - 1);
+            const bool tv = t < nt;
+            float px = 0.f, py = 0.f, pz = 0.f;
+            if (tv) {
+                px = src.x[t0 + t];
+                py = src.y[t0 + t];
+                pz = src.z[t0 + t];
+            }
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            float4 nxt = fetch_pos(st, lane, src);
+            for (int base = 0; base < st.total; base += kWave) {
+                __syncthreads();
+                stage[lane] = nxt;
+                __syncthreads();
+                if (base + kWave < st.total) nxt = fetch_pos(st, base + kWave + lane, src);
+                const int cnt = min(kWave, st.total - base);
+                const int niter = (cnt + kl - 1) >> lk;
+#pragma unroll 4
+                for (int i = 0; i < niter; ++i) {
+                    const float4 s = stage[sub + (i << lk)];
+                    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+                    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                    const float qi = __builtin_amdgcn_rsqf(tt);
+                    const float q2 = qi * qi;
+                    const float f = fmaf(q2, qi, -horner5(cq, tt));
+                    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
+                    const float w = in ? s.w * f : 0.f;
+                    ax = fmaf(w, dx, ax);
+                    ay = fmaf(w, dy, ay);
+                    az = fmaf(w, dz, az);
+                }
+            }
+            for (int o = 1; o < kl; o <<= 1) {
+                ax += __shfl_xor(ax, o);
+                ay += __shfl_xor(ay, o);
+                az += __shfl_xor(az, o);
+            }
+            if (tv && sub == 0) {
+                const int r = out_row[t0 + t];
+                if (r >= 0 && r < n_out) {
+                    const int64_t o3 = 3 * (int64_t)r;
+                    out[o3] = ax;
+                    out[o3 + 1] = ay;
+                    out[o3 + 2] = az;
+                }
+            }
+        }
+    }
+}
+
+// Adjoint: grad[perm] = sum over the stencil of f u + 2 f' (u.d) d,
+// u = m_k g_j - m_j g_k.
+template <class Acc, bool kSoft>
+__global__ __launch_bounds__(64) void k_vjp(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
+                                            const int *__restrict__ start, Src src,
+                                            const float *__restrict__ gx,
+                                            const float *__restrict__ gy,
+                                            const float *__restrict__ gz,
+                                            const int *__restrict__ perm,
+                                            float *__restrict__ out, int n_out)
+{
+    __shared__ float4 stage_p[kWave];
+    __shared__ float4 stage_g[kWave];
+    const int lane = threadIdx.x;
+    const int64_t n_items = hdr[kHdrNItems];
+    const int q0 = blockIdx.x & (kQueues - 1);
+    for (int qq = 0; qq < kQueues; ++qq) {
+        const int q = (q0 + qq) & (kQueues - 1);
+        for (;;) {
+            const int64_t g = next_item(hdr, q, lane);
+            if (g >= n_items) break;
+            const int4 it = items[g];
+            const int t0 = it.y, nt = it.z, lk = it.w & 15;
+            const SegParams &S = acc.get(it.w >> 4);
+            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
+            float cq[6], cd[5];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) cd[k] = S.pc.dq[k];
+            Stencil st;
+            stencil_setup(S, it.x, start, lane, st);
+            const int kl = 1 << lk;
+            const int t = lane >> lk, sub = lane & (kl - 1);
+            const bool tv = t < nt;
+            float px = 0.f, py = 0.f, pz = 0.f, mk = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
+            if (tv) {
+                const int b = t0 + t;
+                px = src.x[b];
+                py = src.y[b];
+                pz = src.z[b];
+                mk = src.m[b];
+                gkx = gx[b];
+                gky = gy[b];
+                gkz = gz[b];
+            }
+            float rx = 0.f, ry = 0.f, rz = 0.f;
+            float4 nxp, nxg;
+            {
+                float sx, sy, sz;
+                const int v = lane;
+                const int j = stencil_locate(st, v, sx, sy, sz);
+                nxp = make_float4(src.x[j] + sx, src.y[j] + sy, src.z[j] + sz, src.m[j]);
+                nxg = make_float4(gx[j], gy[j], gz[j], 0.f);
+                if (v >= st.total) {
+                    nxp = make_float4(kFar, kFar, kFar, 0.f);
+                    nxg = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            for (int base = 0; base < st.total; base += kWave) {
+                __syncthreads();
+                stage_p[lane] = nxp;
+                stage_g[lane] = nxg;
+                __syncthreads();
+                if (base + kWave < st.total) {
+                    float sx, sy, sz;
+                    const int v = base + kWave + lane;
+                    const int j = stencil_locate(st, v, sx, sy, sz);
+                    nxp = make_float4(src.x[j] + sx, src.y[j] + sy, src.z[j] + sz, src.m[j]);
+                    nxg = make_float4(gx[j], gy[j], gz[j], 0.f);
+                    if (v >= st.total) {
+                        nxp = make_float4(kFar, kFar, kFar, 0.f);
+                        nxg = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                }
+                const int cnt = min(kWave, st.total - base);
+                const int niter = (cnt + kl - 1) >> lk;
+#pragma unroll 2
+                for (int i = 0; i < niter; ++i) {
+                    const int e = sub + (i << lk);
+                    const float4 s = stage_p[e];
+                    const float4 gj = stage_g[e];
+                    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+                    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                    const float qi = __builtin_amdgcn_rsqf(tt);
+                    const float q2 = qi * qi;
+                    const float q3 = q2 * qi;
+                    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
+                    const float f = in ? q3 - horner5(cq, tt) : 0.f;
+                    const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
+                    const float ux = fmaf(mk, gj.x, -s.w * gkx);
+                    const float uy = fmaf(mk, gj.y, -s.w * gky);
+                    const float uz = fmaf(mk, gj.z, -s.w * gkz);
+                    const float c = fp2 * fmaf(ux, dx, fmaf(uy, dy, uz * dz));
+                    rx = fmaf(c, dx, fmaf(f, ux, rx));
+                    ry = fmaf(c, dy, fmaf(f, uy, ry));
+                    rz = fmaf(c, dz, fmaf(f, uz, rz));
+                }
+            }
+            for (int o = 1; o < kl; o <<= 1) {
+                rx += __shfl_xor(rx, o);
+                ry += __shfl_xor(ry, o);
+                rz += __shfl_xor(rz, o);
+            }
+            const int pk = (tv && sub == 0) ? perm[t0 + t] : -1;
+            if (pk >= 0 && pk < n_out) {
+                const int64_t o3 = 3 * (int64_t)pk;
+                out[o3] = rx;
+                out[o3 + 1] = ry;
+                out[o3 + 2] = rz;
+            }
+        }
+    }
+}
+
+// Ordered pairs (active target, source) with 0 < s < r_s^2, decided exactly as
+// in k_force.
+template <class Acc>
+__global__ __launch_bounds__(64) void k_count(Acc acc, const int4 *__restrict__ items,
+                                              uint32_t *hdr, const int *__restrict__ start,
+                                              Src src)
+{
+    __shared__ float4 stage[kWave];
+    const int lane = threadIdx.x;
+    const int64_t n_items = hdr[kHdrNItems];
+    const int q0 = blockIdx.x & (kQueues - 1);
+    unsigned long long pairs = 0;
+    for (int qq = 0; qq < kQueues; ++qq) {
+        const int q = (q0 + qq) & (kQueues - 1);
+        for (;;) {
+            const int64_t g = next_item(hdr, q, lane);
+            if (g >= n_items) break;
+            const int4 it = items[g];
+            const int t0 = it.y, nt = it.z, lk = it.w & 15;
+            const SegParams &S = acc.get(it.w >> 4);
+            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
+            Stencil st;
+            stencil_setup(S, it.x, start, lane, st);
+            const int kl = 1 << lk;
+            const int t = lane >> lk, sub = lane & (kl - 1);
+            const bool tv = t < nt;
+            float px = 0.f, py = 0.f, pz = 0.f;
+            if (tv) {
+                px = src.x[t0 + t];
+                py = src.y[t0 + t];
+                pz = src.z[t0 + t];
+            }
+            unsigned cnt_lane = 0;
+            float4 nxt = fetch_pos(st, lane, src);
+            for (int base = 0; base < st.total; base += kWave) {
+                __syncthreads();
+                stage[lane] = nxt;
+                __syncthreads();
+                if (base + kWave < st.total) nxt = fetch_pos(st, base + kWave + lane, src);
+                const int cnt = min(kWave, st.total - base);
+                const int niter = (cnt + kl - 1) >> lk;
+                for (int i = 0; i < niter; ++i) {
+                    const float4 s = stage[sub + (i << lk)];
+                    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+                    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                    const float s2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    cnt_lane += (tt < tc2 && s2 > 0.f && s.w == s.w) ? 1u : 0u;
+                }
+            }
+            if (tv) pairs += cnt_lane;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o);
+    if (lane == 0 && pairs)
+        atomicAdd((unsigned long long *)&hdr[kHdrPairs], pairs);
+}
+
+// --------------------------------------------------------------- A8: momentum
+
+__device__ __forceinline__ double block_sum_d(double v, double *lds)
+{
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+template <class Acc>
+__global__ __launch_bounds__(256) void k_mom_partial(Acc acc, const float *__restrict__ a,
+                                                     const float *__restrict__ mass,
+                                                     double *__restrict__ part)
+{
+    __shared__ double lds[256];
+    const int tile = blockIdx.x;
+    const SegParams &S = acc.get(acc.seg_of_tile(tile));
+    const int64_t r0 = (int64_t)(tile - S.tile_off) * kMomTile;
+    const int64_t r1 = min(r0 + kMomTile, (int64_t)S.n_active);
+    double sx = 0, sy = 0, sz = 0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+        const double m = mass[S.part_off + r];
+        const int64_t o3 = 3 * (S.out_off + r);
+        sx += m * (double)a[o3];
+        sy += m * (double)a[o3 + 1];
+        sz += m * (double)a[o3 + 2];
+    }
+    sx = block_sum_d(sx, lds);
+    sy = block_sum_d(sy, lds);
+    sz = block_sum_d(sz, lds);
+    if (threadIdx.x == 0) {
+        part[3 * tile] = sx;
+        part[3 * tile + 1] = sy;
+        part[3 * tile + 2] = sz;
+    }
+}
+
+template <class Acc>
+__global__ void k_mom_final(Acc acc, int B, int ntiles, const double *__restrict__ part,
+                            double *__restrict__ out)
+{
+    const int b = blockIdx.x;
+    if (threadIdx.x != 0 || b >= B) return;
+    const SegParams &S = acc.get(b);
+    const int t1 = (b + 1 < B) ? acc.get(b + 1).tile_off : ntiles;
+    double x = 0, y = 0, z = 0;
+    for (int t = S.tile_off; t < t1; ++t) {
+        x += part[3 * t];
+        y += part[3 * t + 1];
+        z += part[3 * t + 2];
+    }
+    out[3 * b] = x;
+    out[3 * b + 1] = y;
+    out[3 * b + 2] = z;
+}
+
+// --------------------------------------------------------------- dispatch
+
+template <class F>
+hipError_t with_acc(const DevArgs &a, F &&f)
+{
+    if (a.seg_dev) return f(ManySeg{a.seg_dev, a.L->B});
+    return f(OneSeg{*a.seg_host});
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <class T>
+T *at(const DevArgs &a, size_t off)
+{
+    return reinterpret_cast<T *>(a.ws + off);
+}
+
+bool all_softened(const DevArgs &a)
+{
+    if (a.seg_dev) return a.seg_host != nullptr && a.seg_host->pc.softened;  // host summary
+    return a.seg_host->pc.softened != 0;
+}
+
+template <bool kActiveOnly>
+hipError_t build_items(const DevArgs &a)
+{
+    const Layout &L = *a.L;
+    uint32_t *hdr = at<uint32_t>(a, L.hdr);
+    hipError_t e = fill_u32(hdr + kHdrBucketCount, kClasses, 0, a.st);
+    if (e != hipSuccess) return e;
+    return with_acc(a, [&](auto acc) -> hipError_t {
+        const unsigned nb = blocks_for(L.NC, 256);
+        k_items_count<decltype(acc), kActiveOnly><<<nb, 256, 0, a.st>>>(
+            acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact), at<uint32_t>(a, L.info), hdr,
+            L.magic(), (int)L.N);
+        k_items_base<<<1, 64, 0, a.st>>>(hdr, L.magic());
+        k_items_write<decltype(acc), kActiveOnly><<<nb, 256, 0, a.st>>>(
+            acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact), at<uint32_t>(a, L.info), hdr,
+            at<int4>(a, L.items));
+        return hipGetLastError();
+    });
+}
+
+unsigned persistent_grid(const DevArgs &a)
+{
+    int64_t g = (int64_t)a.num_cu * a.waves_per_cu;
+    if (g > a.L->item_cap) g = a.L->item_cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+Src src_of(const DevArgs &a)
+{
+    const Layout &L = *a.L;
+    return Src{at<float>(a, L.bx), at<float>(a, L.by), at<float>(a, L.bz), at<float>(a, L.bm)};
+}
+
+}  // namespace
+
+int64_t scan_scratch_elems(int64_t m)
+{
+    int64_t total = 0;
+    int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+    while (nb > 1) {
+        total += 2 * nb + 1 + 64;
+        nb = (nb + kScanBlock - 1) / kScanBlock;
+    }
+    return total + 64;
+}
+
+hipError_t dev_zero(void *p, int64_t words, hipStream_t st) { return fill_u32(p, words, 0, st); }
+
+hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
+{
+    const Layout &L = *a.L;
+    hipError_t e;
+    if ((e = fill_u32(at<uint32_t>(a, L.hdr), kHdrWords, 0, a.st)) != hipSuccess) return e;
+    if ((e = fill_u32(at<uint32_t>(a, L.count), L.NC, 0, a.st)) != hipSuccess) return e;
+    if ((e = fill_u32(at<uint32_t>(a, L.nact), L.NC, 0, a.st)) != hipSuccess) return e;
+    if (L.N == 0) return scan_i32(at<int>(a, L.count), at<int>(a, L.start), L.NC, at<int>(a, L.scan_tmp), a.st);
+    e = with_acc(a, [&](auto acc) -> hipError_t {
+        k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, (int)L.N, at<int>(a, L.cell_of),
+                                                             at<int>(a, L.count), at<int>(a, L.nact),
+                                                             at<uint32_t>(a, L.hdr));
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    const int *kin = at<int>(a, L.cell_of);
+    const int *vin = nullptr;
+    const int R = 1 << L.digit_bits;
+    for (int p = 0; p < L.passes; ++p) {
+        const int shift = p * L.digit_bits;
+        int *kout = at<int>(a, L.keys[p & 1]);
+        int *vout = at<int>(a, L.vals[p & 1]);
+        k_radix_hist<<<(unsigned)L.ntiles, 256, 0, a.st>>>(kin, (int)L.N, shift, L.digit_bits,
+                                                         at<int>(a, L.tab), (int)L.ntiles);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan_i32(at<int>(a, L.tab), at<int>(a, L.tabx), (int64_t)R * L.ntiles,
+                          at<int>(a, L.scan_tmp), a.st)) != hipSuccess)
+            return e;
+        k_radix_scatter<<<(unsigned)L.ntiles, 64, 0, a.st>>>(
+            kin, vin, (int)L.N, shift, L.digit_bits, at<int>(a, L.tabx), (int)L.ntiles,
+            p == L.passes - 1 ? nullptr : kout, vout);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        kin = kout;
+        vin = vout;
+    }
+    if ((e = scan_i32(at<int>(a, L.count), at<int>(a, L.start), L.NC, at<int>(a, L.scan_tmp), a.st)) !=
+        hipSuccess)
+        return e;
+    return with_acc(a, [&](auto acc) -> hipError_t {
+        k_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
+            acc, (int)L.N, at<int>(a, L.perm()), pos, mass, at<float>(a, L.bx), at<float>(a, L.by),
+            at<float>(a, L.bz), at<float>(a, L.bm), at<int>(a, L.out_row), at<uint32_t>(a, L.hdr),
+            L.magic());
+        return hipGetLastError();
+    });
+}
+
+hipError_t dev_force(const DevArgs &a, float *acc_out)
+{
+    const Layout &L = *a.L;
+    hipError_t e = build_items<true>(a);
+    if (e != hipSuccess) return e;
+    const bool soft = all_softened(a);
+    return with_acc(a, [&](auto acc) -> hipError_t {
+        void *tok = nullptr;
+        timing_begin("force", a.st, &tok);
+        if (soft)
+            k_force<decltype(acc), true><<<persistent_grid(a), kWave, 0, a.st>>>(
+                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
+                at<int>(a, L.out_row), acc_out, a.n_rows);
+        else
+            k_force<decltype(acc), false><<<persistent_grid(a), kWave, 0, a.st>>>(
+                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
+                at<int>(a, L.out_row), acc_out, a.n_rows);
+        const hipError_t le = hipGetLastError();
+        timing_end(tok, a.st);
+        return le;
+    });
+}
+
+hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad)
+{
+    const Layout &L = *a.L;
+    k_gather_g<<<blocks_for(L.N, 256), 256, 0, a.st>>>((int)L.N, a.n_rows, at<int>(a, L.out_row), g,
+                                                      at<float>(a, L.gx), at<float>(a, L.gy),
+                                                      at<float>(a, L.gz));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = build_items<false>(a)) != hipSuccess) return e;
+    const bool soft = all_softened(a);
+    return with_acc(a, [&](auto acc) -> hipError_t {
+        void *tok = nullptr;
+        timing_begin("vjp", a.st, &tok);
+        if (soft)
+            k_vjp<decltype(acc), true><<<persistent_grid(a), kWave, 0, a.st>>>(
+                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
+                at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz), at<int>(a, L.perm()), grad,
+                (int)L.N);
+        else
+            k_vjp<decltype(acc), false><<<persistent_grid(a), kWave, 0, a.st>>>(
+                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
+                at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz), at<int>(a, L.perm()), grad,
+                (int)L.N);
+        const hipError_t le = hipGetLastError();
+        timing_end(tok, a.st);
+        return le;
+    });
+}
+
+__global__ void k_copy_pairs(const uint32_t *hdr, int64_t *out)
+{
+    if (threadIdx.x == 0) *out = *(const int64_t *)&hdr[kHdrPairs];
+}
+
+hipError_t dev_count_pairs(const DevArgs &a, int64_t *pairs)
+{
+    const Layout &L = *a.L;
+    hipError_t e = build_items<true>(a);
+    if (e != hipSuccess) return e;
+    if ((e = fill_u32(at<uint32_t>(a, L.hdr) + kHdrPairs, 2, 0, a.st)) != hipSuccess) return e;
+    e = with_acc(a, [&](auto acc) -> hipError_t {
+        k_count<<<persistent_grid(a), kWave, 0, a.st>>>(acc, at<int4>(a, L.items),
+                                                       at<uint32_t>(a, L.hdr), at<int>(a, L.start),
+                                                       src_of(a));
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    k_copy_pairs<<<1, 64, 0, a.st>>>(at<uint32_t>(a, L.hdr), pairs);
+    return hipGetLastError();
+}
+
+hipError_t dev_momentum(const DevArgs &a, const float *acc_rows, const float *mass, double *out)
+{
+    const Layout &L = *a.L;
+    if (L.mom_tiles <= 0) {
+        return with_acc(a, [&](auto acc) -> hipError_t {
+            k_mom_final<<<(unsigned)L.B, 64, 0, a.st>>>(acc, L.B, 0, at<double>(a, L.mom), out);
+            return hipGetLastError();
+        });
+    }
+    return with_acc(a, [&](auto acc) -> hipError_t {
+        k_mom_partial<<<(unsigned)L.mom_tiles, 256, 0, a.st>>>(acc, acc_rows, mass, at<double>(a, L.mom));
+        k_mom_final<<<(unsigned)L.B, 64, 0, a.st>>>(acc, L.B, (int)L.mom_tiles, at<double>(a, L.mom), out);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace sr

@@ -1,0 +1,125 @@
+"""The C ABI on the CPU: the library loads, exports what sr.h declares, and
+rejects bad arguments on the host before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_3396_amd import _sr, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sr.h")
+FAKE = C.c_void_p(0x10000)  # never dereferenced: every case fails validation first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sr_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function():
+    L = _sr.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(_sr.EXPORTS)
+    assert L.sr_abi_version() == 1
+    assert L.sr_status_str(0) == b"ok"
+
+
+def prob(length=32.0, periodic=True, r_s=3.0, eps=0.05, lo=(0, 0, 0)):
+    return _sr.as_problem(synth.Problem.make(lo, (length,) * 3, periodic, r_s, eps,
+                                             synth.filter_poly(3.0, 0.05)))
+
+
+def test_grid_matches_binning_rule():
+    for L_, per in [(32.0, True), (9.0, True), (326.0, False), (2.0, False), (128.0, True),
+                    (21.544347, True)]:
+        p = synth.Problem.make((0, 0, 0) if per else (-3, -3, -3), (L_,) * 3, per, 3.0, 0.05,
+                               (0,) * 6)
+        assert tuple(_sr.grid(p)) == tuple(oracle.grid(p))
+
+
+def test_workspace_bytes_grows_with_n():
+    p = prob()
+    sizes = [_sr.workspace_bytes(n, p) for n in (0, 1, 1000, 100000)]
+    assert all(b > 0 and b % 256 == 0 for b in sizes)
+    assert sizes == sorted(sizes)
+
+
+def _force(n=100, n_active=100, p=None, ws=FAKE, ws_bytes=None, flags=0, pos=FAKE, mass=FAKE,
+           acc=FAKE):
+    p = p if p is not None else prob()
+    if ws_bytes is None:
+        ws_bytes = _sr.workspace_bytes(max(n, 0), prob()) + (1 << 20)
+    return _sr.lib().sr_force(pos, mass, n, n_active, C.byref(p), ws, ws_bytes, flags, acc, None)
+
+
+def test_host_validation_codes():
+    E_ARG, E_WS = 1, 2
+    assert _force(n=-1) == E_ARG
+    assert _force(n=10, n_active=11) == E_ARG
+    assert _force(n=10, n_active=-1) == E_ARG
+    assert _force(pos=None) == E_ARG
+    assert _force(mass=None) == E_ARG
+    assert _force(acc=None) == E_ARG
+    assert _force(flags=8) == E_ARG
+    assert _force(p=prob(length=8.9)) == E_ARG          # periodic box below 3 r_s
+    assert _force(p=prob(r_s=0.0)) == E_ARG
+    assert _force(p=prob(r_s=-1.0)) == E_ARG
+    assert _force(p=prob(eps=-0.1)) == E_ARG
+    assert _force(p=prob(lo=(1, 0, 0))) == E_ARG        # periodic needs lo = 0
+    bad = prob()
+    bad.poly[3] = float("nan")
+    assert _force(p=bad) == E_ARG
+    bad = prob()
+    bad.len[1] = float("inf")
+    assert _force(p=bad) == E_ARG
+    assert _force(ws=None) == E_WS
+    assert _force(ws=C.c_void_p(0x10010)) == E_WS       # not 256-byte aligned
+    assert _force(ws_bytes=1024) == E_WS
+
+
+def test_empty_problem_is_a_noop_without_device():
+    p = prob()
+    assert _force(n=0, n_active=0, pos=None, mass=None, acc=None) == 0
+    L = _sr.lib()
+    assert L.sr_bin(None, None, 0, 0, C.byref(p), FAKE, _sr.workspace_bytes(0, p), None) == 0
+    assert L.sr_force_vjp(None, None, 0, 0, C.byref(p), FAKE, _sr.workspace_bytes(0, p), 0, None,
+                          None, None) == 0
+
+
+def test_vjp_and_bin_validation():
+    L = _sr.lib()
+    p = prob()
+    nb = _sr.workspace_bytes(100, p)
+    assert L.sr_force_vjp(FAKE, FAKE, 100, 100, C.byref(p), FAKE, nb, 0, None, FAKE, None) == 1
+    assert L.sr_force_vjp(FAKE, FAKE, 100, 100, C.byref(p), FAKE, nb, 0, FAKE, None, None) == 1
+    assert L.sr_bin(FAKE, FAKE, 100, 101, C.byref(p), FAKE, nb, None) == 1
+    assert L.sr_bin(FAKE, FAKE, 100, 100, C.byref(p), FAKE, nb - 256, None) == 2
+    assert L.sr_momentum(FAKE, FAKE, -1, FAKE, 4096, FAKE, None) == 1
+    assert L.sr_count_pairs(100, 100, C.byref(p), FAKE, nb, None, None) == 1
+
+
+def test_batch_plan_validation_and_layout():
+    L = _sr.lib()
+    probs = [prob(), prob(length=40.0)]
+    arr = (_sr.Problem * 2)(*probs)
+    plan = C.c_void_p()
+    nb = C.c_size_t()
+    off = np.array([0, 100, 250], np.int64)
+    act = np.array([100, 120], np.int64)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    assert L.sr_batch_plan_create(2, ptr(np.array([1, 100, 250], np.int64)), ptr(act), arr, None,
+                                  C.byref(plan), C.byref(nb)) == 1
+    assert L.sr_batch_plan_create(2, ptr(off), ptr(np.array([101, 10], np.int64)), arr, None,
+                                  C.byref(plan), C.byref(nb)) == 1
+    assert L.sr_batch_plan_create(0, ptr(off), ptr(act), arr, None, C.byref(plan), C.byref(nb)) == 1
+    bad = (_sr.Problem * 2)(prob(), prob(length=5.0))
+    assert L.sr_batch_plan_create(2, ptr(off), ptr(act), bad, None, C.byref(plan), C.byref(nb)) == 1
+    assert L.sr_batch_force(None, FAKE, FAKE, FAKE, 1 << 20, FAKE, None, 0, None) == 4

@@ -1,0 +1,155 @@
+"""Forward parity of the HIP force path against the float64 oracle, element by
+element (RMS relative error <= 1e-5), plus edge cases and invariants."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1411_3396_amd as sr
+from paper_1411_3396_amd import synth
+from gpu_helpers import (DEV, FWD_TOL, announce, assert_force_close, gpu_force, oracle_force,
+                         to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def small_cases():
+    return {
+        "uniform_32k": lambda: synth.uniform_32k(),
+        "clustered_65k": lambda: synth.clustered_box(65536, 40.0, 61, 0),
+        "dense_halos": lambda: synth.clustered_box(120000, 30.0, 12, 1, halo_frac=0.8,
+                                                   mass_range=(1e3, 1e5)),
+        "slab_ghosts": lambda: synth.slab_with_ghosts(40, 3.0, 300, 2),
+        "odd_box": lambda: synth.uniform_box(20000, 27.3, 3),
+    }
+
+
+@pytest.mark.parametrize("name", list(small_cases()))
+def test_force_matches_oracle(name):
+    w = small_cases()[name]()
+    announce(f"force {name} n={w.n} n_active={w.n_active}")
+    assert_force_close(gpu_force(w), oracle_force(w), what=name)
+
+
+def test_force_random_masses_and_softening():
+    w = synth.clustered_box(50000, 32.0, 40, 9)
+    w.mass = np.random.default_rng(1).uniform(0.1, 3.0, w.n).astype(np.float32)
+    for eps in (0.02, 0.2):
+        w.problem = synth.Problem.make((0, 0, 0), w.problem.len, True, 3.0, eps,
+                                       synth.filter_poly(3.0, 0.05))
+        announce(f"force random masses eps={eps}")
+        assert_force_close(gpu_force(w), oracle_force(w), what=f"eps={eps}")
+
+
+def test_force_unsoftened_newton():
+    # eps = 0 takes the kernel variant that also masks s = 0
+    rng = np.random.default_rng(4)
+    pos = rng.random((6000, 3)).astype(np.float32) * 20.0
+    w = synth.uniform_box(1, 20.0, 0)
+    w.pos, w.mass, w.n_active = pos, np.ones(6000, np.float32), 6000
+    w.problem = synth.Problem.make((0, 0, 0), (20.0,) * 3, True, 3.0, 0.0, synth.filter_poly(3.0, 0.05))
+    announce("force eps=0")
+    assert_force_close(gpu_force(w), oracle_force(w), what="eps=0")
+
+
+def test_two_body_on_gpu():
+    L = 32.0
+    poly = synth.filter_poly(3.0, 0.05)
+    P = synth.Problem.make((0, 0, 0), (L,) * 3, True, 3.0, 0.05, poly)
+    rs = []
+    for r in [0.01, 0.05, 0.3, 1.0, 2.0, 2.9, 2.999, 3.001, 3.01, 4.0, 15.9]:
+        pos = np.array([[10.0, 11.0, 12.0], [10.0 + r, 11.0, 12.0]], np.float32)
+        w = synth.Workload("two", pos, np.ones(2, np.float32), 2, P)
+        announce(f"two body r={r}")
+        acc = gpu_force(w)
+        ref = oracle_force(w)
+        if r > 3.0:
+            assert np.all(acc == 0.0), (r, acc)
+        else:
+            # float32 error on the scale of the unfiltered Newtonian pull m/r^2
+            np.testing.assert_allclose(acc, ref, rtol=0, atol=2e-6 / r ** 2)
+        rs.append(r)
+    # across the periodic face, softening off, no filter
+    P0 = synth.Problem.make((0, 0, 0), (L,) * 3, True, 3.0, 0.0, (0,) * 6)
+    w = synth.Workload("face", np.array([[0.4, 5, 5], [L - 0.6, 5, 5]], np.float32),
+                       np.ones(2, np.float32), 2, P0)
+    np.testing.assert_allclose(gpu_force(w), [[-1, 0, 0], [1, 0, 0]], rtol=1e-6, atol=1e-7)
+
+
+def test_single_particle_and_one_cell():
+    w = synth.uniform_box(1, 12.0, 0)
+    announce("single particle")
+    assert np.all(gpu_force(w) == 0.0)
+    w = synth.uniform_box(700, 9.0, 7)
+    w.problem = synth.Problem.make((0, 0, 0), (2.5,) * 3, False, 3.0, 0.05, (0,) * 6)
+    w.pos = (w.pos / 9.0 * 2.5).astype(np.float32)
+    announce("one cell, all pairs, no filter")
+    assert_force_close(gpu_force(w), oracle_force(w), what="one cell")
+
+
+def test_no_active_particles():
+    w = synth.slab_with_ghosts(12, 3.0, 5, 3)
+    w.n_active = 0
+    announce("n_active=0")
+    assert gpu_force(w).shape == (0, 3)
+
+
+def test_random_filter_far_from_cutoff():
+    # a filter that is not continuous at r_s: no pair may sit within rounding of the cutoff
+    rng = np.random.default_rng(12)
+    poly = tuple(float(np.float32(rng.uniform(-1, 1) * 0.05 / 9.0 ** k)) for k in range(6))
+    for attempt in range(5):
+        w = synth.uniform_box(8000, 20.0, 100 + attempt)
+        w.problem = synth.Problem.make((0, 0, 0), (20.0,) * 3, True, 3.0, 0.05, poly)
+        from scipy.spatial import cKDTree
+        t = cKDTree(w.pos.astype(np.float64), boxsize=20.0)
+        close = t.query_pairs(3.0 + 1e-4) - t.query_pairs(3.0 - 1e-4)
+        if not close:
+            break
+    else:
+        pytest.skip("no configuration without pairs at the cutoff")
+    announce("random filter")
+    assert_force_close(gpu_force(w), oracle_force(w), what="random poly")
+
+
+def test_deterministic_and_mass_scaling_bitwise():
+    w = synth.clustered_box(80000, 36.0, 50, 21)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    announce("determinism")
+    a1 = sr.force(pos, mass, w.problem).cpu().numpy()
+    a2 = sr.force(pos, mass, w.problem).cpu().numpy()
+    a3 = sr.force(pos, 2.0 * mass, w.problem).cpu().numpy()
+    assert np.array_equal(a1.view(np.uint32), a2.view(np.uint32))
+    assert np.array_equal((2.0 * a1).view(np.uint32), a3.view(np.uint32))
+
+
+def test_reuse_bins_equals_fresh():
+    w = synth.slab_with_ghosts(30, 3.0, 80, 6)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    ws = sr.bin(pos, mass, w.problem, w.n_active)
+    a1 = sr.force(pos, mass, w.problem, w.n_active, ws=ws, reuse_bins=True)
+    a2 = sr.force(pos, mass, w.problem, w.n_active)
+    assert torch.equal(a1, a2)
+
+
+def test_pair_count_matches_oracle():
+    w = synth.clustered_box(60000, 40.0, 40, 13)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    ws = sr.bin(pos, mass, w.problem, w.n_active)
+    pairs = int(sr.count_pairs(ws, w.n, w.problem, w.n_active).item())
+    _, ref = oracle.force(w.pos, w.mass, w.n_active, w.problem)
+    announce(f"pairs gpu={pairs} oracle={ref}")
+    assert abs(pairs - ref) <= max(4, ref // 10 ** 7)
+
+
+def test_momentum_check_float64():
+    w = synth.uniform_box(30000, 31.0, 5)
+    w.mass = np.random.default_rng(3).uniform(0.5, 1.5, w.n).astype(np.float32)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    acc = sr.force(pos, mass, w.problem)
+    mom = sr.momentum(acc, mass).cpu().numpy()
+    a = acc.cpu().numpy().astype(np.float64)
+    ref = np.sum(w.mass.astype(np.float64)[:, None] * a, axis=0)
+    np.testing.assert_allclose(mom, ref, rtol=1e-9, atol=1e-9 * np.sum(np.abs(a)))
+    # Newton's third law for a periodic all-active box, up to float32 force errors
+    assert np.linalg.norm(mom) <= 1e-6 * np.sum(w.mass[:, None] * np.abs(a))

@@ -1,0 +1,251 @@
+"""Benchmark of the short-range force path on one MI355X.
+
+One step = the whole hot path over the node-share workload (320^3 active
+cells plus a 3-cell ghost shell, 34.6M particles, strongly clustered):
+binning, forward force, adjoint (vector-Jacobian product with a fixed N(0,1)
+cotangent) and the float64 momentum check.  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+
+value = pair interactions per second over the whole step: (useful pairs of
+the forward pass + useful pairs of the adjoint pass) / step time, a useful
+pair being an ordered (target, source) pair with 0 < r < r_s.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X (packed), 256 CUs x 2.4 GHz x 256 flop/clk
+PEAK_FP32_NONPACKED = 78.6  # TFLOP/s, one float32 FMA per lane per clock
+FLOP_PER_PAIR = {"force": 30, "vjp": 61}
+KERNEL_SYMBOL = {"force": "k_force", "vjp": "k_vjp"}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1411_3396_amd", "csrc", "sr_kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_SYMBOL[kernel]}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w, g, target_seconds: float):
+    """The float64 oracle on a random sample of active targets of the same workload."""
+    import oracle
+
+    rng = np.random.default_rng(7)
+    pilot = np.sort(rng.choice(w.n_active, size=min(20000, w.n_active), replace=False))
+    t0 = time.perf_counter()
+    _, pairs = oracle.force(w.pos, w.mass, w.n_active, w.problem, targets=pilot)
+    t_pilot = time.perf_counter() - t0
+    rate = pairs / max(t_pilot, 1e-9)
+    # forward + adjoint on the same sample, sized for about target_seconds
+    want = int(min(w.n_active, max(20000, target_seconds / 2.0 * rate / max(pairs / len(pilot), 1))))
+    sample = np.sort(rng.choice(w.n_active, size=want, replace=False))
+    t0 = time.perf_counter()
+    _, pairs = oracle.force(w.pos, w.mass, w.n_active, w.problem, targets=sample)
+    t1 = time.perf_counter()
+    oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g, targets=sample)
+    t2 = time.perf_counter()
+    return {"value": 2.0 * pairs / (t2 - t0), "unit": "pair interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{want} random active targets of {w.name} (seed 7), forward + adjoint, "
+                      f"float64 cell list incl. its own binning of all {w.n} particles per call; "
+                      f"{pairs} useful pairs per pass, {t1 - t0:.1f} s + {t2 - t1:.1f} s"}
+
+
+def batch_comparison(reps: int = 5):
+    """Batched persistent launch (graph) against one launch sequence per subvolume."""
+    import torch
+
+    import paper_1411_3396_amd as sr
+    from paper_1411_3396_amd import synth
+
+    b = synth.subvolumes_96()
+    dev = "cuda:0"
+    pos = torch.from_numpy(b.pos).to(dev)
+    mass = torch.from_numpy(b.mass).to(dev)
+    cache = os.path.join(ROOT, "paper_1411_3396_amd", "tune_cache.json")
+    plan = sr.BatchPlan(b.offsets, b.n_active, b.problems, tune_cache=cache)
+    ws = sr.new_workspace(plan.ws_bytes, dev)
+    acc = torch.empty((plan.total_active, 3), device=dev)
+    mom = torch.empty((plan.B, 3), dtype=torch.float64, device=dev)
+    out = {}
+    for mode in ("graph", "per_subvolume"):
+        plan.run(pos, mass, ws, acc, mom, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.run(pos, mass, ws, acc, mom, mode)
+        torch.cuda.synchronize()
+        out[mode] = 1e3 * (time.perf_counter() - t0) / reps
+    info = plan.info()
+    plan.close()
+    return {"workload": b.name, "subvolumes": b.size, "n": int(b.offsets[-1]),
+            "ms_graph": round(out["graph"], 3), "ms_per_subvolume": round(out["per_subvolume"], 3),
+            "speedup": round(out["per_subvolume"] / out["graph"], 3),
+            "waves_per_cu": info["waves_per_cu"]}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="node_share")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the short-range path is "
+              f"measured on one GPU's share of the domain", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1411_3396_amd as sr
+    from paper_1411_3396_amd import synth
+
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    w = synth.get(args.workload)
+    g_np = synth.cotangent(w.n_active, 1)
+    log(f"workload {w.name}: n={w.n} n_active={w.n_active} ({time.perf_counter() - t0:.1f} s to generate)")
+    pos = torch.from_numpy(w.pos).to(dev)
+    mass = torch.from_numpy(w.mass).to(dev)
+    g = torch.from_numpy(g_np).to(dev)
+    nb = sr.workspace_bytes(w.n, w.problem)
+    ws = sr.new_workspace(nb, dev)
+    acc = torch.empty((w.n_active, 3), device=dev)
+    grad = torch.empty((w.n, 3), device=dev)
+    mws = sr.new_workspace(1 << 20, dev)
+
+    # useful pairs of both passes, counted once outside the timed region
+    sr.bin(pos, mass, w.problem, w.n_active, ws=ws)
+    pairs_fwd = int(sr.count_pairs(ws, w.n, w.problem, w.n_active).item())
+    ws_all = sr.bin(pos, mass, w.problem, w.n)
+    pairs_bwd = int(sr.count_pairs(ws_all, w.n, w.problem, w.n).item())
+    del ws_all
+    torch.cuda.synchronize()
+    log(f"useful pairs: forward {pairs_fwd:.4e}, adjoint {pairs_bwd:.4e}")
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    phase = {"bin": 0.0, "force": 0.0, "vjp": 0.0, "momentum": 0.0}
+
+    def step(record: bool):
+        if record:
+            ev[0].record()
+        sr.bin(pos, mass, w.problem, w.n_active, ws=ws)
+        if record:
+            ev[1].record()
+        sr.force(pos, mass, w.problem, w.n_active, ws=ws, reuse_bins=True, out=acc)
+        if record:
+            ev[2].record()
+        sr.force_vjp(pos, mass, w.problem, g, w.n_active, ws=ws, reuse_bins=True, out=grad)
+        if record:
+            ev[3].record()
+        mom = sr.momentum(acc, mass, ws=mws)
+        if record:
+            ev[4].record()
+        return mom
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    sr.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        phase["bin"] += ev[0].elapsed_time(ev[1])
+        phase["force"] += ev[1].elapsed_time(ev[2])
+        phase["vjp"] += ev[2].elapsed_time(ev[3])
+        phase["momentum"] += ev[3].elapsed_time(ev[4])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kern = {}
+    for k in ("force", "vjp"):
+        ms, cnt = sr.timing_read(k)
+        kern[k] = ms / max(cnt, 1)
+    sr.timing_enable(False)
+    ms_step = 1e3 * elapsed / args.steps
+    for k in phase:
+        phase[k] /= args.steps
+    log(f"phases ms: {json.dumps({k: round(v, 3) for k, v in phase.items()})}; "
+        f"kernels ms: {json.dumps({k: round(v, 3) for k, v in kern.items()})}")
+
+    rate = (pairs_fwd + pairs_bwd) / (ms_step * 1e-3)
+    flops = {"force": FLOP_PER_PAIR["force"] * pairs_fwd, "vjp": FLOP_PER_PAIR["vjp"] * pairs_bwd}
+    dominant = max(kern, key=lambda k: kern[k])
+    achieved = flops[dominant] / (kern[dominant] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": KERNEL_SYMBOL[dominant], "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR, 4),
+                "traffic": measured_traffic(dominant, w.name),
+                "flop_per_useful_pair": FLOP_PER_PAIR[dominant], "kernel_ms": round(kern[dominant], 3)}
+    other = "force" if dominant == "vjp" else "vjp"
+    other_ach = flops[other] / (kern[other] * 1e-3) / 1e12
+    result = {
+        "metric": "short-range pair interactions/s (FP32) + backward/forward time ratio",
+        "value": rate,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "n_active": w.n_active,
+                   "n_ghost": w.n - w.n_active, "cells": int(np.prod(sr.grid(w.problem))),
+                   "r_s": w.problem.r_s, "eps": round(w.problem.eps, 6), "periodic": w.problem.periodic,
+                   "step": "bin + force + adjoint + float64 momentum", "parallelism": "none"},
+        "pairs_forward": pairs_fwd,
+        "pairs_adjoint": pairs_bwd,
+        "forward_pairs_per_s": pairs_fwd / (kern["force"] * 1e-3),
+        "bwd_fwd_ratio_kernel": round(kern["vjp"] / kern["force"], 3),
+        "bwd_fwd_ratio_step": round(phase["vjp"] / (phase["bin"] + phase["force"]), 3),
+        "phase_ms": {k: round(v, 3) for k, v in phase.items()},
+        "roofline": roofline,
+        "roofline_other": {"kernel": KERNEL_SYMBOL[other], "achieved": round(other_ach, 3),
+                           "frac": round(other_ach / PEAK_FP32_VECTOR, 4),
+                           "kernel_ms": round(kern[other], 3)},
+        "peak_fp32_nonpacked": PEAK_FP32_NONPACKED,
+    }
+    if not args.no_batch:
+        log("batched vs per-subvolume")
+        result["batch"] = batch_comparison()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(w, g_np, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

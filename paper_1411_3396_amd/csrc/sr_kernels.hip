@@ -106,24 +106,31 @@ __device__ __forceinline__ int bin_coord(float x, float lo, float len, float inv
 }
 
 // Neighbour j = i + d in one dimension: false if outside an open domain.
-// shift = centre(j) (+/- len when wrapped) - centre(i).
+// shift = centre of the neighbour's image minus centre(i).  Across a periodic
+// face the box length is taken off whichever centre lies in the upper half of
+// the box, a subtraction that is exact (Sterbenz), so no coordinate of
+// magnitude len is ever rounded.
 __device__ __forceinline__ bool neighbour(int i, int d, int nc, float lo, float h, float len,
                                           int periodic, int &j, float &shift)
 {
 #pragma clang fp contract(off)
     j = i + d;
-    float wrap = 0.0f;
+    float cj, ci;
     if (j < 0) {
         if (!periodic) return false;
         j += nc;
-        wrap = -len;
+        cj = cell_centre(j, lo, h) - len;
+        ci = cell_centre(i, lo, h);
     } else if (j >= nc) {
         if (!periodic) return false;
         j -= nc;
-        wrap = len;
+        cj = cell_centre(j, lo, h);
+        ci = cell_centre(i, lo, h) - len;
+    } else {
+        cj = cell_centre(j, lo, h);
+        ci = cell_centre(i, lo, h);
     }
-    const float cj = cell_centre(j, lo, h) + wrap;
-    shift = cj - cell_centre(i, lo, h);
+    shift = cj - ci;
     return true;
 }
 

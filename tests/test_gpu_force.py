@@ -66,14 +66,19 @@ def test_two_body_on_gpu():
         if r > 3.0:
             assert np.all(acc == 0.0), (r, acc)
         else:
-            # float32 error on the scale of the unfiltered Newtonian pull m/r^2
-            np.testing.assert_allclose(acc, ref, rtol=0, atol=2e-6 / r ** 2)
+            # near r_s the filter cancels the Newtonian pull; float32 evaluation of
+            # the pair kernel is good to ~1e-5 of that pull, m / r^2
+            np.testing.assert_allclose(acc, ref, rtol=0, atol=1e-5 / r ** 2)
         rs.append(r)
     # across the periodic face, softening off, no filter
     P0 = synth.Problem.make((0, 0, 0), (L,) * 3, True, 3.0, 0.0, (0,) * 6)
-    w = synth.Workload("face", np.array([[0.4, 5, 5], [L - 0.6, 5, 5]], np.float32),
-                       np.ones(2, np.float32), 2, P0)
-    np.testing.assert_allclose(gpu_force(w), [[-1, 0, 0], [1, 0, 0]], rtol=1e-6, atol=1e-7)
+    for a, b in [(0.4, L - 0.6), (0.001, L - 2.5), (L - 0.3, 1.2), (15.9, 16.1)]:
+        w = synth.Workload("face", np.array([[a, 5, 5], [b, 5, 7]], np.float32),
+                           np.ones(2, np.float32), 2, P0)
+        announce(f"periodic face {a} {b}")
+        # no coordinate of magnitude L is rounded on the way: float32 rounding of the
+        # offsets from the cell centres only
+        np.testing.assert_allclose(gpu_force(w), oracle_force(w), rtol=1e-6, atol=0)
 
 
 def test_single_particle_and_one_cell():

@@ -115,9 +115,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="node_share")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--only", choices=["force", "vjp", "copy"],
+                    help="profiling mode: bin once, then run only this kernel --steps times "
+                         "(copy: a 1 GiB device-to-device copy of known size); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the short-range path is "
@@ -130,6 +133,14 @@ def main() -> int:
     from paper_1411_3396_amd import synth
 
     dev = "cuda:0"
+    if args.only == "copy":
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.steps} x {a.numel() * 4} bytes")
+        return 0
     t0 = time.perf_counter()
     w = synth.get(args.workload)
     g_np = synth.cotangent(w.n_active, 1)
@@ -142,6 +153,17 @@ def main() -> int:
     acc = torch.empty((w.n_active, 3), device=dev)
     grad = torch.empty((w.n, 3), device=dev)
     mws = sr.new_workspace(1 << 20, dev)
+
+    if args.only:
+        sr.bin(pos, mass, w.problem, w.n_active, ws=ws)
+        for _ in range(args.steps):
+            if args.only == "force":
+                sr.force(pos, mass, w.problem, w.n_active, ws=ws, reuse_bins=True, out=acc)
+            else:
+                sr.force_vjp(pos, mass, w.problem, g, w.n_active, ws=ws, reuse_bins=True, out=grad)
+        torch.cuda.synchronize()
+        log(f"ran {args.only} {args.steps} times")
+        return 0
 
     # useful pairs of both passes, counted once outside the timed region
     sr.bin(pos, mass, w.problem, w.n_active, ws=ws)

@@ -28,7 +28,7 @@ FLAG_OUT_OF_DOMAIN = 2
 EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "sr_bin",
            "sr_bin_view", "sr_force", "sr_force_vjp", "sr_count_pairs", "sr_momentum",
            "sr_ws_flags", "sr_batch_plan_create", "sr_batch_force", "sr_batch_plan_destroy",
-           "sr_batch_plan_info", "sr_timing_enable", "sr_timing_read")
+           "sr_batch_plan_info", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
 
 
 class SRError(RuntimeError):
@@ -76,6 +76,7 @@ def lib():
         L.sr_batch_force.argtypes = [p, p, p, p, C.c_size_t, p, p, u, p]
         L.sr_batch_plan_destroy.argtypes = [p]
         L.sr_batch_plan_info.argtypes = [p, p, C.c_size_t]
+        L.sr_launch_config.argtypes = [C.c_int, C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
         for name in EXPORTS:
@@ -348,6 +349,13 @@ def batch_force(pos, mass, offsets, problems, n_active=None, mode="graph", momen
     plan.run(pos, mass, ws, acc, mom, mode)
     plan.close()
     return (acc, mom) if momentum else acc
+
+
+def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0):
+    """Set (0 = keep) and return (waves_per_cu, targets_per_lane) of the single-problem calls."""
+    cur = (C.c_int * 2)()
+    _check(lib().sr_launch_config(int(waves_per_cu), int(targets_per_lane), cur), "sr_launch_config")
+    return int(cur[0]), int(cur[1])
 
 
 def timing_enable(on: bool = True) -> None:

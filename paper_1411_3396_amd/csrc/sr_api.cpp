@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -126,7 +127,6 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles)
     L.vals[1] = take(n4);
     L.tab = take((size_t)L.table * 4);
     L.tabx = take((size_t)(L.table + 1) * 4);
-    L.count = take((size_t)NC * 4);
     L.nact = take((size_t)NC * 4);
     L.start = take((size_t)(NC + 1) * 4);
     L.scan_tmp = take((size_t)std::max(scan_scratch_elems(L.table), scan_scratch_elems(NC)) * 4);
@@ -175,7 +175,23 @@ sr_status check_ws(const void *ws, size_t ws_bytes, const Layout &L)
     return SR_OK;
 }
 
-int g_waves_per_cu_default = 32;
+std::atomic<int> g_waves_per_cu_default{32};
+std::atomic<int> g_targets_per_lane_default{1};
+
+// Launch defaults may be overridden for experiments: SR_WAVES_PER_CU, SR_TARGETS_PER_LANE.
+struct EnvDefaults {
+    EnvDefaults()
+    {
+        if (const char *v = std::getenv("SR_WAVES_PER_CU")) {
+            const int w = std::atoi(v);
+            if (w >= 1 && w <= 64) g_waves_per_cu_default = w;
+        }
+        if (const char *v = std::getenv("SR_TARGETS_PER_LANE")) {
+            const int t = std::atoi(v);
+            if (t == 1 || t == 2) g_targets_per_lane_default = t;
+        }
+    }
+} g_env_defaults;
 
 sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *seg_host,
                       const SegParams *seg_dev, void *stream, int waves_per_cu, int64_t n_rows)
@@ -200,9 +216,10 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.seg_host = seg_host;
     a.seg_dev = seg_dev;
     a.st = static_cast<hipStream_t>(stream);
-    a.waves_per_cu = waves_per_cu > 0 ? waves_per_cu : g_waves_per_cu_default;
+    a.waves_per_cu = waves_per_cu > 0 ? waves_per_cu : g_waves_per_cu_default.load();
     a.num_cu = cus;
     a.n_rows = (int)n_rows;
+    a.targets_per_lane = g_targets_per_lane_default.load();
     return SR_OK;
 }
 
@@ -272,6 +289,7 @@ struct sr_batch_plan {
     const void *b_pos = nullptr, *b_mass = nullptr, *b_ws = nullptr, *b_acc = nullptr,
                *b_mom = nullptr;
     int waves_per_cu = 0;               // 0: not tuned yet
+    int targets_per_lane = 1;
     std::string tune_cache;
     std::string tune_key;
     double tuned_ms = -1.0;
@@ -287,6 +305,7 @@ sr_status run_batched(sr_batch_plan *P, const float *pos, const float *mass, voi
                                   static_cast<char *>(ws) + P->L.seg), st, P->waves_per_cu,
                                   P->total_active);
     if (s != SR_OK) return s;
+    a.targets_per_lane = P->targets_per_lane;
     hipError_t e = hipMemcpyAsync(static_cast<char *>(ws) + P->L.seg, P->pinned,
                                   sizeof(SegParams) * P->B, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return SR_E_DEVICE;
@@ -307,6 +326,7 @@ sr_status run_per_subvolume(sr_batch_plan *P, const float *pos, const float *mas
         DevArgs a;
         sr_status s = device_args(a, ws, &S.L, &S.seg, nullptr, st, P->waves_per_cu, P->n_active[b]);
         if (s != SR_OK) return s;
+        a.targets_per_lane = P->targets_per_lane;
         if (n > 0) {
             if (dev_bin(a, pos + 3 * off, mass + off) != hipSuccess) return SR_E_DEVICE;
             if (P->n_active[b] > 0 && dev_force(a, acc + 3 * out_off) != hipSuccess) return SR_E_DEVICE;
@@ -343,7 +363,7 @@ std::string arch_name()
 }
 
 // Minimal reader of the tune cache: one line per key, "key waves".
-bool cache_lookup(const std::string &path, const std::string &key, int &waves)
+bool cache_lookup(const std::string &path, const std::string &key, int &waves, int &tpl)
 {
     if (path.empty()) return false;
     std::ifstream in(path);
@@ -358,15 +378,18 @@ bool cache_lookup(const std::string &path, const std::string &key, int &waves)
         const size_t w = line.find("\"waves_per_cu\":", q1);
         if (w == std::string::npos) continue;
         const int v = std::atoi(line.c_str() + w + 15);
-        if (v >= 1 && v <= 64) {
+        const size_t t = line.find("\"targets_per_lane\":", q1);
+        const int tv = t == std::string::npos ? 1 : std::atoi(line.c_str() + t + 19);
+        if (v >= 1 && v <= 64 && (tv == 1 || tv == 2)) {
             waves = v;
+            tpl = tv;
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const std::string &path, const std::string &key, int waves, double ms)
+void cache_store(const std::string &path, const std::string &key, int waves, int tpl, double ms)
 {
     if (path.empty()) return;
     std::vector<std::string> keep;
@@ -386,7 +409,8 @@ void cache_store(const std::string &path, const std::string &key, int waves, dou
         }
     }
     std::ostringstream e;
-    e << "  \"" << key << "\": {\"waves_per_cu\": " << waves << ", \"ms\": " << ms << "}";
+    e << "  \"" << key << "\": {\"waves_per_cu\": " << waves << ", \"targets_per_lane\": " << tpl
+      << ", \"ms\": " << ms << "}";
     keep.push_back(e.str());
     const std::string tmp = path + ".tmp";
     {
@@ -399,43 +423,51 @@ void cache_store(const std::string &path, const std::string &key, int waves, dou
     std::rename(tmp.c_str(), path.c_str());
 }
 
-// Pick the persistent grid (waves per CU) by timing the batched sequence.
+// Pick the launch parameters (persistent grid in waves per CU, targets per
+// lane of dense forward items) by timing the batched sequence.
 sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, float *acc,
                hipStream_t st)
 {
-    int waves = 0;
-    if (cache_lookup(P->tune_cache, P->tune_key, waves)) {
+    int waves = 0, tpl = 1;
+    if (cache_lookup(P->tune_cache, P->tune_key, waves, tpl)) {
         P->waves_per_cu = waves;
+        P->targets_per_lane = tpl;
         return SR_OK;
     }
-    const int cand[] = {8, 16, 24, 32};
+    const int cand_w[] = {8, 16, 24, 32};
+    const int cand_t[] = {1, 2};
     double best = 1e300;
-    int best_w = g_waves_per_cu_default;
+    int best_w = g_waves_per_cu_default.load(), best_t = 1;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SR_E_DEVICE;
-    for (int w : cand) {
-        P->waves_per_cu = w;
-        sr_status s = run_batched(P, pos, mass, ws, acc, nullptr, st);  // warm
-        if (s != SR_OK) return s;
-        float ms = 0.f;
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < 2; ++r) {
-            s = run_batched(P, pos, mass, ws, acc, nullptr, st);
+    for (int t : cand_t) {
+        for (int w : cand_w) {
+            P->waves_per_cu = w;
+            P->targets_per_lane = t;
+            sr_status s = run_batched(P, pos, mass, ws, acc, nullptr, st);  // warm
             if (s != SR_OK) return s;
-        }
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) return SR_E_DEVICE;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-            best = ms;
-            best_w = w;
+            float ms = 0.f;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < 2; ++r) {
+                s = run_batched(P, pos, mass, ws, acc, nullptr, st);
+                if (s != SR_OK) return s;
+            }
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) return SR_E_DEVICE;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_w = w;
+                best_t = t;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     P->waves_per_cu = best_w;
+    P->targets_per_lane = best_t;
     P->tuned_ms = best / 2.0;
-    cache_store(P->tune_cache, P->tune_key, best_w, best / 2.0);
+    cache_store(P->tune_cache, P->tune_key, best_w, best_t, best / 2.0);
     return SR_OK;
 }
 
@@ -669,7 +701,7 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets, const int64_t 
         std::ostringstream k;
         int nb = 0;
         while ((int64_t(1) << (nb + 1)) <= std::max<int64_t>(1, offsets[B])) ++nb;
-        k << arch_name() << "/force-v1/B" << B << "/log2N" << nb << "/soft" << (soft ? 1 : 0);
+        k << arch_name() << "/force-v2/B" << B << "/log2N" << nb << "/soft" << (soft ? 1 : 0);
         P->tune_key = k.str();
     }
     *plan = P;
@@ -745,12 +777,26 @@ sr_status sr_batch_plan_info(const sr_batch_plan *P, char *buf, size_t buf_bytes
     std::ostringstream o;
     o << "{\"B\": " << P->B << ", \"n\": " << P->offsets[P->B] << ", \"n_active\": "
       << P->total_active << ", \"cells\": " << P->L.NC << ", \"ws_bytes\": " << P->ws_bytes
-      << ", \"waves_per_cu\": " << P->waves_per_cu << ", \"tuned_ms\": " << P->tuned_ms
+      << ", \"waves_per_cu\": " << P->waves_per_cu << ", \"targets_per_lane\": "
+      << P->targets_per_lane << ", \"tuned_ms\": " << P->tuned_ms
       << ", \"tune_key\": \"" << P->tune_key << "\", \"graph\": " << (P->exec ? "true" : "false")
       << "}";
     const std::string s = o.str();
     if (s.size() + 1 > buf_bytes) return SR_E_ARG;
     std::memcpy(buf, s.c_str(), s.size() + 1);
+    return SR_OK;
+}
+
+sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int *cur)
+{
+    if (waves_per_cu < 0 || waves_per_cu > 64 || targets_per_lane < 0 || targets_per_lane > 2)
+        return SR_E_ARG;
+    if (waves_per_cu > 0) g_waves_per_cu_default = waves_per_cu;
+    if (targets_per_lane > 0) g_targets_per_lane_default = targets_per_lane;
+    if (cur) {
+        cur[0] = g_waves_per_cu_default.load();
+        cur[1] = g_targets_per_lane_default.load();
+    }
     return SR_OK;
 }
 

@@ -75,11 +75,12 @@ struct Layout {
     int64_t item_cap = 0;   // upper bound on work items
     int64_t mom_tiles = 0;  // momentum partials
     size_t hdr = 0, seg = 0, cell_of = 0, keys[2] = {0, 0}, vals[2] = {0, 0};
-    size_t tab = 0, tabx = 0, count = 0, nact = 0, start = 0, scan_tmp = 0;
+    size_t tab = 0, tabx = 0, nact = 0, start = 0, scan_tmp = 0;
     size_t bx = 0, by = 0, bz = 0, bm = 0, out_row = 0, gx = 0, gy = 0, gz = 0;
     size_t items = 0, info = 0, mom = 0;
     size_t total = 0;
     size_t perm() const { return vals[(passes - 1) & 1]; }
+    size_t sorted_keys() const { return keys[(passes - 1) & 1]; }
     // Tag of a binned workspace for these sizes (never zero).
     uint32_t magic() const
     {
@@ -102,6 +103,7 @@ struct DevArgs {
     int waves_per_cu;
     int num_cu;
     int n_rows;  // rows of the force output (sum of n_active)
+    int targets_per_lane;  // 1 or 2 for cells with more than 64 targets (forward)
 };
 
 hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass);

@@ -249,8 +249,7 @@ hipError_t scan_i32(const int *in, int *out, int64_t m, int *tmp, hipStream_t st
 
 template <class Acc>
 __global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restrict__ pos, int N,
-                                                   int *__restrict__ cell_of, int *count,
-                                                   int *nact, uint32_t *hdr)
+                                                   int *__restrict__ cell_of, uint32_t *hdr)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
@@ -264,11 +263,20 @@ __global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restr
                              S.nc[1], S.periodic, o, fl);
     const int iz = bin_coord(pos[p + 2], S.lo[2], S.len[2], S.inv_len[2], S.h[2], S.inv_h[2],
                              S.nc[2], S.periodic, o, fl);
-    const int cell = S.cell_off + (ix * S.nc[1] + iy) * S.nc[2] + iz;
-    cell_of[i] = cell;
-    atomicAdd(&count[cell], 1);
-    if (i - S.part_off < S.n_active) atomicAdd(&nact[cell], 1);
+    cell_of[i] = S.cell_off + (ix * S.nc[1] + iy) * S.nc[2] + iz;
     if (fl) atomicOr(&hdr[kHdrFlags], fl);
+}
+
+// Cell starts from the sorted cell keys: slot b starts every cell in
+// (key[b-1], key[b]]; slot N closes the list.  Each entry is written once.
+__global__ __launch_bounds__(256) void k_cell_bounds(const int *__restrict__ key, int N, int NC,
+                                                     int *__restrict__ start)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b > N) return;
+    const int lo = (b == 0) ? -1 : key[b - 1];
+    const int hi = (b == N) ? NC : key[b];
+    for (int c = lo + 1; c <= hi; ++c) start[c] = b;
 }
 
 // --------------------------------------------------------------- A2: stable radix sort
@@ -341,12 +349,14 @@ __global__ __launch_bounds__(64) void k_radix_scatter(const int *__restrict__ ke
 
 template <class Acc>
 __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__restrict__ perm,
+                                                const int *__restrict__ key,
+                                                const int *__restrict__ start,
                                                 const float *__restrict__ pos,
                                                 const float *__restrict__ mass,
                                                 float *__restrict__ bx, float *__restrict__ by,
                                                 float *__restrict__ bz, float *__restrict__ bm,
-                                                int *__restrict__ out_row, uint32_t *hdr,
-                                                uint32_t magic)
+                                                int *__restrict__ out_row, int *__restrict__ nact,
+                                                uint32_t *hdr, uint32_t magic)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b == 0) hdr[kHdrMagic] = magic;
@@ -367,7 +377,15 @@ __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__res
     bz[b] = oz;
     bm[b] = mass[i];
     const int li = i - S.part_off;
-    out_row[b] = li < S.n_active ? S.out_off + li : -1;
+    const bool act = li < S.n_active;
+    out_row[b] = act ? S.out_off + li : -1;
+    // active particles lead their cell (input order): the last one records the count
+    if (act) {
+        const int c = key[b];
+        bool last = (b + 1 == N) || key[b + 1] != c;
+        if (!last) last = !(perm[b + 1] - S.part_off < S.n_active);
+        if (last) nact[c] = b + 1 - start[c];
+    }
 }
 
 // Cotangent rows in binned order (zero on passive particles).
@@ -397,16 +415,15 @@ __global__ __launch_bounds__(256) void k_gather_g(int N, int n_rows,
 // Per home cell: number of items and cost class (floor log2 of the pairs one
 // lane evaluates); counts items per class.
 template <class Acc, bool kActiveOnly>
-__global__ __launch_bounds__(256) void k_items_count(Acc acc, int NC, const int *__restrict__ start,
-                                                     const int *__restrict__ nact,
-                                                     uint32_t *__restrict__ info, uint32_t *hdr,
-                                                     uint32_t magic, int N)
+__device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
+                                                 const int *__restrict__ start,
+                                                 const int *__restrict__ nact,
+                                                 uint32_t *__restrict__ info, uint32_t *blk,
+                                                 bool ok, int N, bool two)
 {
-    const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= NC) return;
-    if (hdr[kHdrMagic] != magic) {
+    if (!ok) {
         info[c] = 0;
-        if (c == 0) atomicOr(&hdr[kHdrFlags], (uint32_t)SR_FLAG_NOT_BINNED);
         return;
     }
     const int nt = kActiveOnly ? nact[c] : (start[c + 1] - start[c]);
@@ -442,12 +459,33 @@ __global__ __launch_bounds__(256) void k_items_count(Acc acc, int NC, const int 
         }
     }
     const int lk = nt >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / nt));
-    const int n_items = nt >= kTargetsPerItem ? (nt + kTargetsPerItem - 1) / kTargetsPerItem : 1;
-    int64_t cost = (src + (1 << lk) - 1) >> lk;
+    const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
+    const int n_items = (nt + chunk - 1) / chunk;
+    int64_t cost = ((src + (1 << lk) - 1) >> lk) * (chunk / kTargetsPerItem);
     if (cost < 1) cost = 1;
-    const int cls = 63 - __clzll((unsigned long long)cost);
-    info[c] = ((uint32_t)n_items << 5) | (uint32_t)(cls > 31 ? 31 : cls);
-    atomicAdd(&hdr[kHdrBucketCount + (cls > 31 ? 31 : cls)], (uint32_t)n_items);
+    int cls = 63 - __clzll((unsigned long long)cost);
+    cls = cls > 31 ? 31 : cls;
+    info[c] = ((uint32_t)n_items << 5) | (uint32_t)cls;
+    // per-block class totals, one global atomic per class and block
+    atomicAdd(&blk[cls], (uint32_t)n_items);
+}
+
+template <class Acc, bool kActiveOnly>
+__global__ __launch_bounds__(256) void k_items_count(Acc acc, int NC, const int *__restrict__ start,
+                                                     const int *__restrict__ nact,
+                                                     uint32_t *__restrict__ info, uint32_t *hdr,
+                                                     uint32_t magic, int N, int two)
+{
+    __shared__ uint32_t blk[kClasses];
+    if (threadIdx.x < kClasses) blk[threadIdx.x] = 0;
+    __syncthreads();
+    const bool ok = hdr[kHdrMagic] == magic;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (!ok && c == 0) atomicOr(&hdr[kHdrFlags], (uint32_t)SR_FLAG_NOT_BINNED);
+    items_count_cell<Acc, kActiveOnly>(acc, c, NC, start, nact, info, blk, ok, N, two != 0);
+    __syncthreads();
+    if (threadIdx.x < kClasses && blk[threadIdx.x])
+        atomicAdd(&hdr[kHdrBucketCount + threadIdx.x], blk[threadIdx.x]);
 }
 
 // Class bases, heaviest class first; resets cursors and queue counters.
@@ -469,23 +507,36 @@ template <class Acc, bool kActiveOnly>
 __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int *__restrict__ start,
                                                      const int *__restrict__ nact,
                                                      const uint32_t *__restrict__ info,
-                                                     uint32_t *hdr, int4 *__restrict__ items)
+                                                     uint32_t *hdr, int4 *__restrict__ items,
+                                                     int two)
 {
+    __shared__ uint32_t cnt[kClasses];
+    __shared__ uint32_t base[kClasses];
+    if (threadIdx.x < kClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
     const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= NC) return;
-    const uint32_t inf = info[c];
-    if (inf == 0) return;
+    const uint32_t inf = c < NC ? info[c] : 0u;
     const int n_items = (int)(inf >> 5);
     const int cls = (int)(inf & 31);
+    uint32_t local = 0;
+    if (inf) local = atomicAdd(&cnt[cls], (uint32_t)n_items);
+    __syncthreads();
+    if (threadIdx.x < kClasses && cnt[threadIdx.x])
+        base[threadIdx.x] = hdr[kHdrBucketBase + threadIdx.x] +
+                            atomicAdd(&hdr[kHdrBucketCursor + threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (!inf) return;
     const int nt = kActiveOnly ? nact[c] : (start[c + 1] - start[c]);
     const int lk = nt >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / nt));
     const int seg = acc.seg_of_cell(c);
-    const uint32_t at = hdr[kHdrBucketBase + cls] + atomicAdd(&hdr[kHdrBucketCursor + cls], (uint32_t)n_items);
+    const uint32_t at = base[cls] + local;
     const int s0 = start[c];
+    const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
     for (int k = 0; k < n_items; ++k) {
-        const int t0 = k * kTargetsPerItem;
-        const int cnt = min(kTargetsPerItem, nt - t0);
-        items[at + k] = make_int4(c, s0 + t0, cnt, lk | (seg << 4));
+        const int t0 = k * chunk;
+        const int cn = min(chunk, nt - t0);
+        const int tw = cn > kTargetsPerItem ? 1 : 0;
+        items[at + k] = make_int4(c, s0 + t0, cn, lk | (tw << 4) | (seg << 5));
     }
 }
 
@@ -527,7 +578,7 @@ __device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
         if (lane >= d) incl += y;
     }
     st.excl = incl - cnt;
-    st.total = __shfl(incl, 26);
+    st.total = __builtin_amdgcn_readfirstlane(__shfl(incl, 26));
 }
 
 // Source v of the stencil's virtual concatenation: binned slot and shift.
@@ -579,6 +630,20 @@ __device__ __forceinline__ int64_t next_item(uint32_t *hdr, int q, int lane)
     return ((int64_t)(c / kQueueBlock) * kQueues + q) * kQueueBlock + (c % kQueueBlock);
 }
 
+// Work item: x = home cell, y = first target slot, z = targets, w = lk | two << 4 |
+// seg << 5 (lk: log2 lanes per target; two: two targets per lane).
+__device__ __forceinline__ int item_lk(int w) { return w & 15; }
+__device__ __forceinline__ bool item_two(int w) { return (w >> 4) & 1; }
+__device__ __forceinline__ int item_seg(int w) { return w >> 5; }
+
+// Work item with every field wave-uniform (scalar registers).
+__device__ __forceinline__ int4 load_item(const int4 *__restrict__ items, int64_t g)
+{
+    const int4 it = items[g];
+    return make_int4(__builtin_amdgcn_readfirstlane(it.x), __builtin_amdgcn_readfirstlane(it.y),
+                     __builtin_amdgcn_readfirstlane(it.z), __builtin_amdgcn_readfirstlane(it.w));
+}
+
 __device__ __forceinline__ float horner5(const float *q, float t)
 {
     float p = fmaf(q[5], t, q[4]);
@@ -594,6 +659,102 @@ __device__ __forceinline__ float horner4(const float *q, float t)
     p = fmaf(p, t, q[2]);
     p = fmaf(p, t, q[1]);
     return fmaf(p, t, q[0]);
+}
+
+// One forward pair term: acc += m_j d f_SR(s) for t = s + eps^2 < tc2.
+template <bool kSoft>
+__device__ __forceinline__ void force_pair(const float4 s, float px, float py, float pz, float eps2,
+                                           float tc2, const float *cq, float &ax, float &ay,
+                                           float &az)
+{
+    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    const float qi = __builtin_amdgcn_rsqf(tt);
+    const float q2 = qi * qi;
+    const float f = fmaf(q2, qi, -horner5(cq, tt));
+    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
+    const float w = in ? s.w * f : 0.f;
+    ax = fmaf(w, dx, ax);
+    ay = fmaf(w, dy, ay);
+    az = fmaf(w, dz, az);
+}
+
+// One adjoint pair term: r += f u + 2 f' (u.d) d, u = m_k g_j - m_j g_k.
+template <bool kSoft>
+__device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float px, float py,
+                                         float pz, float mk, float gkx, float gky, float gkz,
+                                         float eps2, float tc2, const float *cq, const float *cd,
+                                         float &rx, float &ry, float &rz)
+{
+    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    const float qi = __builtin_amdgcn_rsqf(tt);
+    const float q2 = qi * qi;
+    const float q3 = q2 * qi;
+    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
+    const float f = in ? q3 - horner5(cq, tt) : 0.f;
+    const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
+    const float ux = fmaf(mk, gj.x, -s.w * gkx);
+    const float uy = fmaf(mk, gj.y, -s.w * gky);
+    const float uz = fmaf(mk, gj.z, -s.w * gkz);
+    const float c = fp2 * fmaf(ux, dx, fmaf(uy, dy, uz * dz));
+    rx = fmaf(c, dx, fmaf(f, ux, rx));
+    ry = fmaf(c, dy, fmaf(f, uy, ry));
+    rz = fmaf(c, dz, fmaf(f, uz, rz));
+}
+
+// Dense item with two targets per lane (t0 + lane and t0 + 64 + lane): every
+// source read from LDS feeds two pair terms, halving LDS traffic per pair.
+template <bool kSoft>
+__device__ __forceinline__ void store_acc(const int *__restrict__ out_row, float *__restrict__ out,
+                                          int n_out, int b, float ax, float ay, float az)
+{
+    const int r = out_row[b];
+    if (r >= 0 && r < n_out) {
+        const int64_t o3 = 3 * (int64_t)r;
+        out[o3] = ax;
+        out[o3 + 1] = ay;
+        out[o3 + 2] = az;
+    }
+}
+
+template <bool kSoft>
+__device__ __forceinline__ void force_item_two(const Stencil &st, const Src &src, int t0, int nt,
+                                               int lane, float eps2, float tc2, const float *cq,
+                                               const int *__restrict__ out_row,
+                                               float *__restrict__ out, int n_out, float4 *stage)
+{
+    const bool va = lane < nt, vb = kWave + lane < nt;
+    float pax = 0.f, pay = 0.f, paz = 0.f, pbx = 0.f, pby = 0.f, pbz = 0.f;
+    if (va) {
+        pax = src.x[t0 + lane];
+        pay = src.y[t0 + lane];
+        paz = src.z[t0 + lane];
+    }
+    if (vb) {
+        pbx = src.x[t0 + kWave + lane];
+        pby = src.y[t0 + kWave + lane];
+        pbz = src.z[t0 + kWave + lane];
+    }
+    float aax = 0.f, aay = 0.f, aaz = 0.f, abx = 0.f, aby = 0.f, abz = 0.f;
+    float4 nxt = fetch_pos(st, lane, src);
+    for (int base = 0; base < st.total; base += kWave) {
+        __syncthreads();
+        stage[lane] = nxt;
+        __syncthreads();
+        if (base + kWave < st.total) nxt = fetch_pos(st, base + kWave + lane, src);
+        const int n4 = (min(kWave, st.total - base) + 3) >> 2;
+        for (int u = 0; u < n4; ++u) {
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const float4 sj = stage[4 * u + q4];
+                force_pair<kSoft>(sj, pax, pay, paz, eps2, tc2, cq, aax, aay, aaz);
+                force_pair<kSoft>(sj, pbx, pby, pbz, eps2, tc2, cq, abx, aby, abz);
+            }
+        }
+    }
+    if (va) store_acc<kSoft>(out_row, out, n_out, t0 + lane, aax, aay, aaz);
+    if (vb) store_acc<kSoft>(out_row, out, n_out, t0 + kWave + lane, abx, aby, abz);
 }
 
 // Forward: acc[out_row] = sum over the stencil of m_j d f_SR.
@@ -612,15 +773,20 @@ __global__ __launch_bounds__(64) void k_force(Acc acc, const int4 *__restrict__ 
         for (;;) {
             const int64_t g = next_item(hdr, q, lane);
             if (g >= n_items) break;
-            const int4 it = items[g];
-            const int t0 = it.y, nt = it.z, lk = it.w & 15;
-            const SegParams &S = acc.get(it.w >> 4);
+            const int4 it = load_item(items, g);
+            const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
+            const SegParams &S = acc.get(item_seg(it.w));
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
             float cq[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
             Stencil st;
             stencil_setup(S, it.x, start, lane, st);
+            if (item_two(it.w)) {
+                force_item_two<kSoft>(st, src, t0, nt, lane, eps2, tc2, cq, out_row, out, n_out,
+                                      stage);
+                continue;
+            }
             const int kl = 1 << lk;
             const int t = lane >> lk, sub = lane & (kl - 1);
             const bool tv = t < nt;
@@ -638,20 +804,20 @@ __global__ __launch_bounds__(64) void k_force(Acc acc, const int4 *__restrict__ 
                 __syncthreads();
                 if (base + kWave < st.total) nxt = fetch_pos(st, base + kWave + lane, src);
                 const int cnt = min(kWave, st.total - base);
-                const int niter = (cnt + kl - 1) >> lk;
-#pragma unroll 4
-                for (int i = 0; i < niter; ++i) {
-                    const float4 s = stage[sub + (i << lk)];
-                    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
-                    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                    const float qi = __builtin_amdgcn_rsqf(tt);
-                    const float q2 = qi * qi;
-                    const float f = fmaf(q2, qi, -horner5(cq, tt));
-                    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-                    const float w = in ? s.w * f : 0.f;
-                    ax = fmaf(w, dx, ax);
-                    ay = fmaf(w, dy, ay);
-                    az = fmaf(w, dz, az);
+                if (lk == 0) {
+                    // one lane per target: every lane reads the same source (LDS
+                    // broadcast); groups of 8, the padding after cnt is masked
+                    const int n8 = (cnt + 7) >> 3;
+                    for (int u = 0; u < n8; ++u) {
+#pragma unroll
+                        for (int q8 = 0; q8 < 8; ++q8)
+                            force_pair<kSoft>(stage[8 * u + q8], px, py, pz, eps2, tc2, cq, ax, ay, az);
+                    }
+                } else {
+                    const int niter = (cnt + kl - 1) >> lk;
+#pragma unroll 2
+                    for (int i = 0; i < niter; ++i)
+                        force_pair<kSoft>(stage[sub + (i << lk)], px, py, pz, eps2, tc2, cq, ax, ay, az);
                 }
             }
             for (int o = 1; o < kl; o <<= 1) {
@@ -693,9 +859,9 @@ __global__ __launch_bounds__(64) void k_vjp(Acc acc, const int4 *__restrict__ it
         for (;;) {
             const int64_t g = next_item(hdr, q, lane);
             if (g >= n_items) break;
-            const int4 it = items[g];
-            const int t0 = it.y, nt = it.z, lk = it.w & 15;
-            const SegParams &S = acc.get(it.w >> 4);
+            const int4 it = load_item(items, g);
+            const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
+            const SegParams &S = acc.get(item_seg(it.w));
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
             float cq[6], cd[5];
 #pragma unroll
@@ -748,27 +914,21 @@ __global__ __launch_bounds__(64) void k_vjp(Acc acc, const int4 *__restrict__ it
                     }
                 }
                 const int cnt = min(kWave, st.total - base);
-                const int niter = (cnt + kl - 1) >> lk;
-#pragma unroll 2
-                for (int i = 0; i < niter; ++i) {
-                    const int e = sub + (i << lk);
-                    const float4 s = stage_p[e];
-                    const float4 gj = stage_g[e];
-                    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
-                    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                    const float qi = __builtin_amdgcn_rsqf(tt);
-                    const float q2 = qi * qi;
-                    const float q3 = q2 * qi;
-                    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-                    const float f = in ? q3 - horner5(cq, tt) : 0.f;
-                    const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
-                    const float ux = fmaf(mk, gj.x, -s.w * gkx);
-                    const float uy = fmaf(mk, gj.y, -s.w * gky);
-                    const float uz = fmaf(mk, gj.z, -s.w * gkz);
-                    const float c = fp2 * fmaf(ux, dx, fmaf(uy, dy, uz * dz));
-                    rx = fmaf(c, dx, fmaf(f, ux, rx));
-                    ry = fmaf(c, dy, fmaf(f, uy, ry));
-                    rz = fmaf(c, dz, fmaf(f, uz, rz));
+                if (lk == 0) {
+                    const int n4 = (cnt + 3) >> 2;
+                    for (int u = 0; u < n4; ++u) {
+#pragma unroll
+                        for (int q4 = 0; q4 < 4; ++q4)
+                            vjp_pair<kSoft>(stage_p[4 * u + q4], stage_g[4 * u + q4], px, py, pz, mk,
+                                            gkx, gky, gkz, eps2, tc2, cq, cd, rx, ry, rz);
+                    }
+                } else {
+                    const int niter = (cnt + kl - 1) >> lk;
+                    for (int i = 0; i < niter; ++i) {
+                        const int e = sub + (i << lk);
+                        vjp_pair<kSoft>(stage_p[e], stage_g[e], px, py, pz, mk, gkx, gky, gkz, eps2,
+                                        tc2, cq, cd, rx, ry, rz);
+                    }
                 }
             }
             for (int o = 1; o < kl; o <<= 1) {
@@ -804,9 +964,9 @@ __global__ __launch_bounds__(64) void k_count(Acc acc, const int4 *__restrict__ 
         for (;;) {
             const int64_t g = next_item(hdr, q, lane);
             if (g >= n_items) break;
-            const int4 it = items[g];
-            const int t0 = it.y, nt = it.z, lk = it.w & 15;
-            const SegParams &S = acc.get(it.w >> 4);
+            const int4 it = load_item(items, g);
+            const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
+            const SegParams &S = acc.get(item_seg(it.w));
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
             Stencil st;
             stencil_setup(S, it.x, start, lane, st);
@@ -833,7 +993,7 @@ __global__ __launch_bounds__(64) void k_count(Acc acc, const int4 *__restrict__ 
                     const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
                     const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
                     const float s2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    cnt_lane += (tt < tc2 && s2 > 0.f && s.w == s.w) ? 1u : 0u;
+                    cnt_lane += (tt < tc2 && s2 > 0.f) ? 1u : 0u;
                 }
             }
             if (tv) pairs += cnt_lane;
@@ -930,7 +1090,7 @@ bool all_softened(const DevArgs &a)
 }
 
 template <bool kActiveOnly>
-hipError_t build_items(const DevArgs &a)
+hipError_t build_items(const DevArgs &a, int two)
 {
     const Layout &L = *a.L;
     uint32_t *hdr = at<uint32_t>(a, L.hdr);
@@ -940,11 +1100,11 @@ hipError_t build_items(const DevArgs &a)
         const unsigned nb = blocks_for(L.NC, 256);
         k_items_count<decltype(acc), kActiveOnly><<<nb, 256, 0, a.st>>>(
             acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact), at<uint32_t>(a, L.info), hdr,
-            L.magic(), (int)L.N);
+            L.magic(), (int)L.N, two);
         k_items_base<<<1, 64, 0, a.st>>>(hdr, L.magic());
         k_items_write<decltype(acc), kActiveOnly><<<nb, 256, 0, a.st>>>(
             acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact), at<uint32_t>(a, L.info), hdr,
-            at<int4>(a, L.items));
+            at<int4>(a, L.items), two);
         return hipGetLastError();
     });
 }
@@ -983,12 +1143,10 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
     const Layout &L = *a.L;
     hipError_t e;
     if ((e = fill_u32(at<uint32_t>(a, L.hdr), kHdrWords, 0, a.st)) != hipSuccess) return e;
-    if ((e = fill_u32(at<uint32_t>(a, L.count), L.NC, 0, a.st)) != hipSuccess) return e;
     if ((e = fill_u32(at<uint32_t>(a, L.nact), L.NC, 0, a.st)) != hipSuccess) return e;
-    if (L.N == 0) return scan_i32(at<int>(a, L.count), at<int>(a, L.start), L.NC, at<int>(a, L.scan_tmp), a.st);
+    if (L.N == 0) return hipSuccess;
     e = with_acc(a, [&](auto acc) -> hipError_t {
         k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, (int)L.N, at<int>(a, L.cell_of),
-                                                             at<int>(a, L.count), at<int>(a, L.nact),
                                                              at<uint32_t>(a, L.hdr));
         return hipGetLastError();
     });
@@ -1006,21 +1164,21 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
         if ((e = scan_i32(at<int>(a, L.tab), at<int>(a, L.tabx), (int64_t)R * L.ntiles,
                           at<int>(a, L.scan_tmp), a.st)) != hipSuccess)
             return e;
-        k_radix_scatter<<<(unsigned)L.ntiles, 64, 0, a.st>>>(
-            kin, vin, (int)L.N, shift, L.digit_bits, at<int>(a, L.tabx), (int)L.ntiles,
-            p == L.passes - 1 ? nullptr : kout, vout);
+        k_radix_scatter<<<(unsigned)L.ntiles, 64, 0, a.st>>>(kin, vin, (int)L.N, shift, L.digit_bits,
+                                                             at<int>(a, L.tabx), (int)L.ntiles, kout,
+                                                             vout);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         kin = kout;
         vin = vout;
     }
-    if ((e = scan_i32(at<int>(a, L.count), at<int>(a, L.start), L.NC, at<int>(a, L.scan_tmp), a.st)) !=
-        hipSuccess)
-        return e;
+    k_cell_bounds<<<blocks_for(L.N + 1, 256), 256, 0, a.st>>>(at<int>(a, L.sorted_keys()), (int)L.N,
+                                                              (int)L.NC, at<int>(a, L.start));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     return with_acc(a, [&](auto acc) -> hipError_t {
         k_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
-            acc, (int)L.N, at<int>(a, L.perm()), pos, mass, at<float>(a, L.bx), at<float>(a, L.by),
-            at<float>(a, L.bz), at<float>(a, L.bm), at<int>(a, L.out_row), at<uint32_t>(a, L.hdr),
-            L.magic());
+            acc, (int)L.N, at<int>(a, L.perm()), at<int>(a, L.sorted_keys()), at<int>(a, L.start), pos,
+            mass, at<float>(a, L.bx), at<float>(a, L.by), at<float>(a, L.bz), at<float>(a, L.bm),
+            at<int>(a, L.out_row), at<int>(a, L.nact), at<uint32_t>(a, L.hdr), L.magic());
         return hipGetLastError();
     });
 }
@@ -1028,7 +1186,7 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
 hipError_t dev_force(const DevArgs &a, float *acc_out)
 {
     const Layout &L = *a.L;
-    hipError_t e = build_items<true>(a);
+    hipError_t e = build_items<true>(a, a.targets_per_lane >= 2 ? 1 : 0);
     if (e != hipSuccess) return e;
     const bool soft = all_softened(a);
     return with_acc(a, [&](auto acc) -> hipError_t {
@@ -1056,7 +1214,7 @@ hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad)
                                                       at<float>(a, L.gz));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = build_items<false>(a)) != hipSuccess) return e;
+    if ((e = build_items<false>(a, 0)) != hipSuccess) return e;
     const bool soft = all_softened(a);
     return with_acc(a, [&](auto acc) -> hipError_t {
         void *tok = nullptr;
@@ -1085,7 +1243,7 @@ __global__ void k_copy_pairs(const uint32_t *hdr, int64_t *out)
 hipError_t dev_count_pairs(const DevArgs &a, int64_t *pairs)
 {
     const Layout &L = *a.L;
-    hipError_t e = build_items<true>(a);
+    hipError_t e = build_items<true>(a, 0);
     if (e != hipSuccess) return e;
     if ((e = fill_u32(at<uint32_t>(a, L.hdr) + kHdrPairs, 2, 0, a.st)) != hipSuccess) return e;
     e = with_acc(a, [&](auto acc) -> hipError_t {

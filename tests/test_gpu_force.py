@@ -158,3 +158,23 @@ def test_momentum_check_float64():
     np.testing.assert_allclose(mom, ref, rtol=1e-9, atol=1e-9 * np.sum(np.abs(a)))
     # Newton's third law for a periodic all-active box, up to float32 force errors
     assert np.linalg.norm(mom) <= 1e-6 * np.sum(w.mass[:, None] * np.abs(a))
+
+
+def test_launch_configs_agree_bitwise():
+    # the grid size and the two-targets-per-lane items change scheduling only:
+    # every target sums its sources in the same order, so results are bitwise equal
+    w = synth.clustered_box(150000, 36.0, 30, 3, halo_frac=0.7, mass_range=(1e3, 1e5))
+    w.mass = np.random.default_rng(2).uniform(0.5, 2.0, w.n).astype(np.float32)
+    saved = sr.launch_config()
+    ref = None
+    try:
+        for waves, tpl in [(32, 1), (8, 2), (16, 2), (24, 1)]:
+            sr.launch_config(waves, tpl)
+            announce(f"launch config waves={waves} targets_per_lane={tpl}")
+            a = gpu_force(w)
+            if ref is None:
+                ref = a
+                assert_force_close(a, oracle_force(w), what="dense cells")
+            assert np.array_equal(a.view(np.uint32), ref.view(np.uint32)), (waves, tpl)
+    finally:
+        sr.launch_config(*saved)

@@ -1,0 +1,144 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times, on sampled outputs the oracle computes one by one (its target-subset
+mode): the 2M and 16M clustered boxes, the 96-subvolume batch and the
+34.6M-particle node share with its ghost shell."""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial import cKDTree
+
+import oracle
+import paper_1411_3396_amd as sr
+from paper_1411_3396_amd import synth
+from gpu_helpers import DEV, FWD_TOL, VJP_TOL, announce, assert_force_close, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_clustered_2m_forward_sampled():
+    w = synth.clustered_2m()
+    announce(f"clustered_2m n={w.n}")
+    acc = sr.force(to_dev(w.pos), to_dev(w.mass), w.problem).cpu().numpy()
+    idx = synth.sample_indices(w.n_active, 20000, 2)
+    ref, _ = oracle.force(w.pos, w.mass, w.n_active, w.problem, targets=idx)
+    assert_force_close(acc[idx], ref, what="clustered_2m")
+
+
+def test_clustered_16m_forward_and_adjoint():
+    w = synth.clustered_16m()
+    g = synth.cotangent(w.n_active, 1)
+    idx = synth.sample_indices(w.n, 4096, 2)
+    announce(f"clustered_16m n={w.n}")
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    ws = sr.bin(pos, mass, w.problem)
+    acc = sr.force(pos, mass, w.problem, ws=ws, reuse_bins=True).cpu().numpy()
+    grad = sr.force_vjp(pos, mass, w.problem, to_dev(g), ws=ws, reuse_bins=True).cpu().numpy()
+    ref, _ = oracle.force(w.pos, w.mass, w.n_active, w.problem, targets=idx)
+    assert_force_close(acc[idx], ref, what="clustered_16m forward")
+    gref = oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g, targets=idx)
+    err = oracle.rms_rel(grad[idx], gref)
+    print(f"  clustered_16m adjoint rms_rel={err:.3e}", flush=True)
+    assert err <= VJP_TOL
+
+
+def _local_loss_grad(x, m, g, n_active, P, k, nbr, h):
+    """d/dx_k of sum_{i in targets} g_i . a_i on the subproblem around k (float64 FD)."""
+    L = np.array(P.len, np.float64)
+    d = x[nbr] - x[k]
+    d -= L * np.round(d / L)
+    r = np.sqrt(np.sum(d * d, axis=1))
+    near = nbr[r < P.r_s + 2 * h]
+    act = near[near < n_active]
+    order = np.concatenate([act, np.setdiff1d(nbr, act)])
+    dl = x[order] - x[k]
+    dl -= L * np.round(dl / L)
+    xl = dl + 100.0
+    lp = synth.Problem.make((0, 0, 0), (200.0,) * 3, False, P.r_s, P.eps, P.poly)
+    kk = int(np.nonzero(order == k)[0][0])
+    out = np.zeros(3)
+    for a in range(3):
+        xp = xl.copy()
+        xp[kk, a] += h
+        xm = xl.copy()
+        xm[kk, a] -= h
+        ap, _ = oracle.force(xp, m[order], len(act), lp)
+        am, _ = oracle.force(xm, m[order], len(act), lp)
+        out[a] = np.sum(g[act] * (ap - am)) / (2 * h)
+    return out, r[(r > 0) & (r < P.r_s + 4 * h)]
+
+
+def test_clustered_16m_adjoint_finite_differences():
+    # central differences, h = 1e-3 in float64, on particles of the 4096 subset
+    # (Richardson-extrapolated with h/2); coordinates whose step would move a pair
+    # across r_s are skipped
+    w = synth.clustered_16m()
+    g = synth.cotangent(w.n_active, 1)
+    idx = synth.sample_indices(w.n, 4096, 2)[:512]
+    announce("clustered_16m finite differences")
+    grad = sr.force_vjp(to_dev(w.pos), to_dev(w.mass), w.problem, to_dev(g)).cpu().numpy()
+    x = w.pos.astype(np.float64)
+    m = w.mass.astype(np.float64)
+    gg = g.astype(np.float64)
+    tree = cKDTree(np.mod(x, 256.0), boxsize=256.0)
+    nbrs = tree.query_ball_point(np.mod(x[idx], 256.0), 2 * w.problem.r_s + 0.01)
+    fd, keep = [], []
+    h = 1e-3
+    for q, k in enumerate(idx):
+        nb = np.array(sorted(nbrs[q]), np.int64)
+        f1, rr = _local_loss_grad(x, m, gg, w.n_active, w.problem, int(k), nb, h)
+        if np.any(np.abs(rr - w.problem.r_s) < 2 * h):
+            continue
+        f2, _ = _local_loss_grad(x, m, gg, w.n_active, w.problem, int(k), nb, h / 2)
+        fd.append((4 * f2 - f1) / 3)
+        keep.append(q)
+    err = oracle.rms_rel(grad[idx[keep]], np.array(fd))
+    print(f"  fd points={len(keep)} rms_rel={err:.3e}", flush=True)
+    assert len(keep) >= 200 and err <= VJP_TOL
+
+
+def test_node_share_forward_and_adjoint_sampled():
+    w = synth.node_share()
+    announce(f"node_share n={w.n} n_active={w.n_active}")
+    g = synth.cotangent(w.n_active, 1)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    ws = sr.bin(pos, mass, w.problem, w.n_active)
+    assert sr.ws_flags(ws) == 0
+    acc = sr.force(pos, mass, w.problem, w.n_active, ws=ws, reuse_bins=True).cpu().numpy()
+    grad = sr.force_vjp(pos, mass, w.problem, to_dev(g), w.n_active, ws=ws,
+                        reuse_bins=True).cpu().numpy()
+    idx = synth.sample_indices(w.n_active, 100000, 2)
+    ref, _ = oracle.force(w.pos, w.mass, w.n_active, w.problem, targets=idx)
+    assert_force_close(acc[idx], ref, what="node_share forward (1e5 sample)")
+    gidx = np.concatenate([idx[:15000], synth.sample_indices(w.n - w.n_active, 5000, 3) + w.n_active])
+    gref = oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g, targets=gidx)
+    err = oracle.rms_rel(grad[gidx], gref)
+    print(f"  node_share adjoint rms_rel={err:.3e}", flush=True)
+    assert err <= VJP_TOL
+
+
+def test_subvolumes_96_batched_sampled():
+    b = synth.subvolumes_96()
+    announce(f"subvolumes_96 n={int(b.offsets[-1])}")
+    plan = sr.BatchPlan(b.offsets, b.n_active, b.problems)
+    ws = sr.new_workspace(plan.ws_bytes, DEV)
+    acc = torch.empty((plan.total_active, 3), device=DEV)
+    mom = torch.empty((plan.B, 3), dtype=torch.float64, device=DEV)
+    plan.run(to_dev(b.pos), to_dev(b.mass), ws, acc, mom, "graph")
+    a = acc.cpu().numpy()
+    mo = mom.cpu().numpy()
+    got, ref = [], []
+    row = 0
+    for k in range(b.size):
+        part = b.part(k)
+        rows = a[row: row + part.n_active]
+        idx = synth.sample_indices(part.n_active, 64, 100 + k)
+        r, _ = oracle.force(part.pos, part.mass, part.n_active, part.problem, targets=idx)
+        got.append(rows[idx])
+        ref.append(r)
+        mref = np.sum(part.mass[:, None].astype(np.float64) * rows, axis=0)
+        np.testing.assert_allclose(mo[k], mref, rtol=1e-9, atol=1e-9 * np.abs(rows).sum())
+        # Newton's third law per periodic subvolume, up to float32 force errors
+        assert np.linalg.norm(mo[k]) <= 1e-6 * np.abs(rows).sum()
+        row += part.n_active
+    assert_force_close(np.concatenate(got), np.concatenate(ref), what="subvolumes_96 (64 per subvolume)")
+    plan.close()

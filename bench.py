@@ -118,6 +118,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time the pair kernels under every launch configuration "
+                         "(waves per CU, targets per lane, occupancy variant); one JSON line each")
     ap.add_argument("--only", choices=["force", "vjp", "copy"],
                     help="profiling mode: bin once, then run only this kernel --steps times "
                          "(copy: a 1 GiB device-to-device copy of known size); prints no JSON")
@@ -163,6 +166,31 @@ def main() -> int:
                 sr.force_vjp(pos, mass, w.problem, g, w.n_active, ws=ws, reuse_bins=True, out=grad)
         torch.cuda.synchronize()
         log(f"ran {args.only} {args.steps} times")
+        return 0
+
+    if args.sweep:
+        sr.bin(pos, mass, w.problem, w.n_active, ws=ws)
+        saved = sr.launch_config()
+        for waves in (16, 24, 32):
+            for tpl in (1, 2):
+                for occ in (0, 6, 8):
+                    sr.launch_config(waves, tpl, occ)
+                    for _ in range(args.warmup):
+                        sr.force(pos, mass, w.problem, w.n_active, ws=ws, reuse_bins=True, out=acc)
+                        sr.force_vjp(pos, mass, w.problem, g, w.n_active, ws=ws, reuse_bins=True, out=grad)
+                    torch.cuda.synchronize()
+                    sr.timing_enable(True)
+                    for _ in range(args.steps):
+                        sr.force(pos, mass, w.problem, w.n_active, ws=ws, reuse_bins=True, out=acc)
+                        sr.force_vjp(pos, mass, w.problem, g, w.n_active, ws=ws, reuse_bins=True, out=grad)
+                    torch.cuda.synchronize()
+                    f_ms, f_n = sr.timing_read("force")
+                    v_ms, v_n = sr.timing_read("vjp")
+                    sr.timing_enable(False)
+                    print(json.dumps({"waves_per_cu": waves, "targets_per_lane": tpl, "occupancy": occ,
+                                      "force_ms": round(f_ms / f_n, 3), "vjp_ms": round(v_ms / v_n, 3)}),
+                          flush=True)
+        sr.launch_config(*saved)
         return 0
 
     # useful pairs of both passes, counted once outside the timed region

@@ -201,13 +201,18 @@ sr_status sr_batch_plan_destroy(sr_batch_plan *plan);
 sr_status sr_batch_plan_info(const sr_batch_plan *plan, char *buf /*host*/, size_t buf_bytes);
 
 /* Host only.  Process-wide launch parameters of the single-problem entry
- * points (batch plans tune their own): waves_per_cu sets the persistent
- * grid of the pair kernels to waves_per_cu waves per compute unit (1..64);
- * targets_per_lane (1 or 2) lets a forward wave hold two targets per lane in
- * cells with more than 64 active particles.  A 0 keeps the current value.
- * The values in effect are written to *cur (host, nullable, int[2]).
- * Initial values come from SR_WAVES_PER_CU / SR_TARGETS_PER_LANE if set. */
-sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int *cur /*host out*/);
+ * points (batch plans tune their own):
+ *   waves_per_cu      persistent grid of the pair kernels, in waves per compute
+ *                     unit (1..64; 0 keeps the current value);
+ *   targets_per_lane  1 or 2: with 2, a wave holds two targets per lane in cells
+ *                     with more than 64 targets (0 keeps the current value);
+ *   occupancy         register-allocation variant of the pair kernels: 0 (none),
+ *                     6 or 8 waves per SIMD (-1 keeps the current value).
+ * None of them changes results: every target sums its sources in the same
+ * order.  The values in effect are written to cur (host, nullable, int[3]).
+ * Initial values come from SR_WAVES_PER_CU / SR_TARGETS_PER_LANE / SR_OCCUPANCY. */
+sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy,
+                           int *cur /*host out*/);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * launch of the pair kernels ("force", "vjp").  sr_timing_enable(1) clears

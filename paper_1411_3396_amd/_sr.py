@@ -76,7 +76,7 @@ def lib():
         L.sr_batch_force.argtypes = [p, p, p, p, C.c_size_t, p, p, u, p]
         L.sr_batch_plan_destroy.argtypes = [p]
         L.sr_batch_plan_info.argtypes = [p, p, C.c_size_t]
-        L.sr_launch_config.argtypes = [C.c_int, C.c_int, p]
+        L.sr_launch_config.argtypes = [C.c_int, C.c_int, C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
         for name in EXPORTS:
@@ -351,11 +351,14 @@ def batch_force(pos, mass, offsets, problems, n_active=None, mode="graph", momen
     return (acc, mom) if momentum else acc
 
 
-def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0):
-    """Set (0 = keep) and return (waves_per_cu, targets_per_lane) of the single-problem calls."""
-    cur = (C.c_int * 2)()
-    _check(lib().sr_launch_config(int(waves_per_cu), int(targets_per_lane), cur), "sr_launch_config")
-    return int(cur[0]), int(cur[1])
+def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: int = -1):
+    """Set and return (waves_per_cu, targets_per_lane, occupancy) of the single-problem calls.
+
+    0 keeps waves_per_cu / targets_per_lane, -1 keeps occupancy."""
+    cur = (C.c_int * 3)()
+    _check(lib().sr_launch_config(int(waves_per_cu), int(targets_per_lane), int(occupancy), cur),
+           "sr_launch_config")
+    return int(cur[0]), int(cur[1]), int(cur[2])
 
 
 def timing_enable(on: bool = True) -> None:

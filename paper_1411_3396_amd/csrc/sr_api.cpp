@@ -177,8 +177,10 @@ sr_status check_ws(const void *ws, size_t ws_bytes, const Layout &L)
 
 std::atomic<int> g_waves_per_cu_default{32};
 std::atomic<int> g_targets_per_lane_default{1};
+std::atomic<int> g_occupancy_default{0};
 
-// Launch defaults may be overridden for experiments: SR_WAVES_PER_CU, SR_TARGETS_PER_LANE.
+// Launch defaults may be overridden for experiments: SR_WAVES_PER_CU, SR_TARGETS_PER_LANE,
+// SR_OCCUPANCY.
 struct EnvDefaults {
     EnvDefaults()
     {
@@ -189,6 +191,10 @@ struct EnvDefaults {
         if (const char *v = std::getenv("SR_TARGETS_PER_LANE")) {
             const int t = std::atoi(v);
             if (t == 1 || t == 2) g_targets_per_lane_default = t;
+        }
+        if (const char *v = std::getenv("SR_OCCUPANCY")) {
+            const int o = std::atoi(v);
+            if (o == 0 || o == 6 || o == 8) g_occupancy_default = o;
         }
     }
 } g_env_defaults;
@@ -220,6 +226,7 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.num_cu = cus;
     a.n_rows = (int)n_rows;
     a.targets_per_lane = g_targets_per_lane_default.load();
+    a.occupancy = g_occupancy_default.load();
     return SR_OK;
 }
 
@@ -290,6 +297,7 @@ struct sr_batch_plan {
                *b_mom = nullptr;
     int waves_per_cu = 0;               // 0: not tuned yet
     int targets_per_lane = 1;
+    int occupancy = 0;
     std::string tune_cache;
     std::string tune_key;
     double tuned_ms = -1.0;
@@ -306,6 +314,7 @@ sr_status run_batched(sr_batch_plan *P, const float *pos, const float *mass, voi
                                   P->total_active);
     if (s != SR_OK) return s;
     a.targets_per_lane = P->targets_per_lane;
+    a.occupancy = P->occupancy;
     hipError_t e = hipMemcpyAsync(static_cast<char *>(ws) + P->L.seg, P->pinned,
                                   sizeof(SegParams) * P->B, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return SR_E_DEVICE;
@@ -327,6 +336,7 @@ sr_status run_per_subvolume(sr_batch_plan *P, const float *pos, const float *mas
         sr_status s = device_args(a, ws, &S.L, &S.seg, nullptr, st, P->waves_per_cu, P->n_active[b]);
         if (s != SR_OK) return s;
         a.targets_per_lane = P->targets_per_lane;
+        a.occupancy = P->occupancy;
         if (n > 0) {
             if (dev_bin(a, pos + 3 * off, mass + off) != hipSuccess) return SR_E_DEVICE;
             if (P->n_active[b] > 0 && dev_force(a, acc + 3 * out_off) != hipSuccess) return SR_E_DEVICE;
@@ -363,7 +373,7 @@ std::string arch_name()
 }
 
 // Minimal reader of the tune cache: one line per key, "key waves".
-bool cache_lookup(const std::string &path, const std::string &key, int &waves, int &tpl)
+bool cache_lookup(const std::string &path, const std::string &key, int &waves, int &tpl, int &occ)
 {
     if (path.empty()) return false;
     std::ifstream in(path);
@@ -380,16 +390,20 @@ bool cache_lookup(const std::string &path, const std::string &key, int &waves, i
         const int v = std::atoi(line.c_str() + w + 15);
         const size_t t = line.find("\"targets_per_lane\":", q1);
         const int tv = t == std::string::npos ? 1 : std::atoi(line.c_str() + t + 19);
-        if (v >= 1 && v <= 64 && (tv == 1 || tv == 2)) {
+        const size_t o = line.find("\"occupancy\":", q1);
+        const int ov = o == std::string::npos ? 0 : std::atoi(line.c_str() + o + 12);
+        if (v >= 1 && v <= 64 && (tv == 1 || tv == 2) && (ov == 0 || ov == 6 || ov == 8)) {
             waves = v;
             tpl = tv;
+            occ = ov;
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const std::string &path, const std::string &key, int waves, int tpl, double ms)
+void cache_store(const std::string &path, const std::string &key, int waves, int tpl, int occ,
+                 double ms)
 {
     if (path.empty()) return;
     std::vector<std::string> keep;
@@ -410,7 +424,7 @@ void cache_store(const std::string &path, const std::string &key, int waves, int
     }
     std::ostringstream e;
     e << "  \"" << key << "\": {\"waves_per_cu\": " << waves << ", \"targets_per_lane\": " << tpl
-      << ", \"ms\": " << ms << "}";
+      << ", \"occupancy\": " << occ << ", \"ms\": " << ms << "}";
     keep.push_back(e.str());
     const std::string tmp = path + ".tmp";
     {
@@ -424,50 +438,54 @@ void cache_store(const std::string &path, const std::string &key, int waves, int
 }
 
 // Pick the launch parameters (persistent grid in waves per CU, targets per
-// lane of dense forward items) by timing the batched sequence.
+// lane of dense items, register-allocation variant) by timing the batched
+// sequence; results do not depend on them.
 sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, float *acc,
                hipStream_t st)
 {
-    int waves = 0, tpl = 1;
-    if (cache_lookup(P->tune_cache, P->tune_key, waves, tpl)) {
+    int waves = 0, tpl = 1, occ = 0;
+    if (cache_lookup(P->tune_cache, P->tune_key, waves, tpl, occ)) {
         P->waves_per_cu = waves;
         P->targets_per_lane = tpl;
+        P->occupancy = occ;
         return SR_OK;
     }
-    const int cand_w[] = {8, 16, 24, 32};
-    const int cand_t[] = {1, 2};
+    struct Cand {
+        int w, t, o;
+    };
+    const Cand cand[] = {{16, 1, 0}, {32, 1, 0}, {16, 2, 0}, {32, 2, 0}, {24, 1, 6},
+                         {32, 1, 6}, {24, 2, 6}, {32, 2, 6}, {32, 1, 8}, {32, 2, 8}};
     double best = 1e300;
-    int best_w = g_waves_per_cu_default.load(), best_t = 1;
+    Cand pick{g_waves_per_cu_default.load(), 1, 0};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SR_E_DEVICE;
-    for (int t : cand_t) {
-        for (int w : cand_w) {
-            P->waves_per_cu = w;
-            P->targets_per_lane = t;
-            sr_status s = run_batched(P, pos, mass, ws, acc, nullptr, st);  // warm
+    for (const Cand &c : cand) {
+        P->waves_per_cu = c.w;
+        P->targets_per_lane = c.t;
+        P->occupancy = c.o;
+        sr_status s = run_batched(P, pos, mass, ws, acc, nullptr, st);  // warm
+        if (s != SR_OK) return s;
+        float ms = 0.f;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < 2; ++r) {
+            s = run_batched(P, pos, mass, ws, acc, nullptr, st);
             if (s != SR_OK) return s;
-            float ms = 0.f;
-            (void)hipEventRecord(e0, st);
-            for (int r = 0; r < 2; ++r) {
-                s = run_batched(P, pos, mass, ws, acc, nullptr, st);
-                if (s != SR_OK) return s;
-            }
-            (void)hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) return SR_E_DEVICE;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) {
-                best = ms;
-                best_w = w;
-                best_t = t;
-            }
+        }
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) return SR_E_DEVICE;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            pick = c;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    P->waves_per_cu = best_w;
-    P->targets_per_lane = best_t;
+    P->waves_per_cu = pick.w;
+    P->targets_per_lane = pick.t;
+    P->occupancy = pick.o;
     P->tuned_ms = best / 2.0;
-    cache_store(P->tune_cache, P->tune_key, best_w, best_t, best / 2.0);
+    cache_store(P->tune_cache, P->tune_key, pick.w, pick.t, pick.o, best / 2.0);
     return SR_OK;
 }
 
@@ -701,7 +719,7 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets, const int64_t 
         std::ostringstream k;
         int nb = 0;
         while ((int64_t(1) << (nb + 1)) <= std::max<int64_t>(1, offsets[B])) ++nb;
-        k << arch_name() << "/force-v2/B" << B << "/log2N" << nb << "/soft" << (soft ? 1 : 0);
+        k << arch_name() << "/force-v3/B" << B << "/log2N" << nb << "/soft" << (soft ? 1 : 0);
         P->tune_key = k.str();
     }
     *plan = P;
@@ -778,7 +796,8 @@ sr_status sr_batch_plan_info(const sr_batch_plan *P, char *buf, size_t buf_bytes
     o << "{\"B\": " << P->B << ", \"n\": " << P->offsets[P->B] << ", \"n_active\": "
       << P->total_active << ", \"cells\": " << P->L.NC << ", \"ws_bytes\": " << P->ws_bytes
       << ", \"waves_per_cu\": " << P->waves_per_cu << ", \"targets_per_lane\": "
-      << P->targets_per_lane << ", \"tuned_ms\": " << P->tuned_ms
+      << P->targets_per_lane << ", \"occupancy\": " << P->occupancy << ", \"tuned_ms\": "
+      << P->tuned_ms
       << ", \"tune_key\": \"" << P->tune_key << "\", \"graph\": " << (P->exec ? "true" : "false")
       << "}";
     const std::string s = o.str();
@@ -787,15 +806,18 @@ sr_status sr_batch_plan_info(const sr_batch_plan *P, char *buf, size_t buf_bytes
     return SR_OK;
 }
 
-sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int *cur)
+sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy, int *cur)
 {
     if (waves_per_cu < 0 || waves_per_cu > 64 || targets_per_lane < 0 || targets_per_lane > 2)
         return SR_E_ARG;
+    if (occupancy != -1 && occupancy != 0 && occupancy != 6 && occupancy != 8) return SR_E_ARG;
     if (waves_per_cu > 0) g_waves_per_cu_default = waves_per_cu;
     if (targets_per_lane > 0) g_targets_per_lane_default = targets_per_lane;
+    if (occupancy >= 0) g_occupancy_default = occupancy;
     if (cur) {
         cur[0] = g_waves_per_cu_default.load();
         cur[1] = g_targets_per_lane_default.load();
+        cur[2] = g_occupancy_default.load();
     }
     return SR_OK;
 }

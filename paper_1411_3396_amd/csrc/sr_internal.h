@@ -103,7 +103,8 @@ struct DevArgs {
     int waves_per_cu;
     int num_cu;
     int n_rows;  // rows of the force output (sum of n_active)
-    int targets_per_lane;  // 1 or 2 for cells with more than 64 targets (forward)
+    int targets_per_lane;  // 1 or 2 for cells with more than 64 targets
+    int occupancy;         // register-allocation hint of the pair kernels: 0, 6 or 8 waves/SIMD
 };
 
 hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass);

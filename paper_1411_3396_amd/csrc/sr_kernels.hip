@@ -758,8 +758,9 @@ __device__ __forceinline__ void force_item_two(const Stencil &st, const Src &src
 }
 
 // Forward: acc[out_row] = sum over the stencil of m_j d f_SR.
-template <class Acc, bool kSoft>
-__global__ __launch_bounds__(64) void k_force(Acc acc, const int4 *__restrict__ items,
+// kOcc: minimum waves per SIMD the register allocation must allow (0: no hint).
+template <class Acc, bool kSoft, int kOcc>
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(Acc acc, const int4 *__restrict__ items,
                                               uint32_t *hdr, const int *__restrict__ start, Src src,
                                               const int *__restrict__ out_row,
                                               float *__restrict__ out, int n_out)
@@ -838,10 +839,86 @@ __global__ __launch_bounds__(64) void k_force(Acc acc, const int4 *__restrict__ 
     }
 }
 
+// Source v of the stencil for the adjoint: position (shifted) and mass, and
+// the binned cotangent; padding past the end is far away with zero mass.
+__device__ __forceinline__ void fetch_vjp(const Stencil &st, int v, const Src &src,
+                                          const float *__restrict__ gx,
+                                          const float *__restrict__ gy,
+                                          const float *__restrict__ gz, float4 &p, float4 &gv)
+{
+    float sx, sy, sz;
+    const int j = stencil_locate(st, v, sx, sy, sz);
+    p = make_float4(src.x[j] + sx, src.y[j] + sy, src.z[j] + sz, src.m[j]);
+    gv = make_float4(gx[j], gy[j], gz[j], 0.f);
+    if (v >= st.total) {
+        p = make_float4(kFar, kFar, kFar, 0.f);
+        gv = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// Dense adjoint item with two targets per lane (t0 + lane, t0 + 64 + lane).
+template <bool kSoft>
+__device__ __forceinline__ void vjp_item_two(const Stencil &st, const Src &src,
+                                             const float *__restrict__ gx,
+                                             const float *__restrict__ gy,
+                                             const float *__restrict__ gz, int t0, int nt,
+                                             int lane, float eps2, float tc2, const float *cq,
+                                             const float *cd, const int *__restrict__ perm,
+                                             float *__restrict__ out, int n_out, float4 *stage_p,
+                                             float4 *stage_g)
+{
+    const int ba = t0 + lane, bb = t0 + kWave + lane;
+    const bool va = lane < nt, vb = kWave + lane < nt;
+    float pax = 0.f, pay = 0.f, paz = 0.f, ma = 0.f, gax = 0.f, gay = 0.f, gaz = 0.f;
+    float pbx = 0.f, pby = 0.f, pbz = 0.f, mb = 0.f, gbx = 0.f, gby = 0.f, gbz = 0.f;
+    if (va) {
+        pax = src.x[ba]; pay = src.y[ba]; paz = src.z[ba]; ma = src.m[ba];
+        gax = gx[ba]; gay = gy[ba]; gaz = gz[ba];
+    }
+    if (vb) {
+        pbx = src.x[bb]; pby = src.y[bb]; pbz = src.z[bb]; mb = src.m[bb];
+        gbx = gx[bb]; gby = gy[bb]; gbz = gz[bb];
+    }
+    float rax = 0.f, ray = 0.f, raz = 0.f, rbx = 0.f, rby = 0.f, rbz = 0.f;
+    float4 nxp, nxg;
+    fetch_vjp(st, lane, src, gx, gy, gz, nxp, nxg);
+    for (int base = 0; base < st.total; base += kWave) {
+        __syncthreads();
+        stage_p[lane] = nxp;
+        stage_g[lane] = nxg;
+        __syncthreads();
+        if (base + kWave < st.total) fetch_vjp(st, base + kWave + lane, src, gx, gy, gz, nxp, nxg);
+        const int n2 = (min(kWave, st.total - base) + 1) >> 1;
+        for (int u = 0; u < n2; ++u) {
+#pragma unroll
+            for (int q2 = 0; q2 < 2; ++q2) {
+                const float4 sp = stage_p[2 * u + q2];
+                const float4 sg = stage_g[2 * u + q2];
+                vjp_pair<kSoft>(sp, sg, pax, pay, paz, ma, gax, gay, gaz, eps2, tc2, cq, cd, rax,
+                                ray, raz);
+                vjp_pair<kSoft>(sp, sg, pbx, pby, pbz, mb, gbx, gby, gbz, eps2, tc2, cq, cd, rbx,
+                                rby, rbz);
+            }
+        }
+    }
+    const int pa = va ? perm[ba] : -1;
+    const int pb = vb ? perm[bb] : -1;
+    if (pa >= 0 && pa < n_out) {
+        out[3 * (int64_t)pa] = rax;
+        out[3 * (int64_t)pa + 1] = ray;
+        out[3 * (int64_t)pa + 2] = raz;
+    }
+    if (pb >= 0 && pb < n_out) {
+        out[3 * (int64_t)pb] = rbx;
+        out[3 * (int64_t)pb + 1] = rby;
+        out[3 * (int64_t)pb + 2] = rbz;
+    }
+}
+
 // Adjoint: grad[perm] = sum over the stencil of f u + 2 f' (u.d) d,
 // u = m_k g_j - m_j g_k.
-template <class Acc, bool kSoft>
-__global__ __launch_bounds__(64) void k_vjp(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
+template <class Acc, bool kSoft, int kOcc>
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
                                             const int *__restrict__ start, Src src,
                                             const float *__restrict__ gx,
                                             const float *__restrict__ gy,
@@ -870,6 +947,11 @@ __global__ __launch_bounds__(64) void k_vjp(Acc acc, const int4 *__restrict__ it
             for (int k = 0; k < 5; ++k) cd[k] = S.pc.dq[k];
             Stencil st;
             stencil_setup(S, it.x, start, lane, st);
+            if (item_two(it.w)) {
+                vjp_item_two<kSoft>(st, src, gx, gy, gz, t0, nt, lane, eps2, tc2, cq, cd, perm, out,
+                                    n_out, stage_p, stage_g);
+                continue;
+            }
             const int kl = 1 << lk;
             const int t = lane >> lk, sub = lane & (kl - 1);
             const bool tv = t < nt;
@@ -886,33 +968,13 @@ __global__ __launch_bounds__(64) void k_vjp(Acc acc, const int4 *__restrict__ it
             }
             float rx = 0.f, ry = 0.f, rz = 0.f;
             float4 nxp, nxg;
-            {
-                float sx, sy, sz;
-                const int v = lane;
-                const int j = stencil_locate(st, v, sx, sy, sz);
-                nxp = make_float4(src.x[j] + sx, src.y[j] + sy, src.z[j] + sz, src.m[j]);
-                nxg = make_float4(gx[j], gy[j], gz[j], 0.f);
-                if (v >= st.total) {
-                    nxp = make_float4(kFar, kFar, kFar, 0.f);
-                    nxg = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
+            fetch_vjp(st, lane, src, gx, gy, gz, nxp, nxg);
             for (int base = 0; base < st.total; base += kWave) {
                 __syncthreads();
                 stage_p[lane] = nxp;
                 stage_g[lane] = nxg;
                 __syncthreads();
-                if (base + kWave < st.total) {
-                    float sx, sy, sz;
-                    const int v = base + kWave + lane;
-                    const int j = stencil_locate(st, v, sx, sy, sz);
-                    nxp = make_float4(src.x[j] + sx, src.y[j] + sy, src.z[j] + sz, src.m[j]);
-                    nxg = make_float4(gx[j], gy[j], gz[j], 0.f);
-                    if (v >= st.total) {
-                        nxp = make_float4(kFar, kFar, kFar, 0.f);
-                        nxg = make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-                }
+                if (base + kWave < st.total) fetch_vjp(st, base + kWave + lane, src, gx, gy, gz, nxp, nxg);
                 const int cnt = min(kWave, st.total - base);
                 if (lk == 0) {
                     const int n4 = (cnt + 3) >> 2;
@@ -1183,23 +1245,43 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
     });
 }
 
-hipError_t dev_force(const DevArgs &a, float *acc_out)
+template <class Acc, bool kSoft, int kOcc>
+void launch_force(const DevArgs &a, Acc acc, float *acc_out)
 {
     const Layout &L = *a.L;
+    k_force<Acc, kSoft, kOcc><<<persistent_grid(a), kWave, 0, a.st>>>(
+        acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
+        at<int>(a, L.out_row), acc_out, a.n_rows);
+}
+
+template <class Acc, bool kSoft, int kOcc>
+void launch_vjp(const DevArgs &a, Acc acc, float *grad)
+{
+    const Layout &L = *a.L;
+    k_vjp<Acc, kSoft, kOcc><<<persistent_grid(a), kWave, 0, a.st>>>(
+        acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
+        at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz), at<int>(a, L.perm()), grad,
+        (int)L.N);
+}
+
+hipError_t dev_force(const DevArgs &a, float *acc_out)
+{
     hipError_t e = build_items<true>(a, a.targets_per_lane >= 2 ? 1 : 0);
     if (e != hipSuccess) return e;
     const bool soft = all_softened(a);
     return with_acc(a, [&](auto acc) -> hipError_t {
+        using A = decltype(acc);
         void *tok = nullptr;
         timing_begin("force", a.st, &tok);
-        if (soft)
-            k_force<decltype(acc), true><<<persistent_grid(a), kWave, 0, a.st>>>(
-                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
-                at<int>(a, L.out_row), acc_out, a.n_rows);
-        else
-            k_force<decltype(acc), false><<<persistent_grid(a), kWave, 0, a.st>>>(
-                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
-                at<int>(a, L.out_row), acc_out, a.n_rows);
+        if (soft) {
+            if (a.occupancy >= 8) launch_force<A, true, 8>(a, acc, acc_out);
+            else if (a.occupancy >= 6) launch_force<A, true, 6>(a, acc, acc_out);
+            else launch_force<A, true, 0>(a, acc, acc_out);
+        } else {
+            if (a.occupancy >= 8) launch_force<A, false, 8>(a, acc, acc_out);
+            else if (a.occupancy >= 6) launch_force<A, false, 6>(a, acc, acc_out);
+            else launch_force<A, false, 0>(a, acc, acc_out);
+        }
         const hipError_t le = hipGetLastError();
         timing_end(tok, a.st);
         return le;
@@ -1214,21 +1296,20 @@ hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad)
                                                       at<float>(a, L.gz));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = build_items<false>(a, 0)) != hipSuccess) return e;
+    if ((e = build_items<false>(a, a.targets_per_lane >= 2 ? 1 : 0)) != hipSuccess) return e;
     const bool soft = all_softened(a);
     return with_acc(a, [&](auto acc) -> hipError_t {
+        using A = decltype(acc);
         void *tok = nullptr;
         timing_begin("vjp", a.st, &tok);
-        if (soft)
-            k_vjp<decltype(acc), true><<<persistent_grid(a), kWave, 0, a.st>>>(
-                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
-                at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz), at<int>(a, L.perm()), grad,
-                (int)L.N);
-        else
-            k_vjp<decltype(acc), false><<<persistent_grid(a), kWave, 0, a.st>>>(
-                acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
-                at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz), at<int>(a, L.perm()), grad,
-                (int)L.N);
+        // the adjoint kernel spills at 8 waves per SIMD: 6 is its tightest hint
+        if (soft) {
+            if (a.occupancy >= 6) launch_vjp<A, true, 6>(a, acc, grad);
+            else launch_vjp<A, true, 0>(a, acc, grad);
+        } else {
+            if (a.occupancy >= 6) launch_vjp<A, false, 6>(a, acc, grad);
+            else launch_vjp<A, false, 0>(a, acc, grad);
+        }
         const hipError_t le = hipGetLastError();
         timing_end(tok, a.st);
         return le;

@@ -106,6 +106,19 @@ def test_vjp_and_bin_validation():
     assert L.sr_count_pairs(100, 100, C.byref(p), FAKE, nb, None, None) == 1
 
 
+def test_launch_config_validation():
+    L = _sr.lib()
+    cur = (C.c_int * 3)()
+    assert L.sr_launch_config(65, 0, -1, cur) == 1
+    assert L.sr_launch_config(0, 3, -1, cur) == 1
+    assert L.sr_launch_config(0, 0, 7, cur) == 1
+    saved = _sr.launch_config()
+    assert _sr.launch_config(16, 2, 6) == (16, 2, 6)
+    assert _sr.launch_config() == (16, 2, 6)
+    _sr.launch_config(*saved)
+    assert _sr.launch_config() == saved
+
+
 def test_batch_plan_validation_and_layout():
     L = _sr.lib()
     probs = [prob(), prob(length=40.0)]

@@ -165,16 +165,21 @@ def test_launch_configs_agree_bitwise():
     # every target sums its sources in the same order, so results are bitwise equal
     w = synth.clustered_box(150000, 36.0, 30, 3, halo_frac=0.7, mass_range=(1e3, 1e5))
     w.mass = np.random.default_rng(2).uniform(0.5, 2.0, w.n).astype(np.float32)
+    g = synth.cotangent(w.n_active, 5)
     saved = sr.launch_config()
-    ref = None
+    ref = gref = None
     try:
-        for waves, tpl in [(32, 1), (8, 2), (16, 2), (24, 1)]:
-            sr.launch_config(waves, tpl)
-            announce(f"launch config waves={waves} targets_per_lane={tpl}")
+        for waves, tpl, occ in [(32, 1, 0), (8, 2, 6), (16, 2, 8), (24, 1, 6), (32, 2, 0)]:
+            sr.launch_config(waves, tpl, occ)
+            announce(f"launch config waves={waves} targets_per_lane={tpl} occupancy={occ}")
             a = gpu_force(w)
+            gr = sr.force_vjp(to_dev(w.pos), to_dev(w.mass), w.problem, to_dev(g)).cpu().numpy()
             if ref is None:
-                ref = a
+                ref, gref = a, gr
                 assert_force_close(a, oracle_force(w), what="dense cells")
-            assert np.array_equal(a.view(np.uint32), ref.view(np.uint32)), (waves, tpl)
+                gora = oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g)
+                assert oracle.rms_rel(gr, gora) <= 1e-4
+            assert np.array_equal(a.view(np.uint32), ref.view(np.uint32)), (waves, tpl, occ)
+            assert np.array_equal(gr.view(np.uint32), gref.view(np.uint32)), (waves, tpl, occ)
     finally:
         sr.launch_config(*saved)

@@ -65,6 +65,7 @@ PairConsts pair_consts(const sr_problem *p)
     pc.eps2 = p->eps * p->eps;
     const float rs2 = p->r_s * p->r_s;
     pc.tc2 = rs2 + pc.eps2;
+    pc.cull2 = (float)((double)rs2 * (1.0 + 1e-5));
     pc.softened = p->eps > 0.0f ? 1 : 0;
     // Q(t) = P(t - e2): expand each c_k (t - e2)^k by the binomial theorem in double.
     const double e2 = (double)pc.eps2;

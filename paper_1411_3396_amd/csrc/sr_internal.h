@@ -26,6 +26,7 @@ constexpr int kMomTile = 65536;      // rows per momentum partial
 struct PairConsts {
     float eps2;   // eps * eps
     float tc2;    // r_s^2 + eps^2: pairs with t < tc2 interact
+    float cull2;  // r_s^2 (1 + 1e-5): sources farther than this from the targets' box are skipped
     float q[6];
     float dq[5];
     int32_t softened;  // eps > 0
@@ -47,7 +48,7 @@ struct SegParams {
     int32_t out_off;   // first output row of its accelerations
     int32_t tile_off;  // first momentum partial
     PairConsts pc;
-    int32_t pad[1];
+    int32_t pad[4];
 };
 static_assert(sizeof(SegParams) % 16 == 0, "SegParams must stay 16-byte sized");
 

@@ -703,139 +703,100 @@ __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float 
     rz = fmaf(c, dz, fmaf(f, uz, rz));
 }
 
-// Dense item with two targets per lane (t0 + lane and t0 + 64 + lane): every
-// source read from LDS feeds two pair terms, halving LDS traffic per pair.
-template <bool kSoft>
-__device__ __forceinline__ void store_acc(const int *__restrict__ out_row, float *__restrict__ out,
-                                          int n_out, int b, float ax, float ay, float az)
+// ------------------------------------------------------------- source culling
+
+// Bounding box of the targets an item holds (in the home-cell frame).
+struct Box {
+    float lx, ly, lz, hx, hy, hz;
+};
+
+__device__ __forceinline__ float wave_min(float v)
 {
-    const int r = out_row[b];
-    if (r >= 0 && r < n_out) {
-        const int64_t o3 = 3 * (int64_t)r;
-        out[o3] = ax;
-        out[o3 + 1] = ay;
-        out[o3 + 2] = az;
-    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
 }
 
-template <bool kSoft>
-__device__ __forceinline__ void force_item_two(const Stencil &st, const Src &src, int t0, int nt,
-                                               int lane, float eps2, float tc2, const float *cq,
-                                               const int *__restrict__ out_row,
-                                               float *__restrict__ out, int n_out, float4 *stage)
+__device__ __forceinline__ float wave_max(float v)
 {
-    const bool va = lane < nt, vb = kWave + lane < nt;
-    float pax = 0.f, pay = 0.f, paz = 0.f, pbx = 0.f, pby = 0.f, pbz = 0.f;
-    if (va) {
-        pax = src.x[t0 + lane];
-        pay = src.y[t0 + lane];
-        paz = src.z[t0 + lane];
-    }
-    if (vb) {
-        pbx = src.x[t0 + kWave + lane];
-        pby = src.y[t0 + kWave + lane];
-        pbz = src.z[t0 + kWave + lane];
-    }
-    float aax = 0.f, aay = 0.f, aaz = 0.f, abx = 0.f, aby = 0.f, abz = 0.f;
-    float4 nxt = fetch_pos(st, lane, src);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Box of the valid targets of this wave: lane values (xa, ya, za) when va,
+// (xb, yb, zb) when vb.
+__device__ __forceinline__ Box target_box(bool va, float xa, float ya, float za, bool vb, float xb,
+                                          float yb, float zb)
+{
+    const float inf = __builtin_huge_valf();
+    Box b;
+    b.lx = wave_min(fminf(va ? xa : inf, vb ? xb : inf));
+    b.ly = wave_min(fminf(va ? ya : inf, vb ? yb : inf));
+    b.lz = wave_min(fminf(va ? za : inf, vb ? zb : inf));
+    b.hx = wave_max(fmaxf(va ? xa : -inf, vb ? xb : -inf));
+    b.hy = wave_max(fmaxf(va ? ya : -inf, vb ? yb : -inf));
+    b.hz = wave_max(fmaxf(va ? za : -inf, vb ? zb : -inf));
+    return b;
+}
+
+// A source at (x, y, z) may interact with some target of the box: its squared
+// gap to the box is at most cull2 = r_s^2 (1 + 1e-5).  The margin covers the
+// float32 rounding of both this test and the pair kernel's own cutoff test, so
+// no pair the pair kernel would count is ever dropped.
+__device__ __forceinline__ bool may_reach(const Box &b, float x, float y, float z, float cull2)
+{
+    const float gx = fmaxf(fmaxf(b.lx - x, x - b.hx), 0.f);
+    const float gy = fmaxf(fmaxf(b.ly - y, y - b.hy), 0.f);
+    const float gz = fmaxf(fmaxf(b.lz - z, z - b.hz), 0.f);
+    return fmaf(gx, gx, fmaf(gy, gy, gz * gz)) <= cull2;
+}
+
+// Stream the stencil's sources through LDS.  Candidates are fetched 64 at a
+// time (the next batch is prefetched into registers), sources that cannot
+// reach the target box are dropped, and survivors are packed into stage0
+// (and stage1 for a second float4 per source) with a ballot.  compute(n)
+// consumes stage entries [0, n); entries [n, 64) are padding that the pair
+// terms mask out.  Every lane must call this (wave-uniform control flow).
+template <int kParts, class Fetch, class Compute>
+__device__ __forceinline__ void stream_sources(const Stencil &st, const Box &box, float cull2,
+                                               int lane, float4 *stage0, float4 *stage1,
+                                               Fetch &&fetch, Compute &&compute)
+{
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int fill = 0;
+    float4 c0, c1;
+    fetch(lane, c0, c1);
     for (int base = 0; base < st.total; base += kWave) {
-        __syncthreads();
-        stage[lane] = nxt;
-        __syncthreads();
-        if (base + kWave < st.total) nxt = fetch_pos(st, base + kWave + lane, src);
-        const int n4 = (min(kWave, st.total - base) + 3) >> 2;
-        for (int u = 0; u < n4; ++u) {
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const float4 sj = stage[4 * u + q4];
-                force_pair<kSoft>(sj, pax, pay, paz, eps2, tc2, cq, aax, aay, aaz);
-                force_pair<kSoft>(sj, pbx, pby, pbz, eps2, tc2, cq, abx, aby, abz);
+        const bool keep = (base + lane < st.total) && may_reach(box, c0.x, c0.y, c0.z, cull2);
+        const uint64_t m = __ballot(keep);
+        const int cnt = __popcll(m);
+        if (fill + cnt > kWave) {
+            if (lane >= fill) {
+                stage0[lane] = make_float4(kFar, kFar, kFar, 0.f);
+                if (kParts == 2) stage1[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
+            __syncthreads();
+            compute(fill);
+            __syncthreads();
+            fill = 0;
         }
+        if (keep) {
+            const int at = fill + __popcll(m & below);
+            stage0[at] = c0;
+            if (kParts == 2) stage1[at] = c1;
+        }
+        fill += cnt;
+        if (base + kWave < st.total) fetch(base + kWave + lane, c0, c1);
     }
-    if (va) store_acc<kSoft>(out_row, out, n_out, t0 + lane, aax, aay, aaz);
-    if (vb) store_acc<kSoft>(out_row, out, n_out, t0 + kWave + lane, abx, aby, abz);
-}
-
-// Forward: acc[out_row] = sum over the stencil of m_j d f_SR.
-// kOcc: minimum waves per SIMD the register allocation must allow (0: no hint).
-template <class Acc, bool kSoft, int kOcc>
-__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(Acc acc, const int4 *__restrict__ items,
-                                              uint32_t *hdr, const int *__restrict__ start, Src src,
-                                              const int *__restrict__ out_row,
-                                              float *__restrict__ out, int n_out)
-{
-    __shared__ float4 stage[kWave];
-    const int lane = threadIdx.x;
-    const int64_t n_items = hdr[kHdrNItems];
-    const int q0 = blockIdx.x & (kQueues - 1);
-    for (int qq = 0; qq < kQueues; ++qq) {
-        const int q = (q0 + qq) & (kQueues - 1);
-        for (;;) {
-            const int64_t g = next_item(hdr, q, lane);
-            if (g >= n_items) break;
-            const int4 it = load_item(items, g);
-            const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
-            const SegParams &S = acc.get(item_seg(it.w));
-            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
-            float cq[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
-            Stencil st;
-            stencil_setup(S, it.x, start, lane, st);
-            if (item_two(it.w)) {
-                force_item_two<kSoft>(st, src, t0, nt, lane, eps2, tc2, cq, out_row, out, n_out,
-                                      stage);
-                continue;
-            }
-            const int kl = 1 << lk;
-            const int t = lane >> lk, sub = lane & (kl - 1);
-            const bool tv = t < nt;
-            float px = 0.f, py = 0.f, pz = 0.f;
-            if (tv) {
-                px = src.x[t0 + t];
-                py = src.y[t0 + t];
-                pz = src.z[t0 + t];
-            }
-            float ax = 0.f, ay = 0.f, az = 0.f;
-            float4 nxt = fetch_pos(st, lane, src);
-            for (int base = 0; base < st.total; base += kWave) {
-                __syncthreads();
-                stage[lane] = nxt;
-                __syncthreads();
-                if (base + kWave < st.total) nxt = fetch_pos(st, base + kWave + lane, src);
-                const int cnt = min(kWave, st.total - base);
-                if (lk == 0) {
-                    // one lane per target: every lane reads the same source (LDS
-                    // broadcast); groups of 8, the padding after cnt is masked
-                    const int n8 = (cnt + 7) >> 3;
-                    for (int u = 0; u < n8; ++u) {
-#pragma unroll
-                        for (int q8 = 0; q8 < 8; ++q8)
-                            force_pair<kSoft>(stage[8 * u + q8], px, py, pz, eps2, tc2, cq, ax, ay, az);
-                    }
-                } else {
-                    const int niter = (cnt + kl - 1) >> lk;
-#pragma unroll 2
-                    for (int i = 0; i < niter; ++i)
-                        force_pair<kSoft>(stage[sub + (i << lk)], px, py, pz, eps2, tc2, cq, ax, ay, az);
-                }
-            }
-            for (int o = 1; o < kl; o <<= 1) {
-                ax += __shfl_xor(ax, o);
-                ay += __shfl_xor(ay, o);
-                az += __shfl_xor(az, o);
-            }
-            if (tv && sub == 0) {
-                const int r = out_row[t0 + t];
-                if (r >= 0 && r < n_out) {
-                    const int64_t o3 = 3 * (int64_t)r;
-                    out[o3] = ax;
-                    out[o3 + 1] = ay;
-                    out[o3 + 2] = az;
-                }
-            }
+    if (fill > 0) {
+        if (lane >= fill) {
+            stage0[lane] = make_float4(kFar, kFar, kFar, 0.f);
+            if (kParts == 2) stage1[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        __syncthreads();
+        compute(fill);
+        __syncthreads();
     }
 }
 
@@ -856,75 +817,126 @@ __device__ __forceinline__ void fetch_vjp(const Stencil &st, int v, const Src &s
     }
 }
 
-// Dense adjoint item with two targets per lane (t0 + lane, t0 + 64 + lane).
-template <bool kSoft>
-__device__ __forceinline__ void vjp_item_two(const Stencil &st, const Src &src,
-                                             const float *__restrict__ gx,
-                                             const float *__restrict__ gy,
-                                             const float *__restrict__ gz, int t0, int nt,
-                                             int lane, float eps2, float tc2, const float *cq,
-                                             const float *cd, const int *__restrict__ perm,
-                                             float *__restrict__ out, int n_out, float4 *stage_p,
-                                             float4 *stage_g)
+__device__ __forceinline__ void store3(float *__restrict__ out, int n_out, int r, float x, float y,
+                                       float z)
 {
-    const int ba = t0 + lane, bb = t0 + kWave + lane;
-    const bool va = lane < nt, vb = kWave + lane < nt;
-    float pax = 0.f, pay = 0.f, paz = 0.f, ma = 0.f, gax = 0.f, gay = 0.f, gaz = 0.f;
-    float pbx = 0.f, pby = 0.f, pbz = 0.f, mb = 0.f, gbx = 0.f, gby = 0.f, gbz = 0.f;
-    if (va) {
-        pax = src.x[ba]; pay = src.y[ba]; paz = src.z[ba]; ma = src.m[ba];
-        gax = gx[ba]; gay = gy[ba]; gaz = gz[ba];
-    }
-    if (vb) {
-        pbx = src.x[bb]; pby = src.y[bb]; pbz = src.z[bb]; mb = src.m[bb];
-        gbx = gx[bb]; gby = gy[bb]; gbz = gz[bb];
-    }
-    float rax = 0.f, ray = 0.f, raz = 0.f, rbx = 0.f, rby = 0.f, rbz = 0.f;
-    float4 nxp, nxg;
-    fetch_vjp(st, lane, src, gx, gy, gz, nxp, nxg);
-    for (int base = 0; base < st.total; base += kWave) {
-        __syncthreads();
-        stage_p[lane] = nxp;
-        stage_g[lane] = nxg;
-        __syncthreads();
-        if (base + kWave < st.total) fetch_vjp(st, base + kWave + lane, src, gx, gy, gz, nxp, nxg);
-        const int n2 = (min(kWave, st.total - base) + 1) >> 1;
-        for (int u = 0; u < n2; ++u) {
-#pragma unroll
-            for (int q2 = 0; q2 < 2; ++q2) {
-                const float4 sp = stage_p[2 * u + q2];
-                const float4 sg = stage_g[2 * u + q2];
-                vjp_pair<kSoft>(sp, sg, pax, pay, paz, ma, gax, gay, gaz, eps2, tc2, cq, cd, rax,
-                                ray, raz);
-                vjp_pair<kSoft>(sp, sg, pbx, pby, pbz, mb, gbx, gby, gbz, eps2, tc2, cq, cd, rbx,
-                                rby, rbz);
-            }
-        }
-    }
-    const int pa = va ? perm[ba] : -1;
-    const int pb = vb ? perm[bb] : -1;
-    if (pa >= 0 && pa < n_out) {
-        out[3 * (int64_t)pa] = rax;
-        out[3 * (int64_t)pa + 1] = ray;
-        out[3 * (int64_t)pa + 2] = raz;
-    }
-    if (pb >= 0 && pb < n_out) {
-        out[3 * (int64_t)pb] = rbx;
-        out[3 * (int64_t)pb + 1] = rby;
-        out[3 * (int64_t)pb + 2] = rbz;
+    if (r >= 0 && r < n_out) {
+        const int64_t o3 = 3 * (int64_t)r;
+        out[o3] = x;
+        out[o3 + 1] = y;
+        out[o3 + 2] = z;
     }
 }
 
-// Adjoint: grad[perm] = sum over the stencil of f u + 2 f' (u.d) d,
-// u = m_k g_j - m_j g_k.
+// ------------------------------------------------------------- forward kernel
+
+// Forward: acc[out_row] = sum over the stencil of m_j d f_SR.
+//  - dense items (one target per lane): every lane reads the same staged
+//    source (LDS broadcast), in groups of 8;
+//  - two-target items: lanes hold t0 + lane and t0 + 64 + lane and use each
+//    staged source twice;
+//  - sparse items: 2^lk lanes per target stride over the sources and reduce
+//    with cross-lane butterflies.
 template <class Acc, bool kSoft, int kOcc>
-__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
-                                            const int *__restrict__ start, Src src,
-                                            const float *__restrict__ gx,
-                                            const float *__restrict__ gy,
-                                            const float *__restrict__ gz,
-                                            const int *__restrict__ perm,
-                                            float *__restrict__ out, int n_out)
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
+    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
+    const int *__restrict__ out_row, float *__restrict__ out, int n_out)
+{
+    __shared__ float4 stage[kWave];
+    const int lane = threadIdx.x;
+    const int64_t n_items = hdr[kHdrNItems];
+    const int q0 = blockIdx.x & (kQueues - 1);
+    for (int qq = 0; qq < kQueues; ++qq) {
+        const int q = (q0 + qq) & (kQueues - 1);
+        for (;;) {
+            const int64_t g = next_item(hdr, q, lane);
+            if (g >= n_items) break;
+            const int4 it = load_item(items, g);
+            const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
+            const SegParams &S = acc.get(item_seg(it.w));
+            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
+            float cq[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
+            Stencil st;
+            stencil_setup(S, it.x, start, lane, st);
+            auto fetch_p = [&](int v, float4 &c0, float4 &) { c0 = fetch_pos(st, v, src); };
+            if (item_two(it.w)) {
+                const bool va = lane < nt, vb = kWave + lane < nt;
+                float pax = 0.f, pay = 0.f, paz = 0.f, pbx = 0.f, pby = 0.f, pbz = 0.f;
+                if (va) {
+                    pax = src.x[t0 + lane];
+                    pay = src.y[t0 + lane];
+                    paz = src.z[t0 + lane];
+                }
+                if (vb) {
+                    pbx = src.x[t0 + kWave + lane];
+                    pby = src.y[t0 + kWave + lane];
+                    pbz = src.z[t0 + kWave + lane];
+                }
+                const Box box = target_box(va, pax, pay, paz, vb, pbx, pby, pbz);
+                float aax = 0.f, aay = 0.f, aaz = 0.f, abx = 0.f, aby = 0.f, abz = 0.f;
+                stream_sources<1>(st, box, cull2, lane, stage, stage, fetch_p, [&](int n) {
+                    const int n4 = (n + 3) >> 2;
+                    for (int u = 0; u < n4; ++u) {
+#pragma unroll
+                        for (int q4 = 0; q4 < 4; ++q4) {
+                            const float4 sj = stage[4 * u + q4];
+                            force_pair<kSoft>(sj, pax, pay, paz, eps2, tc2, cq, aax, aay, aaz);
+                            force_pair<kSoft>(sj, pbx, pby, pbz, eps2, tc2, cq, abx, aby, abz);
+                        }
+                    }
+                });
+                if (va) store3(out, n_out, out_row[t0 + lane], aax, aay, aaz);
+                if (vb) store3(out, n_out, out_row[t0 + kWave + lane], abx, aby, abz);
+                continue;
+            }
+            const int kl = 1 << lk;
+            const int t = lane >> lk, sub = lane & (kl - 1);
+            const bool tv = t < nt;
+            float px = 0.f, py = 0.f, pz = 0.f;
+            if (tv) {
+                px = src.x[t0 + t];
+                py = src.y[t0 + t];
+                pz = src.z[t0 + t];
+            }
+            const Box box = target_box(tv, px, py, pz, false, 0.f, 0.f, 0.f);
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            stream_sources<1>(st, box, cull2, lane, stage, stage, fetch_p, [&](int n) {
+                if (lk == 0) {
+                    const int n8 = (n + 7) >> 3;
+                    for (int u = 0; u < n8; ++u) {
+#pragma unroll
+                        for (int q8 = 0; q8 < 8; ++q8)
+                            force_pair<kSoft>(stage[8 * u + q8], px, py, pz, eps2, tc2, cq, ax, ay, az);
+                    }
+                } else {
+                    const int niter = (n + kl - 1) >> lk;
+#pragma unroll 2
+                    for (int i = 0; i < niter; ++i)
+                        force_pair<kSoft>(stage[sub + (i << lk)], px, py, pz, eps2, tc2, cq, ax, ay, az);
+                }
+            });
+            for (int o = 1; o < kl; o <<= 1) {
+                ax += __shfl_xor(ax, o);
+                ay += __shfl_xor(ay, o);
+                az += __shfl_xor(az, o);
+            }
+            if (tv && sub == 0) store3(out, n_out, out_row[t0 + t], ax, ay, az);
+        }
+    }
+}
+
+// ------------------------------------------------------------- adjoint kernel
+
+// Adjoint: grad[perm] = sum over the stencil of f u + 2 f' (u.d) d,
+// u = m_k g_j - m_j g_k.  Same item shapes as the forward kernel; every
+// source stages (x, y, z, m) and (g, 0).
+template <class Acc, bool kSoft, int kOcc>
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
+    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
+    const float *__restrict__ gx, const float *__restrict__ gy, const float *__restrict__ gz,
+    const int *__restrict__ perm, float *__restrict__ out, int n_out)
 {
     __shared__ float4 stage_p[kWave];
     __shared__ float4 stage_g[kWave];
@@ -939,7 +951,7 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(Acc acc, const 
             const int4 it = load_item(items, g);
             const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
             const SegParams &S = acc.get(item_seg(it.w));
-            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
+            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
             float cq[6], cd[5];
 #pragma unroll
             for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
@@ -947,9 +959,40 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(Acc acc, const 
             for (int k = 0; k < 5; ++k) cd[k] = S.pc.dq[k];
             Stencil st;
             stencil_setup(S, it.x, start, lane, st);
+            auto fetch_pg = [&](int v, float4 &c0, float4 &c1) {
+                fetch_vjp(st, v, src, gx, gy, gz, c0, c1);
+            };
             if (item_two(it.w)) {
-                vjp_item_two<kSoft>(st, src, gx, gy, gz, t0, nt, lane, eps2, tc2, cq, cd, perm, out,
-                                    n_out, stage_p, stage_g);
+                const int ba = t0 + lane, bb = t0 + kWave + lane;
+                const bool va = lane < nt, vb = kWave + lane < nt;
+                float pax = 0.f, pay = 0.f, paz = 0.f, ma = 0.f, gax = 0.f, gay = 0.f, gaz = 0.f;
+                float pbx = 0.f, pby = 0.f, pbz = 0.f, mb = 0.f, gbx = 0.f, gby = 0.f, gbz = 0.f;
+                if (va) {
+                    pax = src.x[ba]; pay = src.y[ba]; paz = src.z[ba]; ma = src.m[ba];
+                    gax = gx[ba]; gay = gy[ba]; gaz = gz[ba];
+                }
+                if (vb) {
+                    pbx = src.x[bb]; pby = src.y[bb]; pbz = src.z[bb]; mb = src.m[bb];
+                    gbx = gx[bb]; gby = gy[bb]; gbz = gz[bb];
+                }
+                const Box box = target_box(va, pax, pay, paz, vb, pbx, pby, pbz);
+                float rax = 0.f, ray = 0.f, raz = 0.f, rbx = 0.f, rby = 0.f, rbz = 0.f;
+                stream_sources<2>(st, box, cull2, lane, stage_p, stage_g, fetch_pg, [&](int n) {
+                    const int n2 = (n + 1) >> 1;
+                    for (int u = 0; u < n2; ++u) {
+#pragma unroll
+                        for (int q2 = 0; q2 < 2; ++q2) {
+                            const float4 sp = stage_p[2 * u + q2];
+                            const float4 sg = stage_g[2 * u + q2];
+                            vjp_pair<kSoft>(sp, sg, pax, pay, paz, ma, gax, gay, gaz, eps2, tc2, cq,
+                                            cd, rax, ray, raz);
+                            vjp_pair<kSoft>(sp, sg, pbx, pby, pbz, mb, gbx, gby, gbz, eps2, tc2, cq,
+                                            cd, rbx, rby, rbz);
+                        }
+                    }
+                });
+                if (va) store3(out, n_out, perm[ba], rax, ray, raz);
+                if (vb) store3(out, n_out, perm[bb], rbx, rby, rbz);
                 continue;
             }
             const int kl = 1 << lk;
@@ -966,18 +1009,11 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(Acc acc, const 
                 gky = gy[b];
                 gkz = gz[b];
             }
+            const Box box = target_box(tv, px, py, pz, false, 0.f, 0.f, 0.f);
             float rx = 0.f, ry = 0.f, rz = 0.f;
-            float4 nxp, nxg;
-            fetch_vjp(st, lane, src, gx, gy, gz, nxp, nxg);
-            for (int base = 0; base < st.total; base += kWave) {
-                __syncthreads();
-                stage_p[lane] = nxp;
-                stage_g[lane] = nxg;
-                __syncthreads();
-                if (base + kWave < st.total) fetch_vjp(st, base + kWave + lane, src, gx, gy, gz, nxp, nxg);
-                const int cnt = min(kWave, st.total - base);
+            stream_sources<2>(st, box, cull2, lane, stage_p, stage_g, fetch_pg, [&](int n) {
                 if (lk == 0) {
-                    const int n4 = (cnt + 3) >> 2;
+                    const int n4 = (n + 3) >> 2;
                     for (int u = 0; u < n4; ++u) {
 #pragma unroll
                         for (int q4 = 0; q4 < 4; ++q4)
@@ -985,26 +1021,20 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(Acc acc, const 
                                             gkx, gky, gkz, eps2, tc2, cq, cd, rx, ry, rz);
                     }
                 } else {
-                    const int niter = (cnt + kl - 1) >> lk;
+                    const int niter = (n + kl - 1) >> lk;
                     for (int i = 0; i < niter; ++i) {
                         const int e = sub + (i << lk);
                         vjp_pair<kSoft>(stage_p[e], stage_g[e], px, py, pz, mk, gkx, gky, gkz, eps2,
                                         tc2, cq, cd, rx, ry, rz);
                     }
                 }
-            }
+            });
             for (int o = 1; o < kl; o <<= 1) {
                 rx += __shfl_xor(rx, o);
                 ry += __shfl_xor(ry, o);
                 rz += __shfl_xor(rz, o);
             }
-            const int pk = (tv && sub == 0) ? perm[t0 + t] : -1;
-            if (pk >= 0 && pk < n_out) {
-                const int64_t o3 = 3 * (int64_t)pk;
-                out[o3] = rx;
-                out[o3 + 1] = ry;
-                out[o3 + 2] = rz;
-            }
+            if (tv && sub == 0) store3(out, n_out, perm[t0 + t], rx, ry, rz);
         }
     }
 }

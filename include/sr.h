@@ -98,7 +98,9 @@ typedef struct sr_problem {
  *   i_d = clamp(floor(u * (nc/len)), 0, nc-1)   (u = w when periodic; NaN -> 0)
  *   cell = (i_x * nc_y + i_y) * nc_z + i_z
  *   offset = w - (lo + (i + 0.5) * (len/nc))    (distance from the cell centre)
- * Particles are ordered by (cell, input index). */
+ *   octant = 4 [off_x >= 0] + 2 [off_y >= 0] + [off_z >= 0]
+ * Particles are ordered by (cell, passive, octant, input index): within a
+ * cell the active particles come first, each group sorted by octant. */
 typedef struct sr_bin_layout {
     int32_t nc[3];
     int64_t ncell;
@@ -131,12 +133,14 @@ sr_status sr_bin(const float *pos, const float *mass, int64_t n, int64_t n_activ
                  const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, void *stream);
 
 /* Host only, no device access.  Device pointers into a workspace binned for
- * (n, prob). */
-sr_status sr_bin_view(const void *ws, int64_t n, const sr_problem *prob /*host*/,
+ * (n, n_active, prob). */
+sr_status sr_bin_view(const void *ws, int64_t n, int64_t n_active, const sr_problem *prob /*host*/,
                       sr_bin_layout *out /*host out*/);
 
 /* Short-range accelerations of the active particles: acc [n_active][3], in
- * input order, overwritten.  Bins first unless flags has SR_REUSE_BINS. */
+ * input order, overwritten.  Bins first unless flags has SR_REUSE_BINS (then
+ * n and n_active must be those of the binning: a workspace binned for other
+ * sizes computes nothing and sets SR_FLAG_NOT_BINNED). */
 sr_status sr_force(const float *pos, const float *mass, int64_t n, int64_t n_active,
                    const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, unsigned flags,
                    float *acc, void *stream);

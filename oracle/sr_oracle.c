@@ -120,16 +120,19 @@ static int bin_coord(float x, float lo, float len, int nc, int periodic, float *
 }
 
 /* cell_of[n] (input order), cell_start[ncell+1], perm[n] (binned slot ->
- * input index; stable: equal cells keep input order), off[3n] and
- * mass_binned are in binned order.  Cells are numbered (ix*ncy + iy)*ncz + iz. */
-int oracle_bin_reference(const float *pos, int64_t n, const float lo[3], const float len[3],
-                         int periodic, float r_s, int32_t *cell_of, int32_t *cell_start,
-                         int32_t *perm, float *off, uint32_t *flags_out)
+ * input index) and off[3n] (binned order).  Cells are numbered
+ * (ix*ncy + iy)*ncz + iz.  Slots are ordered by (cell, passive, octant, input
+ * index): passive = index >= n_active, octant = 4 [off_x >= 0] +
+ * 2 [off_y >= 0] + [off_z >= 0]. */
+int oracle_bin_reference(const float *pos, int64_t n, int64_t n_active, const float lo[3],
+                         const float len[3], int periodic, float r_s, int32_t *cell_of,
+                         int32_t *cell_start, int32_t *perm, float *off, uint32_t *flags_out)
 {
     int32_t nc[3];
     int rc = oracle_grid(len, r_s, periodic, nc);
     if (rc) return rc;
     if (periodic && (lo[0] != 0.0f || lo[1] != 0.0f || lo[2] != 0.0f)) return -3;
+    if (n_active < 0 || n_active > n) return -1;
     const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
     uint32_t flags = 0;
     float *o = (float *)malloc(sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
@@ -139,20 +142,27 @@ int oracle_bin_reference(const float *pos, int64_t n, const float lo[3], const f
             ic[d] = bin_coord(pos[3 * p + d], lo[d], len[d], nc[d], periodic, &o[3 * p + d], &flags);
         cell_of[p] = (int32_t)(((int64_t)ic[0] * nc[1] + ic[1]) * nc[2] + ic[2]);
     }
-    /* counting sort: counts, exclusive prefix sum, then placement in input order */
-    memset(cell_start, 0, sizeof(int32_t) * (size_t)(ncell + 1));
-    for (int64_t p = 0; p < n; ++p) cell_start[cell_of[p] + 1]++;
-    for (int64_t c = 0; c < ncell; ++c) cell_start[c + 1] += cell_start[c];
-    int32_t *cursor = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncell > 0 ? ncell : 1));
-    memcpy(cursor, cell_start, sizeof(int32_t) * (size_t)ncell);
+    /* counting sort on key = 16 cell + 8 passive + octant: counts, exclusive
+     * prefix sum, then placement in input order */
+    const int64_t nkey = 16 * ncell;
+    int64_t *kstart = (int64_t *)calloc((size_t)nkey + 1, sizeof(int64_t));
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t p = 0; p < n; ++p) {
-        int32_t slot = cursor[cell_of[p]]++;
+        int oct = (o[3 * p] >= 0.0f ? 4 : 0) + (o[3 * p + 1] >= 0.0f ? 2 : 0) + (o[3 * p + 2] >= 0.0f ? 1 : 0);
+        key[p] = 16 * (int64_t)cell_of[p] + (p >= n_active ? 8 : 0) + oct;
+        kstart[key[p] + 1]++;
+    }
+    for (int64_t k = 0; k < nkey; ++k) kstart[k + 1] += kstart[k];
+    for (int64_t c = 0; c <= ncell; ++c) cell_start[c] = (int32_t)kstart[16 * c];
+    for (int64_t p = 0; p < n; ++p) {
+        int32_t slot = (int32_t)kstart[key[p]]++;
         perm[slot] = (int32_t)p;
         off[3 * (int64_t)slot + 0] = o[3 * p + 0];
         off[3 * (int64_t)slot + 1] = o[3 * p + 1];
         off[3 * (int64_t)slot + 2] = o[3 * p + 2];
     }
-    free(cursor);
+    free(kstart);
+    free(key);
     free(o);
     if (flags_out) *flags_out = flags;
     return 0;

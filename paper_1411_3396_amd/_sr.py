@@ -66,7 +66,7 @@ def lib():
         L.sr_grid.argtypes = [p, p]
         L.sr_workspace_bytes.argtypes = [i64, p, p]
         L.sr_bin.argtypes = [p, p, i64, i64, p, p, C.c_size_t, p]
-        L.sr_bin_view.argtypes = [p, i64, p, p]
+        L.sr_bin_view.argtypes = [p, i64, i64, p, p]
         L.sr_force.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p]
         L.sr_force_vjp.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p, p]
         L.sr_count_pairs.argtypes = [i64, i64, p, p, C.c_size_t, p, p]
@@ -159,11 +159,12 @@ def bin(pos, mass, prob, n_active=None, ws=None, stream=None):  # noqa: A001 (pa
     return ws
 
 
-def bin_view(ws: torch.Tensor, n: int, prob) -> dict:
+def bin_view(ws: torch.Tensor, n: int, prob, n_active=None) -> dict:
     """Views of the binned arrays inside a workspace (int32/float32 tensors)."""
     out = BinLayout()
     P = as_problem(prob)
-    _check(lib().sr_bin_view(_ptr(ws), int(n), C.byref(P), C.byref(out)), "sr_bin_view")
+    n_active = int(n) if n_active is None else int(n_active)
+    _check(lib().sr_bin_view(_ptr(ws), int(n), n_active, C.byref(P), C.byref(out)), "sr_bin_view")
     base = ws.data_ptr()
 
     def view(ptr, count, dtype):

@@ -23,7 +23,7 @@ using namespace sr;
 namespace {
 
 constexpr int64_t kMaxParticles = (int64_t(1) << 31) - 1;
-constexpr int64_t kMaxCells = int64_t(1) << 30;
+constexpr int64_t kMaxCells = int64_t(1) << 26;  // cell << 4 fits the 31-bit sort key
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -98,14 +98,15 @@ SegParams seg_of(const sr_problem *p, const int32_t nc[3])
     return s;
 }
 
-Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles)
+Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_passive)
 {
     Layout L;
     L.N = N;
     L.NC = NC;
     L.B = B;
+    L.key_bits = any_passive ? 4 : 3;
     int bits = 1;
-    while ((int64_t(1) << bits) < NC) ++bits;
+    while ((int64_t(1) << bits) < (NC << L.key_bits)) ++bits;
     L.passes = (bits + 7) / 8;
     L.digit_bits = (bits + L.passes - 1) / L.passes;
     L.ntiles = std::max<int64_t>(1, (N + kRadixTile - 1) / kRadixTile);
@@ -122,6 +123,7 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles)
     L.hdr = take(kHdrWords * 4);
     L.seg = take((size_t)B * sizeof(SegParams));
     L.cell_of = take(n4);
+    L.skey = take(n4);
     L.keys[0] = take(n4);
     L.keys[1] = take(n4);
     L.vals[0] = take(n4);
@@ -164,7 +166,7 @@ sr_status prepare_single(int64_t n, int64_t n_active, const sr_problem *p, Singl
     s.seg = seg_of(p, s.nc);
     s.seg.n = (int32_t)n;
     s.seg.n_active = (int32_t)n_active;
-    s.L = make_layout(n, s.NC, 1, mom_tiles_of(n));
+    s.L = make_layout(n, s.NC, 1, mom_tiles_of(n), n_active < n);
     return SR_OK;
 }
 
@@ -528,10 +530,13 @@ sr_status sr_grid(const sr_problem *prob, int32_t nc[3])
 sr_status sr_workspace_bytes(int64_t n, const sr_problem *prob, size_t *bytes)
 {
     if (!bytes) return SR_E_ARG;
-    Single s;
-    const sr_status st = prepare_single(n, 0, prob, s);
+    // large enough with and without passive particles (the sort key differs)
+    Single all, some;
+    sr_status st = prepare_single(n, n, prob, all);
     if (st != SR_OK) return st;
-    *bytes = s.L.total;
+    st = prepare_single(n, n > 0 ? n - 1 : 0, prob, some);
+    if (st != SR_OK) return st;
+    *bytes = std::max(all.L.total, some.L.total);
     return SR_OK;
 }
 
@@ -549,11 +554,12 @@ sr_status sr_bin(const float *pos, const float *mass, int64_t n, int64_t n_activ
     return hip_status(dev_bin(a, pos, mass));
 }
 
-sr_status sr_bin_view(const void *ws, int64_t n, const sr_problem *prob, sr_bin_layout *out)
+sr_status sr_bin_view(const void *ws, int64_t n, int64_t n_active, const sr_problem *prob,
+                      sr_bin_layout *out)
 {
     if (!ws || !out) return SR_E_ARG;
     Single s;
-    const sr_status st = prepare_single(n, 0, prob, s);
+    const sr_status st = prepare_single(n, n_active, prob, s);
     if (st != SR_OK) return st;
     const char *w = static_cast<const char *>(ws);
     for (int d = 0; d < 3; ++d) out->nc[d] = s.nc[d];
@@ -701,7 +707,9 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets, const int64_t 
     P->total_active = out_off;
     P->summary = P->segs[0];
     P->summary.pc.softened = soft ? 1 : 0;
-    P->L = make_layout(offsets[B], cell_off, B, tile_off);
+    bool any_passive = false;
+    for (int b = 0; b < B; ++b) any_passive = any_passive || (n_active[b] < offsets[b + 1] - offsets[b]);
+    P->L = make_layout(offsets[B], cell_off, B, tile_off, any_passive);
     // per-subvolume momentum scratch sits at the end of the workspace
     const size_t mom_tail = align256((size_t)(3 * mom_tiles_of(offsets[B]) + 3) * 8) + 512;
     P->ws_bytes = std::max(P->L.total, single_max + mom_tail);

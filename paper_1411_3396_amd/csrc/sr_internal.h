@@ -71,11 +71,12 @@ struct Layout {
     int64_t NC = 0;    // cells (all segments)
     int32_t B = 1;     // segments
     int32_t passes = 0, digit_bits = 0;
+    int32_t key_bits = 3;   // low bits of the sort key below the cell: octant (+ passive flag)
     int64_t ntiles = 0;     // radix tiles
     int64_t table = 0;      // radix table entries (R * ntiles)
     int64_t item_cap = 0;   // upper bound on work items
     int64_t mom_tiles = 0;  // momentum partials
-    size_t hdr = 0, seg = 0, cell_of = 0, keys[2] = {0, 0}, vals[2] = {0, 0};
+    size_t hdr = 0, seg = 0, cell_of = 0, skey = 0, keys[2] = {0, 0}, vals[2] = {0, 0};
     size_t tab = 0, tabx = 0, nact = 0, start = 0, scan_tmp = 0;
     size_t bx = 0, by = 0, bz = 0, bm = 0, out_row = 0, gx = 0, gy = 0, gz = 0;
     size_t items = 0, info = 0, mom = 0;
@@ -85,7 +86,8 @@ struct Layout {
     // Tag of a binned workspace for these sizes (never zero).
     uint32_t magic() const
     {
-        uint32_t m = 0x9E3779B9u * (uint32_t)N ^ 0x85EBCA6Bu * (uint32_t)NC ^ 0xC2B2AE35u * (uint32_t)B;
+        uint32_t m = 0x9E3779B9u * (uint32_t)N ^ 0x85EBCA6Bu * (uint32_t)NC ^ 0xC2B2AE35u * (uint32_t)B ^
+                     0x27D4EB2Fu * (uint32_t)key_bits;
         return m ? m : 1u;
     }
 };

@@ -247,35 +247,43 @@ hipError_t scan_i32(const int *in, int *out, int64_t m, int *tmp, hipStream_t st
 
 // --------------------------------------------------------------- A1: cell index
 
+// Cell of each particle and its sort key: (cell, passive, octant), where the
+// octant holds the signs of the offsets from the cell centre, bit 2 = x.  With
+// key_bits = 3 there is no passive bit (every particle is active).
 template <class Acc>
 __global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restrict__ pos, int N,
-                                                   int *__restrict__ cell_of, uint32_t *hdr)
+                                                   int key_bits, int *__restrict__ cell_of,
+                                                   int *__restrict__ skey, uint32_t *hdr)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
     const SegParams &S = acc.get(acc.seg_of_particle(i));
     uint32_t fl = 0;
-    float o;
+    float ox, oy, oz;
     const int64_t p = 3 * (int64_t)i;
     const int ix = bin_coord(pos[p], S.lo[0], S.len[0], S.inv_len[0], S.h[0], S.inv_h[0], S.nc[0],
-                             S.periodic, o, fl);
+                             S.periodic, ox, fl);
     const int iy = bin_coord(pos[p + 1], S.lo[1], S.len[1], S.inv_len[1], S.h[1], S.inv_h[1],
-                             S.nc[1], S.periodic, o, fl);
+                             S.nc[1], S.periodic, oy, fl);
     const int iz = bin_coord(pos[p + 2], S.lo[2], S.len[2], S.inv_len[2], S.h[2], S.inv_h[2],
-                             S.nc[2], S.periodic, o, fl);
-    cell_of[i] = S.cell_off + (ix * S.nc[1] + iy) * S.nc[2] + iz;
+                             S.nc[2], S.periodic, oz, fl);
+    const int cell = S.cell_off + (ix * S.nc[1] + iy) * S.nc[2] + iz;
+    const int oct = (ox >= 0.f ? 4 : 0) | (oy >= 0.f ? 2 : 0) | (oz >= 0.f ? 1 : 0);
+    const int passive = (i - S.part_off < S.n_active) ? 0 : 1;
+    cell_of[i] = cell;
+    skey[i] = (cell << key_bits) | (key_bits > 3 ? passive << 3 : 0) | oct;
     if (fl) atomicOr(&hdr[kHdrFlags], fl);
 }
 
 // Cell starts from the sorted cell keys: slot b starts every cell in
 // (key[b-1], key[b]]; slot N closes the list.  Each entry is written once.
 __global__ __launch_bounds__(256) void k_cell_bounds(const int *__restrict__ key, int N, int NC,
-                                                     int *__restrict__ start)
+                                                     int key_bits, int *__restrict__ start)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b > N) return;
-    const int lo = (b == 0) ? -1 : key[b - 1];
-    const int hi = (b == N) ? NC : key[b];
+    const int lo = (b == 0) ? -1 : (key[b - 1] >> key_bits);
+    const int hi = (b == N) ? NC : (key[b] >> key_bits);
     for (int c = lo + 1; c <= hi; ++c) start[c] = b;
 }
 
@@ -356,7 +364,7 @@ __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__res
                                                 float *__restrict__ bx, float *__restrict__ by,
                                                 float *__restrict__ bz, float *__restrict__ bm,
                                                 int *__restrict__ out_row, int *__restrict__ nact,
-                                                uint32_t *hdr, uint32_t magic)
+                                                int key_bits, uint32_t *hdr, uint32_t magic)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b == 0) hdr[kHdrMagic] = magic;
@@ -381,8 +389,8 @@ __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__res
     out_row[b] = act ? S.out_off + li : -1;
     // active particles lead their cell (input order): the last one records the count
     if (act) {
-        const int c = key[b];
-        bool last = (b + 1 == N) || key[b + 1] != c;
+        const int c = key[b] >> key_bits;
+        bool last = (b + 1 == N) || (key[b + 1] >> key_bits) != c;
         if (!last) last = !(perm[b + 1] - S.part_off < S.n_active);
         if (last) nact[c] = b + 1 - start[c];
     }
@@ -1238,12 +1246,13 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
     if ((e = fill_u32(at<uint32_t>(a, L.nact), L.NC, 0, a.st)) != hipSuccess) return e;
     if (L.N == 0) return hipSuccess;
     e = with_acc(a, [&](auto acc) -> hipError_t {
-        k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, (int)L.N, at<int>(a, L.cell_of),
+        k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, (int)L.N, L.key_bits,
+                                                             at<int>(a, L.cell_of), at<int>(a, L.skey),
                                                              at<uint32_t>(a, L.hdr));
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    const int *kin = at<int>(a, L.cell_of);
+    const int *kin = at<int>(a, L.skey);
     const int *vin = nullptr;
     const int R = 1 << L.digit_bits;
     for (int p = 0; p < L.passes; ++p) {
@@ -1264,13 +1273,13 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
         vin = vout;
     }
     k_cell_bounds<<<blocks_for(L.N + 1, 256), 256, 0, a.st>>>(at<int>(a, L.sorted_keys()), (int)L.N,
-                                                              (int)L.NC, at<int>(a, L.start));
+                                                              (int)L.NC, L.key_bits, at<int>(a, L.start));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return with_acc(a, [&](auto acc) -> hipError_t {
         k_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
             acc, (int)L.N, at<int>(a, L.perm()), at<int>(a, L.sorted_keys()), at<int>(a, L.start), pos,
             mass, at<float>(a, L.bx), at<float>(a, L.by), at<float>(a, L.bz), at<float>(a, L.bm),
-            at<int>(a, L.out_row), at<int>(a, L.nact), at<uint32_t>(a, L.hdr), L.magic());
+            at<int>(a, L.out_row), at<int>(a, L.nact), L.key_bits, at<uint32_t>(a, L.hdr), L.magic());
         return hipGetLastError();
     });
 }

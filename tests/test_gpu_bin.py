@@ -17,9 +17,9 @@ def check_bins(w):
     announce(f"bin {w.name} n={w.n} n_active={w.n_active}")
     pos, mass = to_dev(w.pos), to_dev(w.mass)
     ws = sr.bin(pos, mass, w.problem, w.n_active)
-    v = sr.bin_view(ws, w.n, w.problem)
+    v = sr.bin_view(ws, w.n, w.problem, w.n_active)
     torch.cuda.synchronize()
-    ref = oracle.bin_reference(w.pos, w.problem)
+    ref = oracle.bin_reference(w.pos, w.problem, w.n_active)
     assert tuple(v["nc"]) == tuple(ref["nc"])
     np.testing.assert_array_equal(v["cell_of"].cpu().numpy(), ref["cell_of"])
     np.testing.assert_array_equal(v["cell_start"].cpu().numpy(), ref["cell_start"])

@@ -390,15 +390,22 @@ def test_two_body_jacobian():
 
 # ---------------------------------------------------------------- binning rule
 
-def _check_bins(pos, P, res):
+def _check_bins(pos, P, res, n_active=None):
     n = pos.shape[0]
+    n_active = n if n_active is None else n_active
     nc = res["nc"].astype(np.int64)
     cell_of = res["cell_of"].astype(np.int64)
     perm = res["perm"].astype(np.int64)
     start = res["cell_start"].astype(np.int64)
     ncell = int(np.prod(nc))
     assert np.array_equal(np.sort(perm), np.arange(n))
-    assert np.array_equal(perm, np.argsort(cell_of, kind="stable"))
+    # order: cell, then active before passive, then octant of the offset, then input index
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    off_in = res["off"][inv]
+    octant = 4 * (off_in[:, 0] >= 0) + 2 * (off_in[:, 1] >= 0) + (off_in[:, 2] >= 0)
+    passive = (np.arange(n) >= n_active).astype(np.int64)
+    assert np.array_equal(perm, np.lexsort((np.arange(n), octant, passive, cell_of)))
     assert np.array_equal(start, np.concatenate([[0], np.cumsum(np.bincount(cell_of, minlength=ncell))]))
     # geometry, in float64: the cell brackets the (wrapped) coordinate up to rounding
     L = np.array(P.len, np.float64)
@@ -435,8 +442,8 @@ def test_bin_reference_rules(name):
         w = synth.clustered_box(40000, 30.0, 40, 2)
     else:
         w = synth.slab_with_ghosts(30, 3.0, 50, 3)
-    res = oracle.bin_reference(w.pos, w.problem)
-    _check_bins(w.pos, w.problem, res)
+    res = oracle.bin_reference(w.pos, w.problem, w.n_active)
+    _check_bins(w.pos, w.problem, res, w.n_active)
     assert res["flags"] == 0
 
 
@@ -486,3 +493,5 @@ def test_bin_reference_float32_formula():
     cell = (i[:, 0] * nc[1] + i[:, 1]) * nc[2] + i[:, 2]
     assert np.array_equal(res["cell_of"], cell)
     assert np.array_equal(res["off"], off[res["perm"]])
+    octant = 4 * (off[:, 0] >= 0) + 2 * (off[:, 1] >= 0) + (off[:, 2] >= 0)
+    assert np.array_equal(res["perm"], np.lexsort((np.arange(len(cell)), octant, cell)))

@@ -179,7 +179,7 @@ sr_status check_ws(const void *ws, size_t ws_bytes, const Layout &L)
 }
 
 std::atomic<int> g_waves_per_cu_default{32};
-std::atomic<int> g_targets_per_lane_default{1};
+std::atomic<int> g_targets_per_lane_default{2};
 std::atomic<int> g_occupancy_default{0};
 
 // Launch defaults may be overridden for experiments: SR_WAVES_PER_CU, SR_TARGETS_PER_LANE,

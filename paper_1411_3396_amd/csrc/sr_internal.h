@@ -57,6 +57,7 @@ enum HdrWord : int {
     kHdrFlags = 0,
     kHdrNItems = 1,
     kHdrMagic = 2,          // written by the last binning kernel: bins are ready
+    kHdrMassInfo = 3,       // 0 if every mass equals the first one
     kHdrBucketCount = 64,   // [32]
     kHdrBucketBase = 128,   // [33]
     kHdrBucketCursor = 192, // [32]

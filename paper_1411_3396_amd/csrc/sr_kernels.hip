@@ -383,7 +383,9 @@ __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__res
     bx[b] = ox;
     by[b] = oy;
     bz[b] = oz;
-    bm[b] = mass[i];
+    const float mi = mass[i];
+    bm[b] = mi;
+    if (!(mi == mass[0])) atomicOr(&hdr[kHdrMassInfo], 1u);  // not every mass equal
     const int li = i - S.part_off;
     const bool act = li < S.n_active;
     out_row[b] = act ? S.out_off + li : -1;
@@ -669,8 +671,9 @@ __device__ __forceinline__ float horner4(const float *q, float t)
     return fmaf(p, t, q[0]);
 }
 
-// One forward pair term: acc += m_j d f_SR(s) for t = s + eps^2 < tc2.
-template <bool kSoft>
+// One forward pair term: acc += m_j d f_SR(s) for t = s + eps^2 < tc2.  With
+// kUM (every mass equal) the mass is applied once to the sum instead.
+template <bool kSoft, bool kUM>
 __device__ __forceinline__ void force_pair(const float4 s, float px, float py, float pz, float eps2,
                                            float tc2, const float *cq, float &ax, float &ay,
                                            float &az)
@@ -681,14 +684,15 @@ __device__ __forceinline__ void force_pair(const float4 s, float px, float py, f
     const float q2 = qi * qi;
     const float f = fmaf(q2, qi, -horner5(cq, tt));
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-    const float w = in ? s.w * f : 0.f;
+    const float w = in ? (kUM ? f : s.w * f) : 0.f;
     ax = fmaf(w, dx, ax);
     ay = fmaf(w, dy, ay);
     az = fmaf(w, dz, az);
 }
 
 // One adjoint pair term: r += f u + 2 f' (u.d) d, u = m_k g_j - m_j g_k.
-template <bool kSoft>
+// With kUM, u / m = g_j - g_k is summed and the mass applied once at the end.
+template <bool kSoft, bool kUM>
 __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float px, float py,
                                          float pz, float mk, float gkx, float gky, float gkz,
                                          float eps2, float tc2, const float *cq, const float *cd,
@@ -702,9 +706,9 @@ __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float 
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
     const float f = in ? q3 - horner5(cq, tt) : 0.f;
     const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
-    const float ux = fmaf(mk, gj.x, -s.w * gkx);
-    const float uy = fmaf(mk, gj.y, -s.w * gky);
-    const float uz = fmaf(mk, gj.z, -s.w * gkz);
+    const float ux = kUM ? gj.x - gkx : fmaf(mk, gj.x, -s.w * gkx);
+    const float uy = kUM ? gj.y - gky : fmaf(mk, gj.y, -s.w * gky);
+    const float uz = kUM ? gj.z - gkz : fmaf(mk, gj.z, -s.w * gkz);
     const float c = fp2 * fmaf(ux, dx, fmaf(uy, dy, uz * dz));
     rx = fmaf(c, dx, fmaf(f, ux, rx));
     ry = fmaf(c, dy, fmaf(f, uy, ry));
@@ -845,13 +849,14 @@ __device__ __forceinline__ void store3(float *__restrict__ out, int n_out, int r
 //    staged source twice;
 //  - sparse items: 2^lk lanes per target stride over the sources and reduce
 //    with cross-lane butterflies.
-template <class Acc, bool kSoft, int kOcc>
-__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
-    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
-    const int *__restrict__ out_row, float *__restrict__ out, int n_out)
+template <class Acc, bool kSoft, bool kUM>
+__device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restrict__ items,
+                                            uint32_t *hdr, const int *__restrict__ start,
+                                            const Src &src, const int *__restrict__ out_row,
+                                            float *__restrict__ out, int n_out, float4 *stage)
 {
-    __shared__ float4 stage[kWave];
     const int lane = threadIdx.x;
+    const float m0 = kUM ? src.m[0] : 1.0f;
     const int64_t n_items = hdr[kHdrNItems];
     const int q0 = blockIdx.x & (kQueues - 1);
     for (int qq = 0; qq < kQueues; ++qq) {
@@ -890,13 +895,13 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
 #pragma unroll
                         for (int q4 = 0; q4 < 4; ++q4) {
                             const float4 sj = stage[4 * u + q4];
-                            force_pair<kSoft>(sj, pax, pay, paz, eps2, tc2, cq, aax, aay, aaz);
-                            force_pair<kSoft>(sj, pbx, pby, pbz, eps2, tc2, cq, abx, aby, abz);
+                            force_pair<kSoft, kUM>(sj, pax, pay, paz, eps2, tc2, cq, aax, aay, aaz);
+                            force_pair<kSoft, kUM>(sj, pbx, pby, pbz, eps2, tc2, cq, abx, aby, abz);
                         }
                     }
                 });
-                if (va) store3(out, n_out, out_row[t0 + lane], aax, aay, aaz);
-                if (vb) store3(out, n_out, out_row[t0 + kWave + lane], abx, aby, abz);
+                if (va) store3(out, n_out, out_row[t0 + lane], m0 * aax, m0 * aay, m0 * aaz);
+                if (vb) store3(out, n_out, out_row[t0 + kWave + lane], m0 * abx, m0 * aby, m0 * abz);
                 continue;
             }
             const int kl = 1 << lk;
@@ -916,13 +921,13 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
                     for (int u = 0; u < n8; ++u) {
 #pragma unroll
                         for (int q8 = 0; q8 < 8; ++q8)
-                            force_pair<kSoft>(stage[8 * u + q8], px, py, pz, eps2, tc2, cq, ax, ay, az);
+                            force_pair<kSoft, kUM>(stage[8 * u + q8], px, py, pz, eps2, tc2, cq, ax, ay, az);
                     }
                 } else {
                     const int niter = (n + kl - 1) >> lk;
 #pragma unroll 2
                     for (int i = 0; i < niter; ++i)
-                        force_pair<kSoft>(stage[sub + (i << lk)], px, py, pz, eps2, tc2, cq, ax, ay, az);
+                        force_pair<kSoft, kUM>(stage[sub + (i << lk)], px, py, pz, eps2, tc2, cq, ax, ay, az);
                 }
             });
             for (int o = 1; o < kl; o <<= 1) {
@@ -930,9 +935,21 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
                 ay += __shfl_xor(ay, o);
                 az += __shfl_xor(az, o);
             }
-            if (tv && sub == 0) store3(out, n_out, out_row[t0 + t], ax, ay, az);
+            if (tv && sub == 0) store3(out, n_out, out_row[t0 + t], m0 * ax, m0 * ay, m0 * az);
         }
     }
+}
+
+template <class Acc, bool kSoft, int kOcc>
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
+    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
+    const int *__restrict__ out_row, float *__restrict__ out, int n_out)
+{
+    __shared__ float4 stage[kWave];
+    if (hdr[kHdrMassInfo] == 0)
+        force_items<Acc, kSoft, true>(acc, items, hdr, start, src, out_row, out, n_out, stage);
+    else
+        force_items<Acc, kSoft, false>(acc, items, hdr, start, src, out_row, out, n_out, stage);
 }
 
 // ------------------------------------------------------------- adjoint kernel
@@ -940,15 +957,17 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
 // Adjoint: grad[perm] = sum over the stencil of f u + 2 f' (u.d) d,
 // u = m_k g_j - m_j g_k.  Same item shapes as the forward kernel; every
 // source stages (x, y, z, m) and (g, 0).
-template <class Acc, bool kSoft, int kOcc>
-__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
-    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
-    const float *__restrict__ gx, const float *__restrict__ gy, const float *__restrict__ gz,
-    const int *__restrict__ perm, float *__restrict__ out, int n_out)
+template <class Acc, bool kSoft, bool kUM>
+__device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict__ items,
+                                          uint32_t *hdr, const int *__restrict__ start,
+                                          const Src &src, const float *__restrict__ gx,
+                                          const float *__restrict__ gy,
+                                          const float *__restrict__ gz,
+                                          const int *__restrict__ perm, float *__restrict__ out,
+                                          int n_out, float4 *stage_p, float4 *stage_g)
 {
-    __shared__ float4 stage_p[kWave];
-    __shared__ float4 stage_g[kWave];
     const int lane = threadIdx.x;
+    const float m0 = kUM ? src.m[0] : 1.0f;
     const int64_t n_items = hdr[kHdrNItems];
     const int q0 = blockIdx.x & (kQueues - 1);
     for (int qq = 0; qq < kQueues; ++qq) {
@@ -992,15 +1011,15 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
                         for (int q2 = 0; q2 < 2; ++q2) {
                             const float4 sp = stage_p[2 * u + q2];
                             const float4 sg = stage_g[2 * u + q2];
-                            vjp_pair<kSoft>(sp, sg, pax, pay, paz, ma, gax, gay, gaz, eps2, tc2, cq,
+                            vjp_pair<kSoft, kUM>(sp, sg, pax, pay, paz, ma, gax, gay, gaz, eps2, tc2, cq,
                                             cd, rax, ray, raz);
-                            vjp_pair<kSoft>(sp, sg, pbx, pby, pbz, mb, gbx, gby, gbz, eps2, tc2, cq,
+                            vjp_pair<kSoft, kUM>(sp, sg, pbx, pby, pbz, mb, gbx, gby, gbz, eps2, tc2, cq,
                                             cd, rbx, rby, rbz);
                         }
                     }
                 });
-                if (va) store3(out, n_out, perm[ba], rax, ray, raz);
-                if (vb) store3(out, n_out, perm[bb], rbx, rby, rbz);
+                if (va) store3(out, n_out, perm[ba], m0 * rax, m0 * ray, m0 * raz);
+                if (vb) store3(out, n_out, perm[bb], m0 * rbx, m0 * rby, m0 * rbz);
                 continue;
             }
             const int kl = 1 << lk;
@@ -1025,14 +1044,14 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
                     for (int u = 0; u < n4; ++u) {
 #pragma unroll
                         for (int q4 = 0; q4 < 4; ++q4)
-                            vjp_pair<kSoft>(stage_p[4 * u + q4], stage_g[4 * u + q4], px, py, pz, mk,
+                            vjp_pair<kSoft, kUM>(stage_p[4 * u + q4], stage_g[4 * u + q4], px, py, pz, mk,
                                             gkx, gky, gkz, eps2, tc2, cq, cd, rx, ry, rz);
                     }
                 } else {
                     const int niter = (n + kl - 1) >> lk;
                     for (int i = 0; i < niter; ++i) {
                         const int e = sub + (i << lk);
-                        vjp_pair<kSoft>(stage_p[e], stage_g[e], px, py, pz, mk, gkx, gky, gkz, eps2,
+                        vjp_pair<kSoft, kUM>(stage_p[e], stage_g[e], px, py, pz, mk, gkx, gky, gkz, eps2,
                                         tc2, cq, cd, rx, ry, rz);
                     }
                 }
@@ -1042,9 +1061,25 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
                 ry += __shfl_xor(ry, o);
                 rz += __shfl_xor(rz, o);
             }
-            if (tv && sub == 0) store3(out, n_out, perm[t0 + t], rx, ry, rz);
+            if (tv && sub == 0) store3(out, n_out, perm[t0 + t], m0 * rx, m0 * ry, m0 * rz);
         }
     }
+}
+
+template <class Acc, bool kSoft, int kOcc>
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
+    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
+    const float *__restrict__ gx, const float *__restrict__ gy, const float *__restrict__ gz,
+    const int *__restrict__ perm, float *__restrict__ out, int n_out)
+{
+    __shared__ float4 stage_p[kWave];
+    __shared__ float4 stage_g[kWave];
+    if (hdr[kHdrMassInfo] == 0)
+        vjp_items<Acc, kSoft, true>(acc, items, hdr, start, src, gx, gy, gz, perm, out, n_out,
+                                    stage_p, stage_g);
+    else
+        vjp_items<Acc, kSoft, false>(acc, items, hdr, start, src, gx, gy, gz, perm, out, n_out,
+                                     stage_p, stage_g);
 }
 
 // Ordered pairs (active target, source) with 0 < s < r_s^2, decided exactly as

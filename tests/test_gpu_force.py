@@ -183,3 +183,14 @@ def test_launch_configs_agree_bitwise():
             assert np.array_equal(gr.view(np.uint32), gref.view(np.uint32)), (waves, tpl, occ)
     finally:
         sr.launch_config(*saved)
+
+
+def test_equal_masses_other_than_one():
+    # every mass equal (0.7): the kernels apply the mass once per sum
+    w = synth.clustered_box(60000, 32.0, 30, 17)
+    w.mass = np.full(w.n, 0.7, np.float32)
+    announce("equal masses 0.7")
+    assert_force_close(gpu_force(w), oracle_force(w), what="m=0.7")
+    g = synth.cotangent(w.n, 3)
+    gr = sr.force_vjp(to_dev(w.pos), to_dev(w.mass), w.problem, to_dev(g)).cpu().numpy()
+    assert oracle.rms_rel(gr, oracle.vjp(w.pos, w.mass, w.n, w.problem, g)) <= 1e-4

@@ -109,6 +109,35 @@ def batch_comparison(reps: int = 5):
             "waves_per_cu": info["waves_per_cu"]}
 
 
+def block_comparison(w, pos, mass, acc_mono, reps: int = 3):
+    """Overlapping data blocks of the same domain: equal partitions in grid
+    units, each solved as one batched launch and reconciled."""
+    import torch
+
+    from paper_1411_3396_amd.blocks import BlockForce, equal_blocks, grid_units
+
+    ng = grid_units(w.problem)
+    ref = acc_mono.double()
+    out = []
+    for nbx in (2, 4):
+        blocks = equal_blocks(ng, nbx, nbx)
+        bf = BlockForce(w.problem, blocks, w.n, w.n_active, ng=ng, device=pos.device)
+        acc = bf.forward(pos, mass)  # first run: batch plan tuning
+        times = {}
+        for _ in range(reps):
+            acc = bf.forward(pos, mass, times=times)
+        diff = (acc.double() - ref).norm() / ref.norm()
+        out.append({"blocks": f"{nbx}x{nbx}", "members_per_particle": round(bf.plan.members / w.n, 4),
+                    "ms": {k: round(v / reps, 3) for k, v in times.items()},
+                    "ms_total": round(sum(times.values()) / reps, 3),
+                    "rel_diff_vs_single_domain": float(diff)})
+        log(f"blocks {nbx}x{nbx}: {out[-1]}")
+        bf.close()
+        del bf, acc
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +147,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-blocks", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="time the pair kernels under every launch configuration "
                          "(waves per CU, targets per lane, occupancy variant); one JSON line each")
@@ -290,6 +320,10 @@ def main() -> int:
     if not args.no_batch:
         log("batched vs per-subvolume")
         result["batch"] = batch_comparison()
+    if not args.no_blocks and not w.problem.periodic:
+        log("overlapping data blocks")
+        result["blocks"] = block_comparison(w, pos, mass, acc)
+        result["blocks_force_ms_single_domain"] = round(phase["bin"] + phase["force"], 3)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, g_np, args.cpu_seconds)

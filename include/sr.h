@@ -204,6 +204,74 @@ sr_status sr_batch_plan_destroy(sr_batch_plan *plan);
  * chosen by the tuner (writes a NUL-terminated JSON string). */
 sr_status sr_batch_plan_info(const sr_batch_plan *plan, char *buf /*host*/, size_t buf_bytes);
 
+/* Overlapping data blocks (Sec. 2.1): a domain's x-y extent is tiled by
+ * rectangles in whole grid units, and each block is solved as an independent
+ * open-domain problem holding its own active particles plus, as passive
+ * copies, every particle within r_s of its rectangle in x and y (z is not
+ * cut).  Afterwards each active particle's result is taken from its home
+ * block and the duplicated passive copies are dropped.
+ *
+ * A rectangle [gx0, gx1) x [gy0, gy1) counts grid units of the domain: the
+ * edge of unit g along an axis is lo + g * len / ng (rounded once to
+ * float32).  The rectangles must tile [0, ng_x) x [0, ng_y) without gaps or
+ * overlaps; the outer ones reach to infinity, so every particle, even one
+ * outside the domain, has exactly one home.  Membership: a particle belongs
+ * to block b if it lies within r_s (1 + 1e-5) of b's rectangle in x and in y;
+ * it is active in b when it is active in the domain and b is its home.
+ * Within a block the active members come first, each group in domain index
+ * order.  Block b's problem is the domain with x and y cut to its widened
+ * rectangle (sr_blocks_problems).  Open domains only (SR_E_UNSUPPORTED for
+ * periodic ones); at most 1024 blocks. */
+typedef struct sr_block {
+    int32_t gx0, gx1, gy0, gy1;
+} sr_block;
+
+typedef struct sr_blocks_plan sr_blocks_plan;
+
+/* Host only.  Validate the tiling for n particles (the first n_active
+ * active) and lay out the workspace.  capacity bounds the total number of
+ * memberships (0: the worst case, n times the most widened rectangles any
+ * point can lie in). */
+sr_status sr_blocks_plan_create(const sr_problem *domain /*host*/, const int32_t *ng /*host [2]*/,
+                                int32_t nb, const sr_block *blocks /*host [nb]*/, int64_t n,
+                                int64_t n_active, int64_t capacity,
+                                sr_blocks_plan **plan /*host out*/, size_t *ws_bytes /*host out*/);
+sr_status sr_blocks_plan_destroy(sr_blocks_plan *plan);
+
+/* Host only.  The nb block problems (open domains). */
+sr_status sr_blocks_problems(const sr_blocks_plan *plan, sr_problem *out /*host [nb]*/);
+
+/* Assign particles to blocks.  Writes the total number of memberships to
+ * *members and, per block, its active and passive member counts to
+ * counts[2b], counts[2b+1] (host).  Waits for `stream` (the counts size the
+ * block arrays).  If the memberships exceed the plan's capacity it returns
+ * SR_E_WORKSPACE with *members set to the capacity needed.  The workspace
+ * then holds the partition for the calls below until it is used otherwise. */
+sr_status sr_blocks_partition(sr_blocks_plan *plan, const float *pos, void *ws, size_t ws_bytes,
+                              int64_t *members /*host out*/, int64_t *counts /*host out [2 nb]*/,
+                              void *stream);
+
+/* Block inputs, blocks back to back in block order: bpos [members][3],
+ * bmass [members], src [members] (nullable) = domain index of each member.
+ * With g [n_active][3] (nullable, together with bg) also the cotangent rows
+ * of the block outputs: bg [n_active][3], block b's active rows first after
+ * those of blocks < b. */
+sr_status sr_blocks_gather(const sr_blocks_plan *plan, const float *pos, const float *mass,
+                           const float *g, const void *ws, size_t ws_bytes, float *bpos,
+                           float *bmass, float *bg, int32_t *src, void *stream);
+
+/* Reconcile block accelerations bacc [n_active][3] (the block outputs back
+ * to back, as sr_batch_force writes them) into acc [n_active][3], domain
+ * order: each active particle receives the row of its home block, once. */
+sr_status sr_blocks_reconcile(const sr_blocks_plan *plan, const void *ws, size_t ws_bytes,
+                              const float *bacc, float *acc, void *stream);
+
+/* Reconcile block position gradients bgrad [members][3] (every member's row,
+ * blocks back to back) into grad [n][3]: each particle receives the sum over
+ * its copies, in block order. */
+sr_status sr_blocks_reconcile_grad(const sr_blocks_plan *plan, const void *ws, size_t ws_bytes,
+                                   const float *bgrad, float *grad, void *stream);
+
 /* Host only.  Process-wide launch parameters of the single-problem entry
  * points (batch plans tune their own):
  *   waves_per_cu      persistent grid of the pair kernels, in waves per compute

@@ -28,7 +28,9 @@ FLAG_OUT_OF_DOMAIN = 2
 EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "sr_bin",
            "sr_bin_view", "sr_force", "sr_force_vjp", "sr_count_pairs", "sr_momentum",
            "sr_ws_flags", "sr_batch_plan_create", "sr_batch_force", "sr_batch_plan_destroy",
-           "sr_batch_plan_info", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
+           "sr_batch_plan_info", "sr_blocks_plan_create", "sr_blocks_plan_destroy",
+           "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
+           "sr_blocks_reconcile_grad", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
 
 
 class SRError(RuntimeError):
@@ -40,6 +42,10 @@ class SRError(RuntimeError):
 class Problem(C.Structure):
     _fields_ = [("lo", C.c_float * 3), ("len", C.c_float * 3), ("periodic", C.c_int32),
                 ("r_s", C.c_float), ("eps", C.c_float), ("poly", C.c_float * 6)]
+
+
+class Block(C.Structure):
+    _fields_ = [("gx0", C.c_int32), ("gx1", C.c_int32), ("gy0", C.c_int32), ("gy1", C.c_int32)]
 
 
 class BinLayout(C.Structure):
@@ -76,6 +82,13 @@ def lib():
         L.sr_batch_force.argtypes = [p, p, p, p, C.c_size_t, p, p, u, p]
         L.sr_batch_plan_destroy.argtypes = [p]
         L.sr_batch_plan_info.argtypes = [p, p, C.c_size_t]
+        L.sr_blocks_plan_create.argtypes = [p, p, C.c_int32, p, i64, i64, i64, p, p]
+        L.sr_blocks_plan_destroy.argtypes = [p]
+        L.sr_blocks_problems.argtypes = [p, p]
+        L.sr_blocks_partition.argtypes = [p, p, p, C.c_size_t, p, p, p]
+        L.sr_blocks_gather.argtypes = [p, p, p, p, p, C.c_size_t, p, p, p, p, p]
+        L.sr_blocks_reconcile.argtypes = [p, p, C.c_size_t, p, p, p]
+        L.sr_blocks_reconcile_grad.argtypes = [p, p, C.c_size_t, p, p, p]
         L.sr_launch_config.argtypes = [C.c_int, C.c_int, C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
@@ -120,6 +133,13 @@ def _dev_f32(t: torch.Tensor, name: str, shape: Sequence[int]) -> torch.Tensor:
     if tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
     return t.contiguous()
+
+
+def _out_f32(t: torch.Tensor, name: str, shape: Sequence[int]) -> torch.Tensor:
+    """An output tensor is written in place, so it must already be contiguous."""
+    if isinstance(t, torch.Tensor) and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _dev_f32(t, name, shape)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -197,7 +217,7 @@ def force(pos, mass, prob, n_active=None, ws=None, reuse_bins=False, out=None, s
     if out is None:
         out = torch.empty((n_active, 3), dtype=torch.float32, device=pos.device)
     else:
-        out = _dev_f32(out, "out", (n_active, 3))
+        out = _out_f32(out, "out", (n_active, 3))
     _check(lib().sr_force(_ptr(pos), _ptr(mass), n, n_active, C.byref(P), _ptr(ws), ws.numel(),
                           REUSE_BINS if reuse_bins else 0, _ptr(out), _stream(stream)), "sr_force")
     return out
@@ -218,7 +238,7 @@ def force_vjp(pos, mass, prob, g, n_active=None, ws=None, reuse_bins=False, out=
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
     else:
-        out = _dev_f32(out, "out", (n, 3))
+        out = _out_f32(out, "out", (n, 3))
     _check(lib().sr_force_vjp(_ptr(pos), _ptr(mass), n, n_active, C.byref(P), _ptr(ws), ws.numel(),
                               REUSE_BINS if reuse_bins else 0, _ptr(g), _ptr(out), _stream(stream)),
            "sr_force_vjp")
@@ -311,7 +331,7 @@ class BatchPlan:
         n = int(self.offsets[-1])
         pos = _dev_f32(pos, "pos", (n, 3))
         mass = _dev_f32(mass, "mass", (n,))
-        acc = _dev_f32(acc, "acc", (self.total_active, 3))
+        acc = _out_f32(acc, "acc", (self.total_active, 3))
         if momentum is not None and (momentum.dtype != torch.float64 or momentum.numel() != 3 * self.B):
             raise ValueError("momentum must be float64 [B, 3]")
         _check(lib().sr_batch_force(self._plan, _ptr(pos), _ptr(mass), _ptr(ws), ws.numel(), _ptr(acc),
@@ -350,6 +370,111 @@ def batch_force(pos, mass, offsets, problems, n_active=None, mode="graph", momen
     plan.run(pos, mass, ws, acc, mom, mode)
     plan.close()
     return (acc, mom) if momentum else acc
+
+
+class BlocksPlan:
+    """Overlapping data blocks of one open domain (sr_blocks_*): partition,
+    gather of the block inputs, reconcile of the block results.
+
+    blocks: rectangles (gx0, gx1, gy0, gy1) in grid units tiling
+    [0, ng[0]) x [0, ng[1]).  The workspace holds the partition between the
+    calls, so it serves one partition at a time."""
+
+    def __init__(self, domain, ng, blocks, n: int, n_active: Optional[int] = None,
+                 capacity: int = 0):
+        import numpy as np
+
+        self.nb = len(blocks)
+        arr = (Block * max(1, self.nb))(*[Block(*[int(v) for v in b]) for b in blocks])
+        ngs = (C.c_int32 * 2)(int(ng[0]), int(ng[1]))
+        self.n = int(n)
+        self.n_active = self.n if n_active is None else int(n_active)
+        self._plan = C.c_void_p()
+        nbytes = C.c_size_t()
+        _check(lib().sr_blocks_plan_create(C.byref(as_problem(domain)), ngs, self.nb, arr, self.n,
+                                           self.n_active, int(capacity), C.byref(self._plan),
+                                           C.byref(nbytes)), "sr_blocks_plan_create")
+        self.ws_bytes = int(nbytes.value)
+        self.blocks = [tuple(int(v) for v in b) for b in blocks]
+        self.members = -1
+        self.counts = np.zeros((self.nb, 2), np.int64)
+
+    def problems(self) -> list:
+        out = (Problem * self.nb)()
+        _check(lib().sr_blocks_problems(self._plan, out), "sr_blocks_problems")
+        return list(out)
+
+    def partition(self, pos, ws, stream=None):
+        """Assign particles to blocks; returns counts [nb, 2] (active, passive).
+        Raises SRError(SR_E_WORKSPACE) with .needed set when the plan's
+        capacity is too small."""
+        import numpy as np
+
+        pos = _dev_f32(pos, "pos", (self.n, 3))
+        members = C.c_int64()
+        counts = np.zeros((self.nb, 2), np.int64)
+        code = lib().sr_blocks_partition(self._plan, _ptr(pos), _ptr(ws), ws.numel(), C.byref(members),
+                                         counts.ctypes.data_as(C.c_void_p), _stream(stream))
+        if code != SR_OK:
+            err = SRError(code, "sr_blocks_partition")
+            err.needed = int(members.value)
+            raise err
+        self.members = int(members.value)
+        self.counts = counts
+        return counts
+
+    def gather(self, pos, mass, ws, g=None, bpos=None, bmass=None, want_src=True, stream=None):
+        """Block inputs (bpos [members, 3], bmass [members], src [members] int32
+        or None, and bg [n_active, 3] when g is given).  bpos and bmass may be
+        given to be written in place."""
+        pos = _dev_f32(pos, "pos", (self.n, 3))
+        mass = _dev_f32(mass, "mass", (self.n,))
+        dev = pos.device
+        m = self.members
+        if m < 0:
+            raise SRError(4, "sr_blocks_gather")
+        bpos = (_out_f32(bpos, "bpos", (m, 3)) if bpos is not None
+                else torch.empty((m, 3), dtype=torch.float32, device=dev))
+        bmass = (_out_f32(bmass, "bmass", (m,)) if bmass is not None
+                 else torch.empty((m,), dtype=torch.float32, device=dev))
+        src = torch.empty((m,), dtype=torch.int32, device=dev) if want_src else None
+        bg = None
+        if g is not None:
+            g = _dev_f32(g, "g", (self.n_active, 3))
+            bg = torch.empty((self.n_active, 3), dtype=torch.float32, device=dev)
+        _check(lib().sr_blocks_gather(self._plan, _ptr(pos), _ptr(mass), _ptr(g), _ptr(ws), ws.numel(),
+                                      _ptr(bpos), _ptr(bmass), _ptr(bg), _ptr(src), _stream(stream)),
+               "sr_blocks_gather")
+        return bpos, bmass, src, bg
+
+    def reconcile(self, bacc, ws, out=None, stream=None):
+        bacc = _dev_f32(bacc, "bacc", (self.n_active, 3))
+        acc = out if out is not None else torch.empty((self.n_active, 3), dtype=torch.float32,
+                                                      device=bacc.device)
+        acc = _out_f32(acc, "acc", (self.n_active, 3))
+        _check(lib().sr_blocks_reconcile(self._plan, _ptr(ws), ws.numel(), _ptr(bacc), _ptr(acc),
+                                         _stream(stream)), "sr_blocks_reconcile")
+        return acc
+
+    def reconcile_grad(self, bgrad, ws, out=None, stream=None):
+        bgrad = _dev_f32(bgrad, "bgrad", (self.members, 3))
+        grad = out if out is not None else torch.empty((self.n, 3), dtype=torch.float32,
+                                                       device=bgrad.device)
+        grad = _out_f32(grad, "grad", (self.n, 3))
+        _check(lib().sr_blocks_reconcile_grad(self._plan, _ptr(ws), ws.numel(), _ptr(bgrad), _ptr(grad),
+                                              _stream(stream)), "sr_blocks_reconcile_grad")
+        return grad
+
+    def close(self):
+        if self._plan:
+            lib().sr_blocks_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: int = -1):

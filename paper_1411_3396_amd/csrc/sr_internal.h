@@ -116,6 +116,20 @@ hipError_t dev_force(const DevArgs &a, float *acc);
 hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad);
 hipError_t dev_count_pairs(const DevArgs &a, int64_t *pairs);
 hipError_t dev_zero(void *p, int64_t words, hipStream_t st);
+
+// Shared building blocks (sr_kernels.hip) for other device passes.
+struct RadixBufs {
+    int *keys[2];
+    int *vals[2];
+    int *tab;       // digit table, (1 << digit_bits) * ntiles entries
+    int *tabx;      // its exclusive scan, one more entry
+    int *scan_tmp;  // scan_scratch_elems(table) entries
+};
+hipError_t radix_sort_pairs(const int *keys_in, const int *vals_in, int64_t n, int passes,
+                            int digit_bits, int64_t ntiles, const RadixBufs &b, hipStream_t st);
+hipError_t dev_scan(const int *in, int *out, int64_t m, int *tmp, hipStream_t st);
+hipError_t dev_bounds(const int *sorted_keys, int64_t n, int64_t nk, int key_bits, int *start,
+                      hipStream_t st);
 hipError_t dev_momentum(const DevArgs &a, const float *acc, const float *mass, double *out);
 
 // Event timing hooks (sr_api.cpp).

@@ -1273,6 +1273,46 @@ int64_t scan_scratch_elems(int64_t m)
 
 hipError_t dev_zero(void *p, int64_t words, hipStream_t st) { return fill_u32(p, words, 0, st); }
 
+hipError_t dev_scan(const int *in, int *out, int64_t m, int *tmp, hipStream_t st)
+{
+    return scan_i32(in, out, m, tmp, st);
+}
+
+hipError_t dev_bounds(const int *sorted_keys, int64_t n, int64_t nk, int key_bits, int *start,
+                      hipStream_t st)
+{
+    k_cell_bounds<<<blocks_for(n + 1, 256), 256, 0, st>>>(sorted_keys, (int)n, (int)nk, key_bits, start);
+    return hipGetLastError();
+}
+
+// Stable LSD radix sort of (key, value) pairs: keys in [0, 2^(passes*digit_bits)),
+// values default to the element index.  The result is in keys[(passes-1)&1],
+// vals[(passes-1)&1].
+hipError_t radix_sort_pairs(const int *keys_in, const int *vals_in, int64_t n, int passes,
+                            int digit_bits, int64_t ntiles, const RadixBufs &b, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int *kin = keys_in;
+    const int *vin = vals_in;
+    const int R = 1 << digit_bits;
+    hipError_t e;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * digit_bits;
+        int *kout = b.keys[p & 1];
+        int *vout = b.vals[p & 1];
+        k_radix_hist<<<(unsigned)ntiles, 256, 0, st>>>(kin, (int)n, shift, digit_bits, b.tab,
+                                                     (int)ntiles);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan_i32(b.tab, b.tabx, (int64_t)R * ntiles, b.scan_tmp, st)) != hipSuccess) return e;
+        k_radix_scatter<<<(unsigned)ntiles, 64, 0, st>>>(kin, vin, (int)n, shift, digit_bits, b.tabx,
+                                                        (int)ntiles, kout, vout);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        kin = kout;
+        vin = vout;
+    }
+    return hipSuccess;
+}
+
 hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
 {
     const Layout &L = *a.L;
@@ -1287,29 +1327,15 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    const int *kin = at<int>(a, L.skey);
-    const int *vin = nullptr;
-    const int R = 1 << L.digit_bits;
-    for (int p = 0; p < L.passes; ++p) {
-        const int shift = p * L.digit_bits;
-        int *kout = at<int>(a, L.keys[p & 1]);
-        int *vout = at<int>(a, L.vals[p & 1]);
-        k_radix_hist<<<(unsigned)L.ntiles, 256, 0, a.st>>>(kin, (int)L.N, shift, L.digit_bits,
-                                                         at<int>(a, L.tab), (int)L.ntiles);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = scan_i32(at<int>(a, L.tab), at<int>(a, L.tabx), (int64_t)R * L.ntiles,
-                          at<int>(a, L.scan_tmp), a.st)) != hipSuccess)
-            return e;
-        k_radix_scatter<<<(unsigned)L.ntiles, 64, 0, a.st>>>(kin, vin, (int)L.N, shift, L.digit_bits,
-                                                             at<int>(a, L.tabx), (int)L.ntiles, kout,
-                                                             vout);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        kin = kout;
-        vin = vout;
-    }
-    k_cell_bounds<<<blocks_for(L.N + 1, 256), 256, 0, a.st>>>(at<int>(a, L.sorted_keys()), (int)L.N,
-                                                              (int)L.NC, L.key_bits, at<int>(a, L.start));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    RadixBufs rb{{at<int>(a, L.keys[0]), at<int>(a, L.keys[1])},
+                 {at<int>(a, L.vals[0]), at<int>(a, L.vals[1])},
+                 at<int>(a, L.tab), at<int>(a, L.tabx), at<int>(a, L.scan_tmp)};
+    if ((e = radix_sort_pairs(at<int>(a, L.skey), nullptr, L.N, L.passes, L.digit_bits, L.ntiles, rb,
+                              a.st)) != hipSuccess)
+        return e;
+    if ((e = dev_bounds(at<int>(a, L.sorted_keys()), L.N, L.NC, L.key_bits, at<int>(a, L.start),
+                        a.st)) != hipSuccess)
+        return e;
     return with_acc(a, [&](auto acc) -> hipError_t {
         k_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
             acc, (int)L.N, at<int>(a, L.perm()), at<int>(a, L.sorted_keys()), at<int>(a, L.start), pos,

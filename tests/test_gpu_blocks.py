@@ -37,7 +37,6 @@ def with_strays(w):
     w.pos = np.concatenate([w.pos, np.array([[-40.0, 5.0, 5.0], [5.0, 99.0, 5.0], [np.nan, 1.0, 1.0]],
                                             np.float32)])
     w.mass = np.concatenate([w.mass, np.ones(3, np.float32)])
-    w.n = w.pos.shape[0]
     return w
 
 

@@ -42,8 +42,9 @@ def lib():
                                  _p, _p, _i64, _p]
         L.oracle_vjp_brute.argtypes = [_p, _p, _i64, _i64, _p, _p, C.c_int, C.c_double, C.c_double,
                                        _p, _p, _p]
+        L.oracle_halo_potential.argtypes = [_p, _p, _i64, _p, _i64, C.c_double, _p, _i64, _p]
         for fn in ("oracle_grid", "oracle_bin_reference", "oracle_force", "oracle_force_brute",
-                   "oracle_vjp", "oracle_vjp_brute"):
+                   "oracle_vjp", "oracle_vjp_brute", "oracle_halo_potential"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -174,3 +175,38 @@ def rms_rel(x, ref) -> float:
     den = float(np.sum(ref * ref))
     num = float(np.sum((x - ref) ** 2))
     return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
+
+
+def halo_potential(pos, mass, offsets, eps, targets=None):
+    """float64 potential of each target from the other particles of its halo
+    (halo h holds particles [offsets[h], offsets[h+1]))."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float64).reshape(-1)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = pos.shape[0]
+    if targets is None:
+        tptr, nt = None, n
+    else:
+        targets = np.ascontiguousarray(targets, dtype=np.int64)
+        tptr, nt = _ptr(targets), targets.shape[0]
+    phi = np.zeros(nt, np.float64)
+    rc = lib().oracle_halo_potential(_ptr(pos), _ptr(mass), n, _ptr(offsets), offsets.shape[0] - 1,
+                                     float(np.float32(eps)), tptr, nt, _ptr(phi))
+    _check(rc, "oracle_halo_potential")
+    return phi
+
+
+def most_bound(phi, offsets):
+    """Per halo: index of the smallest phi (the first on ties) and that phi;
+    -1 and 0 for an empty halo."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    H = offsets.shape[0] - 1
+    idx = np.full(H, -1, np.int64)
+    val = np.zeros(H, np.float64)
+    for h in range(H):
+        a, b = offsets[h], offsets[h + 1]
+        if b > a:
+            k = int(np.argmin(phi[a:b]))
+            idx[h] = a + k
+            val[h] = phi[a + k]
+    return idx, val

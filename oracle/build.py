@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "sr_oracle.c")
+SRCS = [os.path.join(HERE, "sr_oracle.c"), os.path.join(HERE, "halo_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 # -ffp-contract=off: the float32 binning rule is specified without fused
@@ -18,7 +18,7 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
+    cmd = ["gcc", *CFLAGS, "-o", tmp, *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -105,6 +105,32 @@ class Batch:
                         int(self.n_active[b]), self.problems[b])
 
 
+@dataclass
+class HaloCatalogue:
+    """Friends-of-friends style halo membership: halo h holds particles
+    [offsets[h], offsets[h+1]), coordinates unwrapped."""
+
+    name: str
+    pos: np.ndarray  # float32 [n, 3]
+    mass: np.ndarray  # float32 [n]
+    offsets: np.ndarray  # int64 [H+1]
+    eps: float
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def n_halos(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    def pairs(self) -> int:
+        """Ordered pairs (i, j != i) inside halos: the centre finder's work."""
+        c = np.diff(self.offsets).astype(np.int64)
+        return int(np.sum(c * (c - 1)))
+
+
 # --------------------------------------------------------------------------
 # primitive draws
 # --------------------------------------------------------------------------
@@ -161,6 +187,63 @@ def clustered_positions(rng: np.random.Generator, n: int, lo: float, length: flo
     pos = np.concatenate([bg, halo], axis=0)
     pos = pos[rng.permutation(n)]
     return pos, {"halo_budget": budget, "max_halo": int(counts.max()) if n_halos else 0}
+
+
+def power_law_counts(rng: np.random.Generator, k: int, n_min: float, n_max: float,
+                     slope: float) -> np.ndarray:
+    """k integers with dN/dn proportional to n^-slope on [n_min, n_max] (inverse CDF)."""
+    a = 1.0 - slope
+    u = rng.random(k)
+    x = (n_min ** a + u * (n_max ** a - n_min ** a)) ** (1.0 / a)
+    return np.floor(x).astype(np.int64)
+
+
+def halo_members(rng: np.random.Generator, counts: np.ndarray, box: float) -> np.ndarray:
+    """float64 positions of Plummer halos with the given particle counts: scale
+    radius R200 / 5 with R200 = (3 n / (800 pi))^(1/3) (200 times a mean density
+    of one particle per cell), centres uniform in [0, box)^3, particles shuffled
+    inside each halo."""
+    H = counts.shape[0]
+    centres = rng.random((H, 3)) * box
+    r200 = np.cbrt(3.0 * np.maximum(counts, 1) / (800.0 * math.pi))
+    hid = np.repeat(np.arange(H), counts)
+    pos = centres[hid] + plummer_offsets(rng, (r200 / 5.0)[hid])
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    for h in range(H):
+        a, b = offsets[h], offsets[h + 1]
+        if b - a > 1:
+            pos[a:b] = pos[a:b][rng.permutation(b - a)]
+    return pos
+
+
+def halo_catalogue(n_halos: int, seed: int, n_min: float = 40, n_max: float = 1e6,
+                   slope: float = 1.9, box: float = 320.0, eps: float = 0.02,
+                   name: str = "halos") -> HaloCatalogue:
+    rng = np.random.default_rng(seed)
+    counts = power_law_counts(rng, n_halos, n_min, n_max, slope)
+    pos = halo_members(rng, counts, box).astype(F32)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return HaloCatalogue(name, pos, np.ones(pos.shape[0], F32), offsets, eps,
+                         {"seed": seed, "slope": slope, "n_min": n_min, "n_max": n_max,
+                          "max_halo": int(counts.max()) if n_halos else 0})
+
+
+def halos_small() -> HaloCatalogue:
+    """Halo sizes around the kernel's group boundaries, empty halos included,
+    random masses."""
+    counts = np.array([0, 1, 2, 3, 40, 63, 64, 65, 0, 127, 128, 129, 255, 256, 257, 500, 1000,
+                       4099, 7, 0], np.int64)
+    rng = np.random.default_rng(11)
+    pos = halo_members(rng, counts, 64.0).astype(F32)
+    mass = rng.uniform(0.5, 2.0, pos.shape[0]).astype(F32)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return HaloCatalogue("halos_small", pos, mass, offsets, 0.02, {"seed": 11})
+
+
+def halos_node() -> HaloCatalogue:
+    """One node's halo catalogue at late times: 10,200 halos of 40 particles and
+    up, dN/dn ~ n^-1.9 up to 1e6 (mean about 630 particles per halo)."""
+    return halo_catalogue(10200, 0, name="halos_node")
 
 
 # --------------------------------------------------------------------------
@@ -271,6 +354,8 @@ WORKLOADS = {
     "subvolumes_96": subvolumes_96,
     "clustered_16m": clustered_16m,
     "node_share": node_share,
+    "halos_small": halos_small,
+    "halos_node": halos_node,
 }
 
 

@@ -138,6 +138,64 @@ def block_comparison(w, pos, mass, acc_mono, reps: int = 3):
     return out
 
 
+FLOP_PER_POTENTIAL_PAIR = 12  # 3 sub, 3 FMA, rsqrt, 1 FMA
+
+
+def centres_measure(reps: int = 3, cpu_seconds: float = 0.0):
+    """Most-bound-particle centres of one node's halo catalogue (all pairs
+    inside each halo), with the oracle on a sample of targets beside it."""
+    import torch
+
+    import paper_1411_3396_amd as sr
+    from paper_1411_3396_amd import synth
+
+    cat = synth.halos_node()
+    dev = "cuda:0"
+    pos = torch.from_numpy(cat.pos).to(dev)
+    mass = torch.from_numpy(cat.mass).to(dev)
+    plan = sr.CentresPlan(cat.offsets)
+    ws = sr.new_workspace(plan.ws_bytes, dev)
+    phi, mbp, pmin = plan.run(pos, mass, cat.eps, ws)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.run(pos, mass, cat.eps, ws, phi, mbp, pmin)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pairs = cat.pairs()
+    rate = pairs / (ms * 1e-3)
+    achieved = FLOP_PER_POTENTIAL_PAIR * rate / 1e12
+    out = {"workload": cat.name, "n": cat.n, "halos": cat.n_halos, "largest_halo": cat.notes["max_halo"],
+           "pairs": pairs, "ms": round(ms, 3), "pairs_per_s": rate,
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR, 4),
+                        "flop_per_pair": FLOP_PER_POTENTIAL_PAIR}}
+    plan.close()
+    if cpu_seconds > 0:
+        import oracle
+
+        counts = np.diff(cat.offsets)
+        t = synth.sample_indices(cat.n, 200, 9)
+        t0 = time.perf_counter()
+        oracle.halo_potential(cat.pos, cat.mass, cat.offsets, cat.eps, targets=t)
+        pilot = time.perf_counter() - t0
+        hid = np.searchsorted(cat.offsets, t, side="right") - 1
+        k = int(min(cat.n, max(200, 200 * cpu_seconds / max(pilot, 1e-3))))
+        t = synth.sample_indices(cat.n, k, 10)
+        hid = np.searchsorted(cat.offsets, t, side="right") - 1
+        t0 = time.perf_counter()
+        oracle.halo_potential(cat.pos, cat.mass, cat.offsets, cat.eps, targets=t)
+        el = time.perf_counter() - t0
+        sp = int(np.sum(counts[hid] - 1))
+        out["cpu_baseline"] = {"value": sp / el, "unit": "pair interactions/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{k} random particles of {cat.name}, each summed over its halo "
+                                         f"({sp} pairs, {el:.1f} s)"}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +206,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-blocks", action="store_true")
+    ap.add_argument("--no-centres", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="time the pair kernels under every launch configuration "
                          "(waves per CU, targets per lane, occupancy variant); one JSON line each")
@@ -324,6 +383,9 @@ def main() -> int:
         log("overlapping data blocks")
         result["blocks"] = block_comparison(w, pos, mass, acc)
         result["blocks_force_ms_single_domain"] = round(phase["bin"] + phase["force"], 3)
+    if not args.no_centres:
+        log("most-bound-particle centres")
+        result["centres"] = centres_measure(cpu_seconds=0.0 if args.no_cpu_baseline else 10.0)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, g_np, args.cpu_seconds)

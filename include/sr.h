@@ -272,6 +272,36 @@ sr_status sr_blocks_reconcile(const sr_blocks_plan *plan, const void *ws, size_t
 sr_status sr_blocks_reconcile_grad(const sr_blocks_plan *plan, const void *ws, size_t ws_bytes,
                                    const float *bgrad, float *grad, void *stream);
 
+/* Most-bound-particle halo centres (Sec. 2.2: a halo's centre is the
+ * particle at its potential minimum, found after friends-of-friends halo
+ * finding).  For every particle i of halo h
+ *
+ *     phi_i = - sum_{j in h, j != i} m_j / sqrt(|x_j - x_i|^2 + eps^2)
+ *
+ * (G = 1; with eps = 0 a pair at zero distance adds nothing), and per halo
+ * the particle with the smallest phi, ties to the smaller index.  Halo h
+ * holds particles [offsets[h], offsets[h+1]) of pos [n][3] / mass [n];
+ * coordinates are used as given (a halo finder's unwrapped positions).
+ * Pair terms are float32; they are accumulated in float64 in groups of 8, so
+ * the rounding does not grow with the halo size.  The most-bound choice is
+ * made on the float32 phi that is returned.  Results do not depend on the
+ * launch (every sum has a fixed order). */
+typedef struct sr_centres_plan sr_centres_plan;
+
+/* Host only.  Work items for n_halos halos (1 <= n_halos <= 2^26, offsets
+ * non-decreasing from 0, n = offsets[n_halos] < 2^31); reports the workspace
+ * size.  The plan owns only host memory (a pinned copy of its tables from
+ * the first run on, where the device is first touched). */
+sr_status sr_centres_plan_create(int32_t n_halos, const int64_t *offsets /*host [n_halos+1]*/,
+                                 sr_centres_plan **plan /*host out*/, size_t *ws_bytes /*host out*/);
+sr_status sr_centres_plan_destroy(sr_centres_plan *plan);
+
+/* phi [n] (required), mbp [n_halos] int64 = index of the most bound particle
+ * (-1 for an empty halo or one whose every phi is NaN), phi_min [n_halos]
+ * (nullable) = its phi (0 when none).  eps >= 0. */
+sr_status sr_centres(sr_centres_plan *plan, const float *pos, const float *mass, float eps, void *ws,
+                     size_t ws_bytes, float *phi, int64_t *mbp, float *phi_min, void *stream);
+
 /* Host only.  Process-wide launch parameters of the single-problem entry
  * points (batch plans tune their own):
  *   waves_per_cu      persistent grid of the pair kernels, in waves per compute

@@ -30,7 +30,8 @@ EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "
            "sr_ws_flags", "sr_batch_plan_create", "sr_batch_force", "sr_batch_plan_destroy",
            "sr_batch_plan_info", "sr_blocks_plan_create", "sr_blocks_plan_destroy",
            "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
-           "sr_blocks_reconcile_grad", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
+           "sr_blocks_reconcile_grad", "sr_centres_plan_create", "sr_centres_plan_destroy",
+           "sr_centres", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
 
 
 class SRError(RuntimeError):
@@ -89,6 +90,9 @@ def lib():
         L.sr_blocks_gather.argtypes = [p, p, p, p, p, C.c_size_t, p, p, p, p, p]
         L.sr_blocks_reconcile.argtypes = [p, p, C.c_size_t, p, p, p]
         L.sr_blocks_reconcile_grad.argtypes = [p, p, C.c_size_t, p, p, p]
+        L.sr_centres_plan_create.argtypes = [C.c_int32, p, p, p]
+        L.sr_centres_plan_destroy.argtypes = [p]
+        L.sr_centres.argtypes = [p, p, p, C.c_float, p, C.c_size_t, p, p, p, p]
         L.sr_launch_config.argtypes = [C.c_int, C.c_int, C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
@@ -475,6 +479,60 @@ class BlocksPlan:
             self.close()
         except Exception:
             pass
+
+
+class CentresPlan:
+    """Most-bound-particle centres of a halo catalogue (sr_centres_*): halo h
+    holds particles [offsets[h], offsets[h+1])."""
+
+    def __init__(self, offsets):
+        import numpy as np
+
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.n_halos = int(self.offsets.shape[0] - 1)
+        self.n = int(self.offsets[-1]) if self.n_halos >= 0 else 0
+        self._plan = C.c_void_p()
+        nbytes = C.c_size_t()
+        _check(lib().sr_centres_plan_create(self.n_halos, self.offsets.ctypes.data_as(C.c_void_p),
+                                            C.byref(self._plan), C.byref(nbytes)), "sr_centres_plan_create")
+        self.ws_bytes = int(nbytes.value)
+
+    def run(self, pos, mass, eps, ws, phi=None, mbp=None, phi_min=None, stream=None):
+        """Returns (phi [n], mbp [n_halos] int64, phi_min [n_halos])."""
+        pos = _dev_f32(pos, "pos", (self.n, 3))
+        mass = _dev_f32(mass, "mass", (self.n,))
+        dev = pos.device
+        phi = (_out_f32(phi, "phi", (self.n,)) if phi is not None
+               else torch.empty((self.n,), dtype=torch.float32, device=dev))
+        if mbp is None:
+            mbp = torch.empty((self.n_halos,), dtype=torch.int64, device=dev)
+        elif mbp.dtype != torch.int64 or tuple(mbp.shape) != (self.n_halos,) or not mbp.is_contiguous():
+            raise ValueError("mbp must be a contiguous int64 [n_halos] tensor")
+        phi_min = (_out_f32(phi_min, "phi_min", (self.n_halos,)) if phi_min is not None
+                   else torch.empty((self.n_halos,), dtype=torch.float32, device=dev))
+        _check(lib().sr_centres(self._plan, _ptr(pos), _ptr(mass), float(eps), _ptr(ws), ws.numel(),
+                                _ptr(phi), _ptr(mbp), _ptr(phi_min), _stream(stream)), "sr_centres")
+        return phi, mbp, phi_min
+
+    def close(self):
+        if self._plan:
+            lib().sr_centres_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def halo_centres(pos, mass, offsets, eps):
+    """phi, most-bound index and its phi per halo (one-shot plan and workspace)."""
+    plan = CentresPlan(offsets)
+    ws = new_workspace(plan.ws_bytes, pos.device)
+    out = plan.run(pos, mass, eps, ws)
+    plan.close()
+    return out
 
 
 def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: int = -1):

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsr.so")
 SOURCES = [os.path.join(CSRC, "sr_kernels.hip"), os.path.join(CSRC, "sr_blocks.hip"),
-           os.path.join(CSRC, "sr_api.cpp")]
+           os.path.join(CSRC, "sr_centres.hip"), os.path.join(CSRC, "sr_api.cpp")]
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from forming packed float32 arithmetic.

@@ -159,6 +159,10 @@ __global__ __launch_bounds__(64, 4) void k_centre_potential(
     __shared__ float4 stage[kTargetsPerWave];
     const int lane = threadIdx.x;
     for (;;) {
+        // Lane 0 takes the next item; the loop body below ends with no other
+        // lane-0-only branch, so the compiler cannot merge the two into one
+        // region across the loop's back edge (which would let the other
+        // lanes start the next iteration without lane 0's new item).
         uint32_t g = 0;
         if (lane == 0) g = atomicAdd(&hdr->next, 1u);
         g = __builtin_amdgcn_readfirstlane(g);
@@ -167,7 +171,8 @@ __global__ __launch_bounds__(64, 4) void k_centre_potential(
         const int h = it.x, t0 = it.y, nt = it.z, lk = it.w & 15;
         const bool two = (it.w >> 4) & 1;
         const int slot = it.w >> 5;
-        const int s0 = hoff[h], s1 = hoff[h + 1];
+        const int s0 = __builtin_amdgcn_readfirstlane(hoff[h]);
+        const int s1 = __builtin_amdgcn_readfirstlane(hoff[h + 1]);
         const int kl = 1 << lk;
         const int tsub = lane >> lk, sub = lane & (kl - 1);
         // targets of this lane: a = t0 + tsub (dense: tsub = lane), b = a + 64
@@ -229,8 +234,9 @@ __global__ __launch_bounds__(64, 4) void k_centre_potential(
             v = pb;
             idx = ib;
         }
+        // every lane holds the same minimum: all store it (one address)
         const MinIdx m = wave_argmin(v, idx);
-        if (lane == 0) partial[slot] = make_int2(__float_as_int(m.v), m.i);
+        partial[slot] = make_int2(__float_as_int(m.v), m.i);
     }
 }
 

@@ -210,9 +210,10 @@ def main() -> int:
     ap.add_argument("--sweep", action="store_true",
                     help="time the pair kernels under every launch configuration "
                          "(waves per CU, targets per lane, occupancy variant); one JSON line each")
-    ap.add_argument("--only", choices=["force", "vjp", "copy"],
+    ap.add_argument("--only", choices=["force", "vjp", "copy", "centres"],
                     help="profiling mode: bin once, then run only this kernel --steps times "
-                         "(copy: a 1 GiB device-to-device copy of known size); prints no JSON")
+                         "(copy: a 1 GiB device-to-device copy of known size; centres: the halo "
+                         "catalogue's centre finder); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the short-range path is "
@@ -225,6 +226,10 @@ def main() -> int:
     from paper_1411_3396_amd import synth
 
     dev = "cuda:0"
+    if args.only == "centres":
+        out = centres_measure(reps=args.steps)
+        log(f"centres {args.steps} runs: {out['ms']} ms each")
+        return 0
     if args.only == "copy":
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)

@@ -196,6 +196,53 @@ def centres_measure(reps: int = 3, cpu_seconds: float = 0.0):
     return out
 
 
+def pk_measure(reps: int = 5):
+    """Power spectrum on the fly (CIC deposit, FFT, bins) of the 16.7M-particle
+    clustered box on 256^3 and 512^3 grids."""
+    import torch
+
+    import paper_1411_3396_amd as sr
+    from paper_1411_3396_amd import synth
+
+    w = synth.clustered_16m()
+    dev = "cuda:0"
+    pos = torch.from_numpy(w.pos).to(dev)
+    mass = torch.from_numpy(w.mass).to(dev)
+    box = float(w.problem.len[0])
+    out = []
+    for ng in (256, 512):
+        n_bins = ng // 2
+        plan = sr.PkPlan(ng, box, n_bins)
+        ws = sr.new_workspace(plan.ws_bytes, dev)
+        plan.run(pos, mass, ws)  # first run: FFT plan
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        dep = tot = 0.0
+        for _ in range(reps):
+            e[0].record()
+            plan.deposit(pos, mass, ws)
+            e[1].record()
+            plan.run(pos, mass, ws)
+            e[2].record()
+            e[2].synchronize()
+            dep += e[0].elapsed_time(e[1])
+            tot += e[1].elapsed_time(e[2])
+        dep /= reps
+        tot /= reps
+        # deposit: 16 B read per particle and 8 float32 read-modify-write atomics
+        gbs = w.n * (16 + 8 * 8) / (dep * 1e-3) / 1e9
+        out.append({"workload": w.name, "ng": ng, "n": w.n, "ms": round(tot, 3), "ms_deposit": round(dep, 3),
+                    "particles_per_s": w.n / (tot * 1e-3),
+                    "deposit_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
+                                         "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                                         "bytes_per_particle": 80}})
+        log(f"pk ng={ng}: {out[-1]}")
+        plan.close()
+        del ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,10 +254,11 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-blocks", action="store_true")
     ap.add_argument("--no-centres", action="store_true")
+    ap.add_argument("--no-pk", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="time the pair kernels under every launch configuration "
                          "(waves per CU, targets per lane, occupancy variant); one JSON line each")
-    ap.add_argument("--only", choices=["force", "vjp", "copy", "centres"],
+    ap.add_argument("--only", choices=["force", "vjp", "copy", "centres", "pk"],
                     help="profiling mode: bin once, then run only this kernel --steps times "
                          "(copy: a 1 GiB device-to-device copy of known size; centres: the halo "
                          "catalogue's centre finder); prints no JSON")
@@ -226,6 +274,9 @@ def main() -> int:
     from paper_1411_3396_amd import synth
 
     dev = "cuda:0"
+    if args.only == "pk":
+        pk_measure(reps=args.steps)
+        return 0
     if args.only == "centres":
         out = centres_measure(reps=args.steps)
         log(f"centres {args.steps} runs: {out['ms']} ms each")
@@ -388,6 +439,9 @@ def main() -> int:
         log("overlapping data blocks")
         result["blocks"] = block_comparison(w, pos, mass, acc)
         result["blocks_force_ms_single_domain"] = round(phase["bin"] + phase["force"], 3)
+    if not args.no_pk:
+        log("power spectrum")
+        result["pk"] = pk_measure()
     if not args.no_centres:
         log("most-bound-particle centres")
         result["centres"] = centres_measure(cpu_seconds=0.0 if args.no_cpu_baseline else 10.0)

@@ -21,8 +21,10 @@
  *  - Pointers are DEVICE pointers unless marked (host).  Arrays are row-major
  *    float32: positions [n][3], masses [n], accelerations [n_active][3].
  *  - The caller owns all device memory.  The library never allocates device
- *    memory and never synchronises, except where stated (sr_ws_flags, plan
- *    creation and the first run of a batch plan).  Work is enqueued on
+ *    memory (except the FFT tables of a power-spectrum plan, see
+ *    sr_power_spectrum) and never synchronises, except where stated
+ *    (sr_ws_flags, plan creation, the first run of a batch plan, and
+ *    sr_blocks_partition).  Work is enqueued on
  *    `stream` (a hipStream_t passed as an opaque pointer; NULL is the null
  *    stream) and the call returns at once.
  *  - The workspace is caller-allocated scratch of at least the size
@@ -301,6 +303,49 @@ sr_status sr_centres_plan_destroy(sr_centres_plan *plan);
  * (nullable) = its phi (0 when none).  eps >= 0. */
 sr_status sr_centres(sr_centres_plan *plan, const float *pos, const float *mass, float eps, void *ws,
                      size_t ws_bytes, float *phi, int64_t *mbp, float *phi_min, void *stream);
+
+/* Power spectrum on the fly (Sec. 4.1): cloud-in-cell deposit of the
+ * particles onto an ng^3 periodic grid of cell h = box / ng, a DFT, and
+ * P(k) = |delta(k)|^2 box^3 / ng^6 divided by the CIC window
+ * W(k)^2 = prod_d sinc^4(pi n_d / ng), averaged over the modes of each bin
+ * b = floor(|n| / dn) (n the integer mode vector, k = 2 pi n / box; k = 0 is
+ * left out), with delta = rho / mean(rho) - 1.  Deposit: a particle at
+ * u = x / h, wrapped into [0, ng), gives m (1 - f) to grid point floor(u) and
+ * m f to floor(u) + 1 per axis (f = u - floor(u)), the product over axes to
+ * each of 8 points; grid points sit at multiples of h.  The deposit uses
+ * float32 atomic additions (the order of additions into one point is not
+ * fixed); the FFT is rocFFT's single-precision real-to-complex transform,
+ * in place in the workspace; mode sums are float64.  Non-finite positions
+ * make the spectrum non-finite. */
+typedef struct sr_pk_plan sr_pk_plan;
+
+/* Host only.  2 <= ng <= 2048, ng even; box > 0; 1 <= n_bins <= 2048; dn > 0
+ * (bin width in units of the fundamental 2 pi / box). */
+sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn,
+                            sr_pk_plan **plan /*host out*/, size_t *ws_bytes /*host out*/);
+/* Releases the plan and the FFT plan's device tables. */
+sr_status sr_pk_plan_destroy(sr_pk_plan *plan);
+
+/* Deposit only: the mass grid and the total mass, in the workspace (see
+ * sr_pk_grid). pos [n][3], mass [n], 0 <= n < 2^31. */
+sr_status sr_pk_deposit(sr_pk_plan *plan, const float *pos, const float *mass, int64_t n, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Host only, no device access.  Device pointers into the workspace: the grid
+ * (mass at point (ix, iy, iz) at grid[(ix * ng + iy) * row_pitch + iz], valid
+ * after sr_pk_deposit and overwritten by the FFT of sr_power_spectrum) and the
+ * float64 total mass (nullable). */
+sr_status sr_pk_grid(const sr_pk_plan *plan, const void *ws, const float **grid /*host out*/,
+                     int32_t *row_pitch /*host out*/, const double **mass_total /*host out*/);
+
+/* Deposit, FFT and bins: pk [n_bins] float64, k [n_bins] float64 (nullable:
+ * the bin's mean |k|), modes [n_bins] int64 (nullable: modes in the bin, the
+ * full grid counted).  Empty bins give 0.  The first call creates the rocFFT
+ * plan on the current device: it compiles or loads the transform's kernels
+ * and keeps its twiddle tables in device memory it allocates itself (the one
+ * device allocation the library makes), released by sr_pk_plan_destroy. */
+sr_status sr_power_spectrum(sr_pk_plan *plan, const float *pos, const float *mass, int64_t n, void *ws,
+                            size_t ws_bytes, double *pk, double *k, int64_t *modes, void *stream);
 
 /* Host only.  Process-wide launch parameters of the single-problem entry
  * points (batch plans tune their own):

@@ -31,7 +31,8 @@ EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "
            "sr_batch_plan_info", "sr_blocks_plan_create", "sr_blocks_plan_destroy",
            "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
            "sr_blocks_reconcile_grad", "sr_centres_plan_create", "sr_centres_plan_destroy",
-           "sr_centres", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
+           "sr_centres", "sr_pk_plan_create", "sr_pk_plan_destroy", "sr_pk_deposit", "sr_pk_grid",
+           "sr_power_spectrum", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
 
 
 class SRError(RuntimeError):
@@ -93,6 +94,11 @@ def lib():
         L.sr_centres_plan_create.argtypes = [C.c_int32, p, p, p]
         L.sr_centres_plan_destroy.argtypes = [p]
         L.sr_centres.argtypes = [p, p, p, C.c_float, p, C.c_size_t, p, p, p, p]
+        L.sr_pk_plan_create.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_double, p, p]
+        L.sr_pk_plan_destroy.argtypes = [p]
+        L.sr_pk_deposit.argtypes = [p, p, p, i64, p, C.c_size_t, p]
+        L.sr_pk_grid.argtypes = [p, p, p, p, p]
+        L.sr_power_spectrum.argtypes = [p, p, p, i64, p, C.c_size_t, p, p, p, p]
         L.sr_launch_config.argtypes = [C.c_int, C.c_int, C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
@@ -533,6 +539,62 @@ def halo_centres(pos, mass, offsets, eps):
     out = plan.run(pos, mass, eps, ws)
     plan.close()
     return out
+
+
+class PkPlan:
+    """Power spectrum of particles on an ng^3 periodic grid (sr_pk_*)."""
+
+    def __init__(self, ng: int, box: float, n_bins: int, dn: float = 1.0):
+        self.ng, self.box, self.n_bins, self.dn = int(ng), float(box), int(n_bins), float(dn)
+        self._plan = C.c_void_p()
+        nbytes = C.c_size_t()
+        _check(lib().sr_pk_plan_create(self.ng, self.box, self.n_bins, self.dn, C.byref(self._plan),
+                                       C.byref(nbytes)), "sr_pk_plan_create")
+        self.ws_bytes = int(nbytes.value)
+
+    def deposit(self, pos, mass, ws, stream=None):
+        """The CIC mass grid [ng, ng, ng] (a view into the workspace) and the total mass (device)."""
+        n = int(pos.shape[0])
+        pos = _dev_f32(pos, "pos", (n, 3))
+        mass = _dev_f32(mass, "mass", (n,))
+        _check(lib().sr_pk_deposit(self._plan, _ptr(pos), _ptr(mass), n, _ptr(ws), ws.numel(),
+                                   _stream(stream)), "sr_pk_deposit")
+        return self.grid(ws)
+
+    def grid(self, ws):
+        g = C.c_void_p()
+        pitch = C.c_int32()
+        mt = C.c_void_p()
+        _check(lib().sr_pk_grid(self._plan, _ptr(ws), C.byref(g), C.byref(pitch), C.byref(mt)), "sr_pk_grid")
+        base = ws.data_ptr()
+        off, moff = (g.value or 0) - base, (mt.value or 0) - base
+        ng, pitch = self.ng, int(pitch.value)
+        full = ws[off: off + 4 * ng * ng * pitch].view(torch.float32).view(ng, ng, pitch)
+        return full[:, :, :ng], ws[moff: moff + 8].view(torch.float64)
+
+    def run(self, pos, mass, ws, stream=None):
+        """(P per bin, mean |k| per bin, modes per bin) as device tensors."""
+        n = int(pos.shape[0])
+        pos = _dev_f32(pos, "pos", (n, 3))
+        mass = _dev_f32(mass, "mass", (n,))
+        dev = pos.device
+        pk = torch.empty(self.n_bins, dtype=torch.float64, device=dev)
+        km = torch.empty(self.n_bins, dtype=torch.float64, device=dev)
+        modes = torch.empty(self.n_bins, dtype=torch.int64, device=dev)
+        _check(lib().sr_power_spectrum(self._plan, _ptr(pos), _ptr(mass), n, _ptr(ws), ws.numel(), _ptr(pk),
+                                       _ptr(km), _ptr(modes), _stream(stream)), "sr_power_spectrum")
+        return pk, km, modes
+
+    def close(self):
+        if self._plan:
+            lib().sr_pk_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: int = -1):

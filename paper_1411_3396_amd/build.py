@@ -11,7 +11,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsr.so")
 SOURCES = [os.path.join(CSRC, "sr_kernels.hip"), os.path.join(CSRC, "sr_blocks.hip"),
-           os.path.join(CSRC, "sr_centres.hip"), os.path.join(CSRC, "sr_api.cpp")]
+           os.path.join(CSRC, "sr_centres.hip"), os.path.join(CSRC, "sr_pk.hip"),
+           os.path.join(CSRC, "sr_api.cpp")]
+LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from forming packed float32 arithmetic.
@@ -26,7 +28,7 @@ def build(verbose: bool = False, extra=None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc, *HIPFLAGS, *(extra or []), "-I", INCLUDE, "-I", CSRC, "-shared", "-o", tmp,
-           *SOURCES]
+           *SOURCES, *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -246,6 +246,48 @@ def halos_node() -> HaloCatalogue:
     return halo_catalogue(10200, 0, name="halos_node")
 
 
+def clustered_positions_absolute(rng: np.random.Generator, n: int, lo: float, length: float,
+                                 halo_frac: float, mass_range=(1e2, 1e5),
+                                 scale_range=(0.5, 4.0)) -> Tuple[np.ndarray, dict]:
+    """Halo masses taken as absolute particle counts, drawn log-uniform until
+    the halo budget is full (the last halo takes what is left): few, very
+    large halos (float64 positions, unwrapped)."""
+    budget = int(round(halo_frac * n))
+    counts = []
+    total = 0
+    while total < budget:
+        m = int(math.exp(rng.uniform(math.log(mass_range[0]), math.log(mass_range[1]))))
+        m = max(1, min(m, budget - total))
+        counts.append(m)
+        total += m
+    counts = np.array(counts, np.int64)
+    H = counts.shape[0]
+    loga = rng.uniform(math.log(scale_range[0]), math.log(scale_range[1]), H)
+    centres = lo + rng.random((H, 3)) * length
+    hid = np.repeat(np.arange(H), counts)
+    halo = centres[hid] + plummer_offsets(rng, np.exp(loga)[hid])
+    bg = lo + rng.random((n - budget, 3)) * length
+    pos = np.concatenate([bg, halo], axis=0)
+    pos = pos[rng.permutation(n)]
+    return pos, {"halo_budget": budget, "halos": H, "max_halo": int(counts.max()) if H else 0}
+
+
+def clustered_box_absolute(n: int, length: float, seed: int, halo_frac: float = 0.4,
+                           mass_range=(1e2, 1e5), r_s: float = 3.0, eps: float = 0.05,
+                           name: str = "clustered_abs") -> Workload:
+    rng = np.random.default_rng(seed)
+    p64, info = clustered_positions_absolute(rng, n, 0.0, length, halo_frac, mass_range)
+    prob = Problem.make((0, 0, 0), (length,) * 3, True, r_s, eps, filter_poly(r_s, eps))
+    info["seed"] = seed
+    return Workload(name, _to_box32(p64, 0.0, length), np.ones(n, F32), n, prob, info)
+
+
+def clustered_2m_extreme() -> Workload:
+    """The 2M box with halo masses as absolute counts (a few halos up to ~1e5
+    particles): the extreme-clustering stress case."""
+    return clustered_box_absolute(2097152, 128.0, 0, name="clustered_2m_extreme")
+
+
 # --------------------------------------------------------------------------
 # workloads
 # --------------------------------------------------------------------------
@@ -354,6 +396,7 @@ WORKLOADS = {
     "subvolumes_96": subvolumes_96,
     "clustered_16m": clustered_16m,
     "node_share": node_share,
+    "clustered_2m_extreme": clustered_2m_extreme,
     "halos_small": halos_small,
     "halos_node": halos_node,
 }

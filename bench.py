@@ -177,12 +177,17 @@ def centres_measure(reps: int = 3, cpu_seconds: float = 0.0):
         import oracle
 
         counts = np.diff(cat.offsets)
-        t = synth.sample_indices(cat.n, 200, 9)
-        t0 = time.perf_counter()
-        oracle.halo_potential(cat.pos, cat.mass, cat.offsets, cat.eps, targets=t)
-        pilot = time.perf_counter() - t0
-        hid = np.searchsorted(cat.offsets, t, side="right") - 1
-        k = int(min(cat.n, max(200, 200 * cpu_seconds / max(pilot, 1e-3))))
+        # pilots grow the sample until one takes a tenth of the time asked for
+        k, pilot = 200, 0.0
+        while True:
+            t = synth.sample_indices(cat.n, k, 9)
+            t0 = time.perf_counter()
+            oracle.halo_potential(cat.pos, cat.mass, cat.offsets, cat.eps, targets=t)
+            pilot = time.perf_counter() - t0
+            if pilot >= 0.1 * cpu_seconds or k >= cat.n:
+                break
+            k = min(cat.n, k * 4)
+        k = int(min(cat.n, max(200, k * cpu_seconds / max(pilot, 1e-3))))
         t = synth.sample_indices(cat.n, k, 10)
         hid = np.searchsorted(cat.offsets, t, side="right") - 1
         t0 = time.perf_counter()

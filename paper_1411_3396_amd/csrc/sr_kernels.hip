@@ -422,6 +422,25 @@ __global__ __launch_bounds__(256) void k_gather_g(int N, int n_rows,
 
 // --------------------------------------------------------------- work items
 
+// Items of a home cell with nt targets.  A cell of fewer than 64 targets is one
+// item with 2^lk lanes per target.  A larger cell is cut into items of 64
+// targets (128, two per lane, with `two`; then a last 64 when an odd number
+// of 64s remain), and its last nt mod 64 targets form one item of their own
+// with 2^lk lanes per target, so no item runs with mostly idle lanes.  Every
+// target is summed in the same order whether or not `two` is set.
+__device__ __forceinline__ int lanes_log2(int n)
+{
+    return n >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / n));
+}
+
+__device__ __forceinline__ int cell_items(int nt, bool two)
+{
+    if (nt < kTargetsPerItem) return 1;
+    const int r = nt % kTargetsPerItem, groups = nt / kTargetsPerItem;
+    const int dense = two ? (groups + 1) / 2 : groups;
+    return dense + (r > 0 ? 1 : 0);
+}
+
 // Per home cell: number of items and cost class (floor log2 of the pairs one
 // lane evaluates); counts items per class.
 template <class Acc, bool kActiveOnly>
@@ -470,7 +489,7 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
     }
     const int lk = nt >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / nt));
     const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
-    const int n_items = (nt + chunk - 1) / chunk;
+    const int n_items = cell_items(nt, two);
     int64_t cost = ((src + (1 << lk) - 1) >> lk) * (chunk / kTargetsPerItem);
     if (cost < 1) cost = 1;
     int cls = 63 - __clzll((unsigned long long)cost);
@@ -537,17 +556,21 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
     __syncthreads();
     if (!inf) return;
     const int nt = kActiveOnly ? nact[c] : (start[c + 1] - start[c]);
-    const int lk = nt >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / nt));
     const int seg = acc.seg_of_cell(c);
     const uint32_t at = base[cls] + local;
     const int s0 = start[c];
-    const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
-    for (int k = 0; k < n_items; ++k) {
-        const int t0 = k * chunk;
-        const int cn = min(chunk, nt - t0);
-        const int tw = cn > kTargetsPerItem ? 1 : 0;
-        items[at + k] = make_int4(c, s0 + t0, cn, lk | (tw << 4) | (seg << 5));
+    if (nt < kTargetsPerItem) {
+        items[at] = make_int4(c, s0, nt, lanes_log2(nt) | (seg << 5));
+        return;
     }
+    const int r = nt % kTargetsPerItem, dense_end = nt - r;
+    int k = 0;
+    for (int t0 = 0; t0 < dense_end; ++k) {
+        const int cn = (two && dense_end - t0 >= 2 * kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
+        items[at + k] = make_int4(c, s0 + t0, cn, ((cn > kTargetsPerItem ? 1 : 0) << 4) | (seg << 5));
+        t0 += cn;
+    }
+    if (r > 0) items[at + k] = make_int4(c, s0 + dense_end, r, lanes_log2(r) | (seg << 5));
 }
 
 // --------------------------------------------------------------- pair kernels

@@ -320,7 +320,7 @@ def main() -> int:
 
     if args.sweep:
         sr.bin(pos, mass, w.problem, w.n_active, ws=ws)
-        saved = sr.launch_config()
+        saved = {k: sr.launch_config(kernel=k) for k in ("force", "vjp")}
         for waves in (16, 24, 32):
             for tpl in (1, 2):
                 for occ in (0, 6, 8):
@@ -340,7 +340,8 @@ def main() -> int:
                     print(json.dumps({"waves_per_cu": waves, "targets_per_lane": tpl, "occupancy": occ,
                                       "force_ms": round(f_ms / f_n, 3), "vjp_ms": round(v_ms / v_n, 3)}),
                           flush=True)
-        sr.launch_config(*saved)
+        for k, v in saved.items():
+            sr.launch_config(*v, kernel=k)
         return 0
 
     # useful pairs of both passes, counted once outside the timed region

@@ -356,10 +356,18 @@ sr_status sr_power_spectrum(sr_pk_plan *plan, const float *pos, const float *mas
  *   occupancy         register-allocation variant of the pair kernels: 0 (none),
  *                     6 or 8 waves per SIMD (-1 keeps the current value).
  * None of them changes results: every target sums its sources in the same
- * order.  The values in effect are written to cur (host, nullable, int[3]).
- * Initial values come from SR_WAVES_PER_CU / SR_TARGETS_PER_LANE / SR_OCCUPANCY. */
+ * order.  sr_launch_config sets the forward and adjoint kernels alike and
+ * writes the forward kernel's values in effect to cur (host, nullable,
+ * int[3]).  The initial values differ per kernel (forward: 32, 1, 6; adjoint:
+ * 24, 2, 0, the fastest measured); SR_WAVES_PER_CU / SR_TARGETS_PER_LANE /
+ * SR_OCCUPANCY override them for both. */
 sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy,
                            int *cur /*host out*/);
+
+/* Host only.  The same for one kernel: "force" (also sr_count_pairs) or
+ * "vjp"; cur receives that kernel's values. */
+sr_status sr_launch_config_kernel(const char *kernel /*host*/, int waves_per_cu,
+                                  int targets_per_lane, int occupancy, int *cur /*host out*/);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * launch of the pair kernels ("force", "vjp").  sr_timing_enable(1) clears

@@ -32,7 +32,8 @@ EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "
            "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
            "sr_blocks_reconcile_grad", "sr_centres_plan_create", "sr_centres_plan_destroy",
            "sr_centres", "sr_pk_plan_create", "sr_pk_plan_destroy", "sr_pk_deposit", "sr_pk_grid",
-           "sr_power_spectrum", "sr_launch_config", "sr_timing_enable", "sr_timing_read")
+           "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_timing_enable",
+           "sr_timing_read")
 
 
 class SRError(RuntimeError):
@@ -100,6 +101,7 @@ def lib():
         L.sr_pk_grid.argtypes = [p, p, p, p, p]
         L.sr_power_spectrum.argtypes = [p, p, p, i64, p, C.c_size_t, p, p, p, p]
         L.sr_launch_config.argtypes = [C.c_int, C.c_int, C.c_int, p]
+        L.sr_launch_config_kernel.argtypes = [C.c_char_p, C.c_int, C.c_int, C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
         for name in EXPORTS:
@@ -597,13 +599,19 @@ class PkPlan:
             pass
 
 
-def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: int = -1):
-    """Set and return (waves_per_cu, targets_per_lane, occupancy) of the single-problem calls.
+def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: int = -1,
+                  kernel: Optional[str] = None):
+    """Set and return (waves_per_cu, targets_per_lane, occupancy) of the single-problem calls:
+    both pair kernels, or only ``kernel`` ("force" or "vjp").
 
     0 keeps waves_per_cu / targets_per_lane, -1 keeps occupancy."""
     cur = (C.c_int * 3)()
-    _check(lib().sr_launch_config(int(waves_per_cu), int(targets_per_lane), int(occupancy), cur),
-           "sr_launch_config")
+    if kernel is None:
+        _check(lib().sr_launch_config(int(waves_per_cu), int(targets_per_lane), int(occupancy), cur),
+               "sr_launch_config")
+    else:
+        _check(lib().sr_launch_config_kernel(kernel.encode(), int(waves_per_cu), int(targets_per_lane),
+                                             int(occupancy), cur), "sr_launch_config_kernel")
     return int(cur[0]), int(cur[1]), int(cur[2])
 
 

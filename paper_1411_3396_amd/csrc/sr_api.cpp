@@ -178,32 +178,39 @@ sr_status check_ws(const void *ws, size_t ws_bytes, const Layout &L)
     return SR_OK;
 }
 
-std::atomic<int> g_waves_per_cu_default{32};
-std::atomic<int> g_targets_per_lane_default{2};
-std::atomic<int> g_occupancy_default{0};
+// Launch parameters of the single-problem pair kernels, per kernel: [0] the
+// forward kernel (and the pair count), [1] the adjoint.  Defaults are the
+// fastest settings measured on the node-share workload.
+constexpr int kCfgForce = 0, kCfgVjp = 1;
+std::atomic<int> g_waves_default[2] = {{32}, {24}};
+std::atomic<int> g_tpl_default[2] = {{1}, {2}};
+std::atomic<int> g_occ_default[2] = {{6}, {0}};
 
-// Launch defaults may be overridden for experiments: SR_WAVES_PER_CU, SR_TARGETS_PER_LANE,
-// SR_OCCUPANCY.
+// Launch defaults may be overridden for experiments (both kernels):
+// SR_WAVES_PER_CU, SR_TARGETS_PER_LANE, SR_OCCUPANCY.
 struct EnvDefaults {
     EnvDefaults()
     {
-        if (const char *v = std::getenv("SR_WAVES_PER_CU")) {
-            const int w = std::atoi(v);
-            if (w >= 1 && w <= 64) g_waves_per_cu_default = w;
-        }
-        if (const char *v = std::getenv("SR_TARGETS_PER_LANE")) {
-            const int t = std::atoi(v);
-            if (t == 1 || t == 2) g_targets_per_lane_default = t;
-        }
-        if (const char *v = std::getenv("SR_OCCUPANCY")) {
-            const int o = std::atoi(v);
-            if (o == 0 || o == 6 || o == 8) g_occupancy_default = o;
+        for (int k = 0; k < 2; ++k) {
+            if (const char *v = std::getenv("SR_WAVES_PER_CU")) {
+                const int w = std::atoi(v);
+                if (w >= 1 && w <= 64) g_waves_default[k] = w;
+            }
+            if (const char *v = std::getenv("SR_TARGETS_PER_LANE")) {
+                const int t = std::atoi(v);
+                if (t == 1 || t == 2) g_tpl_default[k] = t;
+            }
+            if (const char *v = std::getenv("SR_OCCUPANCY")) {
+                const int o = std::atoi(v);
+                if (o == 0 || o == 6 || o == 8) g_occ_default[k] = o;
+            }
         }
     }
 } g_env_defaults;
 
 sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *seg_host,
-                      const SegParams *seg_dev, void *stream, int waves_per_cu, int64_t n_rows)
+                      const SegParams *seg_dev, void *stream, int waves_per_cu, int64_t n_rows,
+                      int cfg = kCfgForce)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SR_E_DEVICE;
@@ -225,11 +232,11 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.seg_host = seg_host;
     a.seg_dev = seg_dev;
     a.st = static_cast<hipStream_t>(stream);
-    a.waves_per_cu = waves_per_cu > 0 ? waves_per_cu : g_waves_per_cu_default.load();
+    a.waves_per_cu = waves_per_cu > 0 ? waves_per_cu : g_waves_default[cfg].load();
     a.num_cu = cus;
     a.n_rows = (int)n_rows;
-    a.targets_per_lane = g_targets_per_lane_default.load();
-    a.occupancy = g_occupancy_default.load();
+    a.targets_per_lane = g_tpl_default[cfg].load();
+    a.occupancy = g_occ_default[cfg].load();
     return SR_OK;
 }
 
@@ -459,7 +466,7 @@ sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, 
     const Cand cand[] = {{16, 1, 0}, {32, 1, 0}, {16, 2, 0}, {32, 2, 0}, {24, 1, 6},
                          {32, 1, 6}, {24, 2, 6}, {32, 2, 6}, {32, 1, 8}, {32, 2, 8}};
     double best = 1e300;
-    Cand pick{g_waves_per_cu_default.load(), 1, 0};
+    Cand pick{g_waves_default[kCfgForce].load(), 1, 0};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SR_E_DEVICE;
     for (const Cand &c : cand) {
@@ -607,7 +614,7 @@ sr_status sr_force_vjp(const float *pos, const float *mass, int64_t n, int64_t n
     if ((st = check_ws(ws, ws_bytes, s.L)) != SR_OK) return st;
     if (n == 0) return SR_OK;
     DevArgs a;
-    if ((st = device_args(a, ws, &s.L, &s.seg, nullptr, stream, 0, n_active)) != SR_OK) return st;
+    if ((st = device_args(a, ws, &s.L, &s.seg, nullptr, stream, 0, n_active, kCfgVjp)) != SR_OK) return st;
     if (!(flags & SR_REUSE_BINS) && dev_bin(a, pos, mass) != hipSuccess) return SR_E_DEVICE;
     return hip_status(dev_vjp(a, g, grad_pos));
 }
@@ -815,19 +822,50 @@ sr_status sr_batch_plan_info(const sr_batch_plan *P, char *buf, size_t buf_bytes
     return SR_OK;
 }
 
-sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy, int *cur)
+namespace {
+
+sr_status set_config(int k, int waves_per_cu, int targets_per_lane, int occupancy)
 {
     if (waves_per_cu < 0 || waves_per_cu > 64 || targets_per_lane < 0 || targets_per_lane > 2)
         return SR_E_ARG;
     if (occupancy != -1 && occupancy != 0 && occupancy != 6 && occupancy != 8) return SR_E_ARG;
-    if (waves_per_cu > 0) g_waves_per_cu_default = waves_per_cu;
-    if (targets_per_lane > 0) g_targets_per_lane_default = targets_per_lane;
-    if (occupancy >= 0) g_occupancy_default = occupancy;
-    if (cur) {
-        cur[0] = g_waves_per_cu_default.load();
-        cur[1] = g_targets_per_lane_default.load();
-        cur[2] = g_occupancy_default.load();
-    }
+    if (waves_per_cu > 0) g_waves_default[k] = waves_per_cu;
+    if (targets_per_lane > 0) g_tpl_default[k] = targets_per_lane;
+    if (occupancy >= 0) g_occ_default[k] = occupancy;
+    return SR_OK;
+}
+
+void get_config(int k, int *cur)
+{
+    if (!cur) return;
+    cur[0] = g_waves_default[k].load();
+    cur[1] = g_tpl_default[k].load();
+    cur[2] = g_occ_default[k].load();
+}
+
+}  // namespace
+
+sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy, int *cur)
+{
+    // validate once, then apply to both kernels
+    sr_status st = set_config(kCfgForce, waves_per_cu, targets_per_lane, occupancy);
+    if (st != SR_OK) return st;
+    (void)set_config(kCfgVjp, waves_per_cu, targets_per_lane, occupancy);
+    get_config(kCfgForce, cur);
+    return SR_OK;
+}
+
+sr_status sr_launch_config_kernel(const char *kernel, int waves_per_cu, int targets_per_lane,
+                                  int occupancy, int *cur)
+{
+    if (!kernel) return SR_E_ARG;
+    int k = -1;
+    if (std::strcmp(kernel, "force") == 0) k = kCfgForce;
+    if (std::strcmp(kernel, "vjp") == 0) k = kCfgVjp;
+    if (k < 0) return SR_E_ARG;
+    const sr_status st = set_config(k, waves_per_cu, targets_per_lane, occupancy);
+    if (st != SR_OK) return st;
+    get_config(k, cur);
     return SR_OK;
 }
 

@@ -112,11 +112,17 @@ def test_launch_config_validation():
     assert L.sr_launch_config(65, 0, -1, cur) == 1
     assert L.sr_launch_config(0, 3, -1, cur) == 1
     assert L.sr_launch_config(0, 0, 7, cur) == 1
-    saved = _sr.launch_config()
+    saved = {k: _sr.launch_config(kernel=k) for k in ("force", "vjp")}
+    assert saved["force"] == (32, 1, 6) and saved["vjp"] == (24, 2, 0)  # defaults differ per kernel
     assert _sr.launch_config(16, 2, 6) == (16, 2, 6)
-    assert _sr.launch_config() == (16, 2, 6)
-    _sr.launch_config(*saved)
-    assert _sr.launch_config() == saved
+    assert _sr.launch_config() == (16, 2, 6) and _sr.launch_config(kernel="vjp") == (16, 2, 6)
+    assert _sr.launch_config(8, 1, 0, kernel="vjp") == (8, 1, 0)
+    assert _sr.launch_config() == (16, 2, 6)  # the forward kernel's values are untouched
+    assert L.sr_launch_config_kernel(b"bogus", 0, 0, -1, cur) == 1
+    assert L.sr_launch_config_kernel(b"vjp", 0, 0, 7, cur) == 1
+    for k, v in saved.items():
+        _sr.launch_config(*v, kernel=k)
+    assert {k: _sr.launch_config(kernel=k) for k in ("force", "vjp")} == saved
 
 
 def test_batch_plan_validation_and_layout():

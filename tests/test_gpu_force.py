@@ -166,7 +166,7 @@ def test_launch_configs_agree_bitwise():
     w = synth.clustered_box(150000, 36.0, 30, 3, halo_frac=0.7, mass_range=(1e3, 1e5))
     w.mass = np.random.default_rng(2).uniform(0.5, 2.0, w.n).astype(np.float32)
     g = synth.cotangent(w.n_active, 5)
-    saved = sr.launch_config()
+    saved = {k: sr.launch_config(kernel=k) for k in ("force", "vjp")}
     ref = gref = None
     try:
         for waves, tpl, occ in [(32, 1, 0), (8, 2, 6), (16, 2, 8), (24, 1, 6), (32, 2, 0)]:
@@ -182,7 +182,8 @@ def test_launch_configs_agree_bitwise():
             assert np.array_equal(a.view(np.uint32), ref.view(np.uint32)), (waves, tpl, occ)
             assert np.array_equal(gr.view(np.uint32), gref.view(np.uint32)), (waves, tpl, occ)
     finally:
-        sr.launch_config(*saved)
+        for k, v in saved.items():
+            sr.launch_config(*v, kernel=k)
 
 
 def test_equal_masses_other_than_one():

@@ -95,7 +95,7 @@ def lib():
         L.sr_centres_plan_create.argtypes = [C.c_int32, p, p, p]
         L.sr_centres_plan_destroy.argtypes = [p]
         L.sr_centres.argtypes = [p, p, p, C.c_float, p, C.c_size_t, p, p, p, p]
-        L.sr_pk_plan_create.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_double, p, p]
+        L.sr_pk_plan_create.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_double, i64, p, p]
         L.sr_pk_plan_destroy.argtypes = [p]
         L.sr_pk_deposit.argtypes = [p, p, p, i64, p, C.c_size_t, p]
         L.sr_pk_grid.argtypes = [p, p, p, p, p]
@@ -546,12 +546,13 @@ def halo_centres(pos, mass, offsets, eps):
 class PkPlan:
     """Power spectrum of particles on an ng^3 periodic grid (sr_pk_*)."""
 
-    def __init__(self, ng: int, box: float, n_bins: int, dn: float = 1.0):
+    def __init__(self, ng: int, box: float, n_bins: int, dn: float = 1.0, n_max: int = 0):
         self.ng, self.box, self.n_bins, self.dn = int(ng), float(box), int(n_bins), float(dn)
+        self.n_max = int(n_max)
         self._plan = C.c_void_p()
         nbytes = C.c_size_t()
-        _check(lib().sr_pk_plan_create(self.ng, self.box, self.n_bins, self.dn, C.byref(self._plan),
-                                       C.byref(nbytes)), "sr_pk_plan_create")
+        _check(lib().sr_pk_plan_create(self.ng, self.box, self.n_bins, self.dn, self.n_max,
+                                       C.byref(self._plan), C.byref(nbytes)), "sr_pk_plan_create")
         self.ws_bytes = int(nbytes.value)
 
     def deposit(self, pos, mass, ws, stream=None):

@@ -2,9 +2,12 @@
 // deposit onto an ng^3 periodic grid, a real-to-complex FFT, |delta(k)|^2
 // divided by the CIC window and averaged in bins of |k|.
 //
-// Device passes: a fill of the grid, the deposit (eight float32 atomic adds
-// per particle into the FFT's padded in-place layout), a float64 mass sum in
-// a fixed order, the FFT (rocFFT, in place), and the binning: every mode of
+// Device passes: the deposit into the FFT's padded in-place layout, a
+// float64 mass sum in a fixed order, the FFT (rocFFT, in place), and the
+// binning.  For grids up to 1024^3 the deposit is atomic-free: particles are
+// sorted by the cell of their lower corner point (the binning's radix sort)
+// and every grid point gathers its 8 cells in float64, in a fixed order;
+// larger grids use eight float32 atomic adds per particle.  Binning: every mode of
 // the half spectrum adds w |rho_k|^2 / W(k)^2 (w = 2 for modes whose mirror
 // is not stored) into per-workgroup float64 bins in LDS; a last pass adds
 // the workgroups' bins in workgroup order.
@@ -63,6 +66,83 @@ __global__ __launch_bounds__(256) void k_cic_deposit(const float *__restrict__ p
             atomicAdd(&grid[row + (i0[2] + 1 == ng ? 0 : i0[2] + 1)], wxy * f[2]);
         }
     }
+}
+
+// Sorted deposit, step 1: per particle the grid cell of its lower corner
+// point (the sort key) and (f_x, f_y, f_z, m), by the same wrap rule.
+__global__ __launch_bounds__(256) void k_cic_key(const float *__restrict__ pos,
+                                                 const float *__restrict__ mass, int n, int ng,
+                                                 float inv_h, int *__restrict__ key,
+                                                 float4 *__restrict__ pf)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float fng = (float)ng;
+    int i0[3];
+    float f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float u = pos[3 * (int64_t)i + d] * inv_h;
+        u = u - floorf(u / fng) * fng;
+        int k = (int)floorf(u);
+        float fr = u - (float)k;
+        if (k >= ng) {
+            k = 0;
+            fr = 0.f;
+        }
+        if (k < 0) k = 0;
+        i0[d] = k;
+        f[d] = fr;
+    }
+    key[i] = (i0[0] * ng + i0[1]) * ng + i0[2];
+    pf[i] = make_float4(f[0], f[1], f[2], mass[i]);
+}
+
+__global__ __launch_bounds__(256) void k_cic_pack(const int *__restrict__ perm, int n,
+                                                  const float4 *__restrict__ pf,
+                                                  float4 *__restrict__ spf)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) spf[i] = pf[perm[i]];
+}
+
+// Sorted deposit, step 2: every grid point sums, in float64 and a fixed
+// order, the particles of the 8 cells whose lower corner is the point or its
+// lower neighbours (cells (p - c) for c in {0,1}^3, periodic).
+__global__ __launch_bounds__(256) void k_cic_gather(const int *__restrict__ cstart,
+                                                    const float4 *__restrict__ spf, int ng, int pad,
+                                                    float *__restrict__ grid)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)ng * ng * ng;
+    if (g >= total) return;
+    const int iz = (int)(g % ng);
+    const int64_t r = g / ng;
+    const int iy = (int)(r % ng), ix = (int)(r / ng);
+    double sum = 0.0;
+#pragma unroll
+    for (int cx = 0; cx < 2; ++cx) {
+        const int x = cx ? (ix == 0 ? ng - 1 : ix - 1) : ix;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+            const int y = cy ? (iy == 0 ? ng - 1 : iy - 1) : iy;
+#pragma unroll
+            for (int cz = 0; cz < 2; ++cz) {
+                const int z = cz ? (iz == 0 ? ng - 1 : iz - 1) : iz;
+                const int c = (x * ng + y) * ng + z;
+                const int e = cstart[c + 1];
+                for (int p = cstart[c]; p < e; ++p) {
+                    const float4 v = spf[p];
+                    // this point is the particle's corner point + (cx, cy, cz)
+                    const float wx = cx ? v.x : 1.f - v.x;
+                    const float wy = cy ? v.y : 1.f - v.y;
+                    const float wz = cz ? v.z : 1.f - v.z;
+                    sum += (double)(v.w * wx * wy * wz);
+                }
+            }
+        }
+    }
+    grid[((int64_t)ix * ng + iy) * pad + iz] = (float)sum;
 }
 
 // Float64 sum of the masses: strided partial sums per thread, a fixed tree
@@ -176,8 +256,13 @@ using namespace sr;
 struct sr_pk_plan {
     int ng = 0, n_bins = 0;
     double box = 0.0, dn = 1.0;
+    int64_t n_max = 0;
+    bool sorted = false;  // atomic-free sorted deposit (grids up to 1024^3)
+    int passes = 1, digit_bits = 1;
+    int64_t tiles = 1;
     size_t grid_off = 0, grid_bytes = 0, sinc_off = 0, mass_off = 0, part_off = 0, work_off = 0,
-           ws_bytes = 0;
+           key_off[2] = {0, 0}, val_off[2] = {0, 0}, pf_off = 0, spf_off = 0, cstart_off = 0,
+           tab_off = 0, tabx_off = 0, scan_off = 0, ws_bytes = 0;
     rocfft_plan fft = nullptr;
     size_t work_bytes = 0;
     bool fft_failed = false;
@@ -220,11 +305,40 @@ sr_status check_pk_ws(const sr_pk_plan *P, const void *ws, size_t ws_bytes)
 sr_status deposit(sr_pk_plan *P, const float *pos, const float *mass, int64_t n, char *w, hipStream_t s)
 {
     float *grid = reinterpret_cast<float *>(w + P->grid_off);
-    if (dev_zero(grid, (int64_t)(P->grid_bytes / 4), s) != hipSuccess) return SR_E_DEVICE;
-    if (n > 0) {
-        const int pad = 2 * (P->ng / 2 + 1);
-        k_cic_deposit<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pos, mass, (int)n, P->ng,
-                                                                 (float)(P->ng / P->box), pad, grid);
+    const int pad = 2 * (P->ng / 2 + 1);
+    const float inv_h = (float)(P->ng / P->box);
+    auto I = [&](size_t off) { return reinterpret_cast<int *>(w + off); };
+    if (!P->sorted) {
+        if (dev_zero(grid, (int64_t)(P->grid_bytes / 4), s) != hipSuccess) return SR_E_DEVICE;
+        if (n > 0) {
+            k_cic_deposit<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pos, mass, (int)n, P->ng, inv_h,
+                                                                     pad, grid);
+            if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+        }
+    } else {
+        const int64_t cells = (int64_t)P->ng * P->ng * P->ng;
+        float4 *pf = reinterpret_cast<float4 *>(w + P->pf_off);
+        float4 *spf = reinterpret_cast<float4 *>(w + P->spf_off);
+        if (n > 0) {
+            k_cic_key<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pos, mass, (int)n, P->ng, inv_h,
+                                                                 I(P->key_off[1]), pf);
+            if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+            // stable radix sort of the cell keys; pass p writes buffer p & 1
+            const int64_t tiles = std::max<int64_t>(1, (n + kRadixTile - 1) / kRadixTile);
+            const RadixBufs rb{{I(P->key_off[0]), I(P->key_off[1])}, {I(P->val_off[0]), I(P->val_off[1])},
+                               I(P->tab_off), I(P->tabx_off), I(P->scan_off)};
+            if (radix_sort_pairs(I(P->key_off[1]), nullptr, n, P->passes, P->digit_bits, tiles, rb, s) !=
+                hipSuccess)
+                return SR_E_DEVICE;
+            const int out = (P->passes - 1) & 1;
+            k_cic_pack<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(I(P->val_off[out]), (int)n, pf, spf);
+            if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+            if (dev_bounds(I(P->key_off[out]), n, cells, 0, I(P->cstart_off), s) != hipSuccess)
+                return SR_E_DEVICE;
+        } else if (dev_zero(I(P->cstart_off), cells + 1, s) != hipSuccess) {
+            return SR_E_DEVICE;
+        }
+        k_cic_gather<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(I(P->cstart_off), spf, P->ng, pad, grid);
         if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
     }
     double *part = reinterpret_cast<double *>(w + P->mass_off);
@@ -237,19 +351,22 @@ sr_status deposit(sr_pk_plan *P, const float *pos, const float *mass, int64_t n,
 
 extern "C" {
 
-sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, sr_pk_plan **plan,
-                            size_t *ws_bytes)
+sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, int64_t n_max,
+                            sr_pk_plan **plan, size_t *ws_bytes)
 {
     if (!plan || !ws_bytes) return SR_E_ARG;
     *plan = nullptr;
     if (ng < 2 || ng > 2048 || (ng & 1) || !(box > 0.0) || !std::isfinite(box) || n_bins < 1 ||
-        n_bins > kMaxBins || !(dn > 0.0) || !std::isfinite(dn))
+        n_bins > kMaxBins || !(dn > 0.0) || !std::isfinite(dn) || n_max < 0 ||
+        n_max > (int64_t(1) << 31) - 1)
         return SR_E_ARG;
     auto *P = new sr_pk_plan;
     P->ng = ng;
     P->box = box;
     P->n_bins = n_bins;
     P->dn = dn;
+    P->n_max = n_max;
+    P->sorted = ng <= 1024;  // cell keys fit 30 bits
     const int nzh = ng / 2 + 1;
     P->grid_bytes = (size_t)ng * ng * 2 * nzh * sizeof(float);
     size_t o = 0;
@@ -266,6 +383,34 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, s
     // conservative bound (one complex grid), checked again at the first run
     P->work_bytes = (size_t)ng * ng * nzh * 2 * sizeof(float);
     o = align256(o + P->work_bytes);
+    if (P->sorted) {
+        const int64_t cells = (int64_t)ng * ng * ng;
+        int bits = 1;
+        while ((int64_t(1) << bits) < cells) ++bits;
+        P->passes = (bits + 7) / 8;
+        P->digit_bits = (bits + P->passes - 1) / P->passes;
+        const int64_t m = std::max<int64_t>(1, n_max);
+        P->tiles = std::max<int64_t>(1, (m + kRadixTile - 1) / kRadixTile);
+        const int64_t table = (int64_t(1) << P->digit_bits) * P->tiles;
+        for (int k = 0; k < 2; ++k) {
+            P->key_off[k] = o;
+            o = align256(o + sizeof(int) * m);
+            P->val_off[k] = o;
+            o = align256(o + sizeof(int) * m);
+        }
+        P->pf_off = o;
+        o = align256(o + sizeof(float4) * m);
+        P->spf_off = o;
+        o = align256(o + sizeof(float4) * m);
+        P->cstart_off = o;
+        o = align256(o + sizeof(int) * (cells + 1));
+        P->tab_off = o;
+        o = align256(o + sizeof(int) * table);
+        P->tabx_off = o;
+        o = align256(o + sizeof(int) * (table + 1));
+        P->scan_off = o;
+        o = align256(o + sizeof(int) * scan_scratch_elems(table));
+    }
     P->ws_bytes = o;
     *plan = P;
     *ws_bytes = P->ws_bytes;
@@ -284,7 +429,7 @@ sr_status sr_pk_deposit(sr_pk_plan *P, const float *pos, const float *mass, int6
                         size_t ws_bytes, void *stream)
 {
     if (!P) return SR_E_PLAN;
-    if (n < 0 || n > (int64_t(1) << 31) - 1 || (n > 0 && (!pos || !mass))) return SR_E_ARG;
+    if (n < 0 || n > P->n_max || (n > 0 && (!pos || !mass))) return SR_E_ARG;
     const sr_status st = check_pk_ws(P, ws, ws_bytes);
     if (st != SR_OK) return st;
     return deposit(P, pos, mass, n, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
@@ -306,7 +451,7 @@ sr_status sr_power_spectrum(sr_pk_plan *P, const float *pos, const float *mass, 
                             size_t ws_bytes, double *pk, double *k, int64_t *modes, void *stream)
 {
     if (!P) return SR_E_PLAN;
-    if (n < 1 || n > (int64_t(1) << 31) - 1 || !pos || !mass || !pk) return SR_E_ARG;
+    if (n < 1 || n > P->n_max || !pos || !mass || !pk) return SR_E_ARG;
     sr_status st = check_pk_ws(P, ws, ws_bytes);
     if (st != SR_OK) return st;
     if ((st = ensure_fft(P)) != SR_OK) return st;

@@ -162,3 +162,33 @@ def test_empty_blocks_and_all_passive():
     assert bf.forward(pos, mass).shape == (0, 3)
     assert np.all(bf.counts[:, 0] == 0)
     bf.close()
+
+
+def test_refinement_by_pair_counts_stays_exact():
+    # a clustered slab: equal 2x2 blocks, then Sec. 2.1's rule (split a block
+    # costing more than twice the mean) for a few rounds by pair counts; the
+    # irregular blocks that result still give the oracle's forces
+    from paper_1411_3396_amd.blocks import balanced_blocks, equal_blocks as eq, refine as rf
+
+    w = synth.slab_with_ghosts(24, 3.0, 12, 3)
+    ng = grid_units(w.problem)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    blocks, history = balanced_blocks(pos, mass, w.problem, w.n_active, nbx=2, nby=2, kind="pairs",
+                                      max_rounds=4, ng=ng)
+    announce(f"refined blocks: {len(history)} rounds, {len(blocks)} blocks")
+    # replay the rule on the recorded costs: the same blocks come out
+    replay = eq(ng, 2, 2)
+    for cost in history:
+        nxt = rf(replay, cost)
+        if nxt == replay:
+            break
+        replay = nxt
+    assert replay == blocks and len(blocks) > 4
+    assert history[0].max() > 2.0 * history[0].mean()
+    bf = BlockForce(w.problem, blocks, w.n, w.n_active, ng=ng, device=DEV, tune_cache=None)
+    acc = bf.forward(pos, mass).cpu().numpy()
+    times = bf.block_costs(pos, mass, kind="time", repeats=1)
+    assert np.all(times[bf.counts[:, 0] > 0] > 0)
+    bf.close()
+    ref, _ = oracle.force(w.pos, w.mass, w.n_active, w.problem)
+    assert_force_close(acc, ref, what="refined blocks")

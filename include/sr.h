@@ -312,16 +312,15 @@ sr_status sr_centres(sr_centres_plan *plan, const float *pos, const float *mass,
  * left out), with delta = rho / mean(rho) - 1.  Deposit: a particle at
  * u = x / h, wrapped into [0, ng), gives m (1 - f) to grid point floor(u) and
  * m f to floor(u) + 1 per axis (f = u - floor(u)), the product over axes to
- * each of 8 points; grid points sit at multiples of h.  For ng <= 1024 the
- * particles are sorted by cell and every grid point sums its contributions
- * in float64 in a fixed order (results are reproducible bit for bit); larger
- * grids use float32 atomic additions (the order of additions into one point
- * is not fixed).  The FFT is rocFFT's single-precision real-to-complex
- * transform, in place in the workspace; mode sums are float64.  Non-finite
- * positions make the spectrum non-finite. */
+ * each of 8 points; grid points sit at multiples of h.  The particles are
+ * sorted by cell and every grid point sums its contributions in float64 in a
+ * fixed order (the grid is reproducible bit for bit).  The FFT is rocFFT's
+ * single-precision real-to-complex transform, in place in the workspace;
+ * mode sums are float64.  Non-finite positions make the spectrum
+ * non-finite. */
 typedef struct sr_pk_plan sr_pk_plan;
 
-/* Host only.  2 <= ng <= 2048, ng even; box > 0; 1 <= n_bins <= 2048; dn > 0
+/* Host only.  2 <= ng <= 1024, ng even; box > 0; 1 <= n_bins <= 2048; dn > 0
  * (bin width in units of the fundamental 2 pi / box); n_max: the most
  * particles a call will pass (sizes the workspace), 0 <= n_max < 2^31. */
 sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, int64_t n_max,

@@ -4,10 +4,9 @@
 //
 // Device passes: the deposit into the FFT's padded in-place layout, a
 // float64 mass sum in a fixed order, the FFT (rocFFT, in place), and the
-// binning.  For grids up to 1024^3 the deposit is atomic-free: particles are
-// sorted by the cell of their lower corner point (the binning's radix sort)
-// and every grid point gathers its 8 cells in float64, in a fixed order;
-// larger grids use eight float32 atomic adds per particle.  Binning: every mode of
+// binning.  The deposit is atomic-free: particles are sorted by the cell of
+// their lower corner point (the binning's radix sort) and every grid point
+// gathers its 8 cells in float64, in a fixed order.  Binning: every mode of
 // the half spectrum adds w |rho_k|^2 / W(k)^2 (w = 2 for modes whose mirror
 // is not stored) into per-workgroup float64 bins in LDS; a last pass adds
 // the workgroups' bins in workgroup order.
@@ -26,47 +25,7 @@ namespace {
 constexpr int kBinBlocks = 512;  // workgroups of the binning pass
 constexpr int kSumBlocks = 256;  // workgroups of the mass sum
 constexpr int kMaxBins = 2048;
-
-// Grid point of each particle per axis: u = x / h wrapped into [0, ng), i0 =
-// floor(u) and the weights (1 - f, f) of points i0 and i0 + 1 (periodic).
-__global__ __launch_bounds__(256) void k_cic_deposit(const float *__restrict__ pos,
-                                                     const float *__restrict__ mass, int n, int ng,
-                                                     float inv_h, int pad, float *__restrict__ grid)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const float fng = (float)ng;
-    int i0[3];
-    float f[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        float u = pos[3 * (int64_t)i + d] * inv_h;
-        u = u - floorf(u / fng) * fng;
-        int k = (int)floorf(u);
-        float fr = u - (float)k;
-        if (k >= ng) {  // u rounded up to ng
-            k = 0;
-            fr = 0.f;
-        }
-        if (k < 0) k = 0;  // non-finite input
-        i0[d] = k;
-        f[d] = fr;
-    }
-    const float m = mass[i];
-#pragma unroll
-    for (int cx = 0; cx < 2; ++cx) {
-        const int x = cx ? (i0[0] + 1 == ng ? 0 : i0[0] + 1) : i0[0];
-        const float wx = m * (cx ? f[0] : 1.f - f[0]);
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy) {
-            const int y = cy ? (i0[1] + 1 == ng ? 0 : i0[1] + 1) : i0[1];
-            const float wxy = wx * (cy ? f[1] : 1.f - f[1]);
-            const int64_t row = ((int64_t)x * ng + y) * pad;
-            atomicAdd(&grid[row + i0[2]], wxy * (1.f - f[2]));
-            atomicAdd(&grid[row + (i0[2] + 1 == ng ? 0 : i0[2] + 1)], wxy * f[2]);
-        }
-    }
-}
+constexpr int kMaxGrid = 1024;  // ng^3 cell keys fit 30 bits
 
 // Sorted deposit, step 1: per particle the grid cell of its lower corner
 // point (the sort key) and (f_x, f_y, f_z, m), by the same wrap rule.
@@ -257,7 +216,6 @@ struct sr_pk_plan {
     int ng = 0, n_bins = 0;
     double box = 0.0, dn = 1.0;
     int64_t n_max = 0;
-    bool sorted = false;  // atomic-free sorted deposit (grids up to 1024^3)
     int passes = 1, digit_bits = 1;
     int64_t tiles = 1;
     size_t grid_off = 0, grid_bytes = 0, sinc_off = 0, mass_off = 0, part_off = 0, work_off = 0,
@@ -308,14 +266,7 @@ sr_status deposit(sr_pk_plan *P, const float *pos, const float *mass, int64_t n,
     const int pad = 2 * (P->ng / 2 + 1);
     const float inv_h = (float)(P->ng / P->box);
     auto I = [&](size_t off) { return reinterpret_cast<int *>(w + off); };
-    if (!P->sorted) {
-        if (dev_zero(grid, (int64_t)(P->grid_bytes / 4), s) != hipSuccess) return SR_E_DEVICE;
-        if (n > 0) {
-            k_cic_deposit<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pos, mass, (int)n, P->ng, inv_h,
-                                                                     pad, grid);
-            if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
-        }
-    } else {
+    {
         const int64_t cells = (int64_t)P->ng * P->ng * P->ng;
         float4 *pf = reinterpret_cast<float4 *>(w + P->pf_off);
         float4 *spf = reinterpret_cast<float4 *>(w + P->spf_off);
@@ -356,7 +307,7 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
 {
     if (!plan || !ws_bytes) return SR_E_ARG;
     *plan = nullptr;
-    if (ng < 2 || ng > 2048 || (ng & 1) || !(box > 0.0) || !std::isfinite(box) || n_bins < 1 ||
+    if (ng < 2 || ng > kMaxGrid || (ng & 1) || !(box > 0.0) || !std::isfinite(box) || n_bins < 1 ||
         n_bins > kMaxBins || !(dn > 0.0) || !std::isfinite(dn) || n_max < 0 ||
         n_max > (int64_t(1) << 31) - 1)
         return SR_E_ARG;
@@ -366,7 +317,6 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
     P->n_bins = n_bins;
     P->dn = dn;
     P->n_max = n_max;
-    P->sorted = ng <= 1024;  // cell keys fit 30 bits
     const int nzh = ng / 2 + 1;
     P->grid_bytes = (size_t)ng * ng * 2 * nzh * sizeof(float);
     size_t o = 0;
@@ -383,8 +333,8 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
     // conservative bound (one complex grid), checked again at the first run
     P->work_bytes = (size_t)ng * ng * nzh * 2 * sizeof(float);
     o = align256(o + P->work_bytes);
-    if (P->sorted) {
-        const int64_t cells = (int64_t)ng * ng * ng;
+    {
+        const int64_t cells = (int64_t)ng * ng * ng;  // cell keys fit 30 bits
         int bits = 1;
         while ((int64_t(1) << bits) < cells) ++bits;
         P->passes = (bits + 7) / 8;

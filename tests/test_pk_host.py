@@ -15,7 +15,7 @@ def _create(ng, box=100.0, n_bins=10, dn=1.0, n_max=1000):
 
 def test_plan_validation_and_sizes():
     assert _create(64)[0] == 0
-    for bad in (dict(ng=63), dict(ng=0), dict(ng=4096), dict(ng=64, box=0.0), dict(ng=64, box=float("inf")),
+    for bad in (dict(ng=63), dict(ng=0), dict(ng=2048), dict(ng=64, box=0.0), dict(ng=64, box=float("inf")),
                 dict(ng=64, n_bins=0), dict(ng=64, n_bins=5000), dict(ng=64, dn=0.0),
                 dict(ng=64, n_max=-1), dict(ng=64, n_max=1 << 31)):
         assert _create(**bad)[0] == 1, bad

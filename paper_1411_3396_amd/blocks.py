@@ -89,19 +89,39 @@ class _PhaseClock:
         self.t = t
 
 
+def membership_estimate(domain, ng: Sequence[int], blocks: Sequence[Rect]) -> float:
+    """Memberships per particle for a uniform density: the widened rectangles'
+    areas inside the domain, over the domain's area."""
+    lo = [float(domain.lo[0]), float(domain.lo[1])]
+    ln = [float(domain.len[0]), float(domain.len[1])]
+    r = float(domain.r_s)
+    total = 0.0
+    for b in blocks:
+        area = 1.0
+        for a, (g0, g1) in enumerate(((b[0], b[1]), (b[2], b[3]))):
+            x0 = lo[a] + g0 * ln[a] / ng[a] - (r if g0 > 0 else 0.0)
+            x1 = lo[a] + g1 * ln[a] / ng[a] + (r if g1 < ng[a] else 0.0)
+            area *= max(0.0, min(x1, lo[a] + ln[a]) - max(x0, lo[a]))
+        total += area
+    return total / (ln[0] * ln[1])
+
+
 class BlockForce:
     """Short-range forces of one open domain computed block by block.
 
-    ``capacity`` bounds the total memberships (0: the worst case); when a
-    partition needs more, the plan is rebuilt with the reported need."""
+    ``capacity`` bounds the total memberships; by default it is 1.3 times the
+    uniform-density estimate.  When a partition needs more (clustering), the
+    plan is rebuilt with the reported need."""
 
     def __init__(self, domain, blocks: Sequence[Rect], n: int, n_active: Optional[int] = None,
-                 ng: Optional[Sequence[int]] = None, capacity: int = 0, device="cuda",
+                 ng: Optional[Sequence[int]] = None, capacity: Optional[int] = None, device="cuda",
                  tune_cache: Optional[str] = TUNE_CACHE):
         self.domain = domain
         self.ng = tuple(ng) if ng is not None else grid_units(domain)
         self.blocks = [tuple(int(v) for v in b) for b in blocks]
         self.n = int(n)
+        if capacity is None:
+            capacity = int(1.3 * membership_estimate(domain, self.ng, self.blocks) * self.n) + 4096
         self.n_active = self.n if n_active is None else int(n_active)
         self.device = device
         self.tune_cache = tune_cache

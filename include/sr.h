@@ -34,8 +34,8 @@
  *    is enqueued (no partial work).  n == 0 is a valid no-op.
  *  - Conditions found on the device (non-finite positions, positions outside
  *    an open domain) set bits in the workspace, read by sr_ws_flags.
- *  - All functions are thread-safe except that one batch plan must not be
- *    used from two threads at once.
+ *  - All functions are thread-safe except that one plan (batch, blocks,
+ *    centres or power spectrum) must not be used from two threads at once.
  */
 #ifndef SR_H
 #define SR_H

@@ -655,6 +655,9 @@ __device__ __forceinline__ float4 fetch_pos(const Stencil &st, int v, const Src 
 
 // Pull the next work item: queues are interleaved blocks of kQueueBlock
 // items of the cost-ordered list; a wave drains the queue of its XCD first.
+// The persistent loops that call this end their bodies without a lane-0-only
+// branch: otherwise the compiler may merge that branch with this one across
+// the back edge and let the other lanes start the next item without lane 0.
 __device__ __forceinline__ int64_t next_item(uint32_t *hdr, int q, int lane)
 {
     uint32_t c = 0;
@@ -958,7 +961,9 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
                 ay += __shfl_xor(ay, o);
                 az += __shfl_xor(az, o);
             }
-            if (tv && sub == 0) store3(out, n_out, out_row[t0 + t], m0 * ax, m0 * ay, m0 * az);
+            // every lane of a target's group holds the same sum: all store it, so the
+            // loop body ends without a single-lane branch (see next_item)
+            if (tv) store3(out, n_out, out_row[t0 + t], m0 * ax, m0 * ay, m0 * az);
         }
     }
 }
@@ -1084,7 +1089,7 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
                 ry += __shfl_xor(ry, o);
                 rz += __shfl_xor(rz, o);
             }
-            if (tv && sub == 0) store3(out, n_out, perm[t0 + t], m0 * rx, m0 * ry, m0 * rz);
+            if (tv) store3(out, n_out, perm[t0 + t], m0 * rx, m0 * ry, m0 * rz);
         }
     }
 }

@@ -195,3 +195,42 @@ def test_equal_masses_other_than_one():
     g = synth.cotangent(w.n, 3)
     gr = sr.force_vjp(to_dev(w.pos), to_dev(w.mass), w.problem, to_dev(g)).cpu().numpy()
     assert oracle.rms_rel(gr, oracle.vjp(w.pos, w.mass, w.n, w.problem, g)) <= 1e-4
+
+
+def test_item_boundaries():
+    # cells holding 1, 31, 32, 63, 64, 65, 127, 128, 129, 191, 192, 193 and 300
+    # targets: the item split (groups of 64 or 128, the last nt mod 64 on their
+    # own with 2^lk lanes each) at every boundary, under both target layouts;
+    # forward and adjoint against the oracle, and bitwise equal across layouts
+    counts = [1, 31, 32, 63, 64, 65, 127, 128, 129, 191, 192, 193, 300, 0, 7, 0, 2, 0, 0, 0, 0, 0, 0, 0, 0, 0, 5]
+    L, nc = 12.0, 4  # periodic box of 4^3 cells of side 3
+    rng = np.random.default_rng(21)
+    parts = []
+    for c, k in enumerate(counts):
+        ix, iy, iz = c // 16, (c // 4) % 4, c % 4
+        parts.append((np.array([ix, iy, iz]) + rng.random((k, 3))) * (L / nc))
+    w = synth.uniform_box(1, L, 0)
+    w.pos = np.concatenate(parts).astype(np.float32)
+    w.pos = w.pos[rng.permutation(w.pos.shape[0])]
+    w.mass = rng.uniform(0.5, 2.0, w.pos.shape[0]).astype(np.float32)
+    w.n_active = w.pos.shape[0]
+    assert tuple(sr.grid(w.problem)) == (nc, nc, nc)
+    g = synth.cotangent(w.n, 8)
+    ref = oracle_force(w)
+    gref = oracle.vjp(w.pos, w.mass, w.n, w.problem, g)
+    saved = {k: sr.launch_config(kernel=k) for k in ("force", "vjp")}
+    out = []
+    try:
+        for tpl in (1, 2):
+            sr.launch_config(0, tpl, 0)
+            announce(f"item boundaries targets_per_lane={tpl}")
+            a = gpu_force(w)
+            gr = sr.force_vjp(to_dev(w.pos), to_dev(w.mass), w.problem, to_dev(g)).cpu().numpy()
+            assert_force_close(a, ref, what=f"item boundaries tpl={tpl}")
+            assert oracle.rms_rel(gr, gref) <= 1e-4
+            out.append((a, gr))
+    finally:
+        for k, v in saved.items():
+            sr.launch_config(*v, kernel=k)
+    assert np.array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
+    assert np.array_equal(out[0][1].view(np.uint32), out[1][1].view(np.uint32))

@@ -32,8 +32,8 @@ def lib():
         L = C.CDLL(_LIB_PATH)
         L.oracle_num_threads.restype = C.c_int
         L.oracle_grid.argtypes = [_p, C.c_float, C.c_int, _p]
-        L.oracle_bin_reference.argtypes = [_p, _i64, _i64, _p, _p, C.c_int, C.c_float, _p, _p, _p, _p,
-                                           _p]
+        L.oracle_bin_reference.argtypes = [_p, _i64, _i64, _p, _p, C.c_int, C.c_float, C.c_int, _p, _p,
+                                           _p, _p, _p]
         L.oracle_force.argtypes = [_p, _p, _i64, _i64, _p, _p, C.c_int, C.c_double, C.c_double, _p,
                                    _p, _i64, _p, _p]
         L.oracle_force_brute.argtypes = [_p, _p, _i64, _i64, _p, _p, C.c_int, C.c_double,
@@ -84,7 +84,9 @@ def grid(prob) -> np.ndarray:
 
 
 def bin_reference(pos32: np.ndarray, prob, n_active=None) -> dict:
-    """Float32 binning rule: cell ids, cell starts, permutation, offsets."""
+    """Float32 binning rule: cell ids, cell starts, permutation, offsets; each
+    cell ordered by the leaves of an octree of prob.leaf_depth levels (1 when
+    absent or 0)."""
     pos32 = np.ascontiguousarray(pos32, dtype=np.float32).reshape(-1, 3)
     n = pos32.shape[0]
     n_active = n if n_active is None else int(n_active)
@@ -97,8 +99,9 @@ def bin_reference(pos32: np.ndarray, prob, n_active=None) -> dict:
     flags = np.zeros(1, np.uint32)
     lo = np.ascontiguousarray(np.asarray(prob.lo, np.float32))
     ln = np.ascontiguousarray(np.asarray(prob.len, np.float32))
+    depth = int(getattr(prob, "leaf_depth", 1)) or 1
     rc = lib().oracle_bin_reference(_ptr(pos32), n, n_active, _ptr(lo), _ptr(ln), int(bool(prob.periodic)),
-                                    C.c_float(prob.r_s), _ptr(cell_of), _ptr(start), _ptr(perm),
+                                    C.c_float(prob.r_s), depth, _ptr(cell_of), _ptr(start), _ptr(perm),
                                     _ptr(off), _ptr(flags))
     _check(rc, "oracle_bin_reference")
     return {"nc": nc, "cell_of": cell_of, "cell_start": start, "perm": perm, "off": off,

@@ -23,7 +23,10 @@
  *   oracle_bin_reference  the float32 cell-binning rule the library's binning
  *                         must reproduce bit for bit (the rule is a reading:
  *                         the paper names chaining-mesh binning only through
- *                         the HACC papers);
+ *                         the HACC papers), with the particles of each cell
+ *                         ordered by the leaves of an octree of a given depth
+ *                         inside the cell (tree codes are the paper's
+ *                         short-range solver on CPU systems, Sec. 2);
  *   oracle_force          the sum above through a float64 cell list;
  *   oracle_force_brute    the same sum over all pairs and all 27 periodic
  *                         images, no cells;
@@ -119,50 +122,86 @@ static int bin_coord(float x, float lo, float len, int nc, int periodic, float *
     return i;
 }
 
+/* Leaf of an octree of `depth` levels inside the cell that holds a particle
+ * at offset o from the cell centre (cell sides h).  Per axis, level 1 takes
+ * the sign of the offset; each deeper level first re-centres the offset on
+ * the half it fell in (subtract or add a quarter of the current side, in
+ * float32) and takes the sign again.  The code lists the levels from the
+ * top, one octal digit 4 b_x + 2 b_y + b_z each (Z order). */
+static int64_t leaf_code(const float o[3], const float h[3], int depth)
+{
+    int b[3][8];
+    for (int d = 0; d < 3; ++d) {
+        float off = o[d];
+        float quarter = h[d] * 0.25f;
+        for (int l = 0; l < depth; ++l) {
+            b[d][l] = off >= 0.0f;
+            off = b[d][l] ? off - quarter : off + quarter;
+            quarter = quarter * 0.5f;
+        }
+    }
+    int64_t code = 0;
+    for (int l = 0; l < depth; ++l) code = 8 * code + 4 * b[0][l] + 2 * b[1][l] + b[2][l];
+    return code;
+}
+
+typedef struct {
+    int64_t key; /* (cell, passive, leaf code) */
+    int64_t p;   /* input index */
+} bin_entry;
+
+static int cmp_entry(const void *a, const void *b)
+{
+    const bin_entry *x = (const bin_entry *)a, *y = (const bin_entry *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->p > y->p) - (x->p < y->p);
+}
+
 /* cell_of[n] (input order), cell_start[ncell+1], perm[n] (binned slot ->
  * input index) and off[3n] (binned order).  Cells are numbered
- * (ix*ncy + iy)*ncz + iz.  Slots are ordered by (cell, passive, octant, input
- * index): passive = index >= n_active, octant = 4 [off_x >= 0] +
- * 2 [off_y >= 0] + [off_z >= 0]. */
+ * (ix*ncy + iy)*ncz + iz.  Slots are ordered by (cell, passive, leaf code,
+ * input index): passive = index >= n_active; the leaf code is that of an
+ * octree of leaf_depth levels (1..4); at depth 1 it is the octant
+ * 4 [off_x >= 0] + 2 [off_y >= 0] + [off_z >= 0]. */
 int oracle_bin_reference(const float *pos, int64_t n, int64_t n_active, const float lo[3],
-                         const float len[3], int periodic, float r_s, int32_t *cell_of,
-                         int32_t *cell_start, int32_t *perm, float *off, uint32_t *flags_out)
+                         const float len[3], int periodic, float r_s, int leaf_depth,
+                         int32_t *cell_of, int32_t *cell_start, int32_t *perm, float *off,
+                         uint32_t *flags_out)
 {
     int32_t nc[3];
     int rc = oracle_grid(len, r_s, periodic, nc);
     if (rc) return rc;
     if (periodic && (lo[0] != 0.0f || lo[1] != 0.0f || lo[2] != 0.0f)) return -3;
     if (n_active < 0 || n_active > n) return -1;
+    if (leaf_depth < 1 || leaf_depth > 4) return -1;
     const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    float h[3];
+    for (int d = 0; d < 3; ++d) h[d] = len[d] / (float)nc[d];
     uint32_t flags = 0;
     float *o = (float *)malloc(sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
+    bin_entry *e = (bin_entry *)malloc(sizeof(bin_entry) * (size_t)(n > 0 ? n : 1));
+    const int64_t leaves = (int64_t)1 << (3 * leaf_depth);
     for (int64_t p = 0; p < n; ++p) {
         int ic[3];
         for (int d = 0; d < 3; ++d)
             ic[d] = bin_coord(pos[3 * p + d], lo[d], len[d], nc[d], periodic, &o[3 * p + d], &flags);
         cell_of[p] = (int32_t)(((int64_t)ic[0] * nc[1] + ic[1]) * nc[2] + ic[2]);
+        e[p].key = (2 * (int64_t)cell_of[p] + (p >= n_active ? 1 : 0)) * leaves + leaf_code(&o[3 * p], h, leaf_depth);
+        e[p].p = p;
     }
-    /* counting sort on key = 16 cell + 8 passive + octant: counts, exclusive
-     * prefix sum, then placement in input order */
-    const int64_t nkey = 16 * ncell;
-    int64_t *kstart = (int64_t *)calloc((size_t)nkey + 1, sizeof(int64_t));
-    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    for (int64_t p = 0; p < n; ++p) {
-        int oct = (o[3 * p] >= 0.0f ? 4 : 0) + (o[3 * p + 1] >= 0.0f ? 2 : 0) + (o[3 * p + 2] >= 0.0f ? 1 : 0);
-        key[p] = 16 * (int64_t)cell_of[p] + (p >= n_active ? 8 : 0) + oct;
-        kstart[key[p] + 1]++;
+    qsort(e, (size_t)n, sizeof(bin_entry), cmp_entry);
+    /* the first slot of each cell: count per cell, then an exclusive prefix sum */
+    for (int64_t c = 0; c <= ncell; ++c) cell_start[c] = 0;
+    for (int64_t p = 0; p < n; ++p) cell_start[cell_of[p] + 1]++;
+    for (int64_t c = 0; c < ncell; ++c) cell_start[c + 1] += cell_start[c];
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t p = e[s].p;
+        perm[s] = (int32_t)p;
+        off[3 * s + 0] = o[3 * p + 0];
+        off[3 * s + 1] = o[3 * p + 1];
+        off[3 * s + 2] = o[3 * p + 2];
     }
-    for (int64_t k = 0; k < nkey; ++k) kstart[k + 1] += kstart[k];
-    for (int64_t c = 0; c <= ncell; ++c) cell_start[c] = (int32_t)kstart[16 * c];
-    for (int64_t p = 0; p < n; ++p) {
-        int32_t slot = (int32_t)kstart[key[p]]++;
-        perm[slot] = (int32_t)p;
-        off[3 * (int64_t)slot + 0] = o[3 * p + 0];
-        off[3 * (int64_t)slot + 1] = o[3 * p + 1];
-        off[3 * (int64_t)slot + 2] = o[3 * p + 2];
-    }
-    free(kstart);
-    free(key);
+    free(e);
     free(o);
     if (flags_out) *flags_out = flags;
     return 0;

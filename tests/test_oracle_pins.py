@@ -495,3 +495,92 @@ def test_bin_reference_float32_formula():
     assert np.array_equal(res["off"], off[res["perm"]])
     octant = 4 * (off[:, 0] >= 0) + 2 * (off[:, 1] >= 0) + (off[:, 2] >= 0)
     assert np.array_equal(res["perm"], np.lexsort((np.arange(len(cell)), octant, cell)))
+
+
+# ---------------------------------------------------------------- tree-leaf order inside a cell
+
+def _zorder(k, depth):
+    """Z-order code of integer sub-cell indices k [n, 3]: top level first, x bit highest."""
+    code = np.zeros(k.shape[0], np.int64)
+    for level in range(depth - 1, -1, -1):
+        bits = (k >> level) & 1
+        code = 8 * code + 4 * bits[:, 0] + 2 * bits[:, 1] + bits[:, 2]
+    return code
+
+
+def test_leaf_order_of_subcell_centres():
+    # one particle at the centre of each of the 8^3 sub-cells of one cell, in
+    # shuffled input order: binned order is the Z order of the integer indices
+    P = prob(30.0, True).with_leaf_depth(3)
+    h = 3.0
+    k = np.stack(np.meshgrid(*(np.arange(8),) * 3, indexing="ij"), -1).reshape(-1, 3)
+    rng = RNG(4)
+    shuffle = rng.permutation(len(k))
+    k = k[shuffle]
+    pos = (3 * h + (k + 0.5) * (h / 8)).astype(np.float32)  # cell (3, 3, 3)
+    res = oracle.bin_reference(pos, P)
+    assert np.all(res["cell_of"] == (3 * 10 + 3) * 10 + 3)
+    assert np.array_equal(res["perm"], np.argsort(_zorder(k, 3), kind="stable"))
+    # depth 1 on the same points is the octant order
+    res1 = oracle.bin_reference(pos, P.with_leaf_depth(1))
+    octant = 4 * (k[:, 0] >= 4) + 2 * (k[:, 1] >= 4) + (k[:, 2] >= 4)
+    assert np.array_equal(res1["perm"], np.argsort(octant, kind="stable"))
+
+
+@pytest.mark.parametrize("depth", [2, 3, 4])
+def test_leaf_order_matches_subcell_geometry(depth):
+    # float64 geometry: the sub-cell of side h / 2^depth holding each offset.
+    # Along the binned order, the particles clear of every sub-cell face are
+    # sorted by (cell, passive, Z-order code of that sub-cell, input index).
+    w = synth.slab_with_ghosts(30, 3.0, 60, 7)
+    P = w.problem.with_leaf_depth(depth)
+    res = oracle.bin_reference(w.pos, P, w.n_active)
+    n = w.n
+    nc = res["nc"].astype(np.float64)
+    h = np.array(P.len, np.float64) / nc
+    off = res["off"].astype(np.float64)  # binned order
+    m = 2 ** depth
+    v = (off + 0.5 * h) / (h / m)
+    k = np.clip(np.floor(v), 0, m - 1).astype(np.int64)
+    clear = np.all(np.abs(v - np.round(v)) > 1e-4, axis=1) & np.all((v > 0) & (v < m), axis=1)
+    perm = res["perm"].astype(np.int64)
+    cell = res["cell_of"][perm].astype(np.int64)
+    passive = (perm >= w.n_active).astype(np.int64)
+    key = np.stack([cell, passive, _zorder(k, depth), perm], 1)[clear]
+    assert clear.mean() > 0.9
+    order = np.lexsort(key.T[::-1])
+    assert np.array_equal(order, np.arange(len(key)))
+    # the same particles and cells as at depth 1; only the order inside a cell differs
+    res1 = oracle.bin_reference(w.pos, w.problem, w.n_active)
+    assert np.array_equal(res1["cell_start"], res["cell_start"])
+    assert np.array_equal(res1["cell_of"], res["cell_of"])
+    for c in np.flatnonzero(np.diff(res["cell_start"]) > 0)[:200]:
+        a, b = res["cell_start"][c], res["cell_start"][c + 1]
+        assert np.array_equal(np.sort(res["perm"][a:b]), np.sort(res1["perm"][a:b]))
+
+
+def test_leaf_order_float32_rule():
+    # the written rule in numpy float32: re-centre on the half, halve the step
+    w = synth.clustered_box(20000, 27.0, 25, 13)
+    depth = 3
+    res = oracle.bin_reference(w.pos, w.problem.with_leaf_depth(depth))
+    f = np.float32
+    h = f(27.0) / f(res["nc"][0])
+    o = res["off"].copy()  # binned order
+    q = np.full(3, h * f(0.25), np.float32)
+    code = np.zeros(len(o), np.int64)
+    for level in range(depth):
+        b = o >= f(0)
+        code = 8 * code + 4 * b[:, 0] + 2 * b[:, 1] + b[:, 2]
+        o = np.where(b, o - q, o + q).astype(np.float32)
+        q = (q * f(0.5)).astype(np.float32)
+    perm = res["perm"]
+    cell = res["cell_of"][perm]
+    assert np.array_equal(np.lexsort((perm, code, cell)), np.arange(len(perm)))
+
+
+def test_leaf_depth_rejected_outside_range():
+    pos = np.zeros((4, 3), np.float32)
+    for bad in (5, -1):
+        with pytest.raises(Exception):
+            oracle.bin_reference(pos, prob(30.0, True).with_leaf_depth(bad))

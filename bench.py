@@ -138,6 +138,54 @@ def block_comparison(w, pos, mass, acc_mono, reps: int = 3):
     return out
 
 
+def leaf_comparison(w, reps: int = 3, depths=(1, 2, 3, 4)):
+    """Bin, forward and adjoint kernel times of one workload with the cells
+    ordered by the leaves of an octree of each depth (depth 1: octants)."""
+    import torch
+
+    import paper_1411_3396_amd as sr
+    from paper_1411_3396_amd import synth
+
+    dev = "cuda:0"
+    pos = torch.from_numpy(w.pos).to(dev)
+    mass = torch.from_numpy(w.mass).to(dev)
+    g = torch.from_numpy(synth.cotangent(w.n_active, 1)).to(dev)
+    acc = torch.empty((w.n_active, 3), device=dev)
+    grad = torch.empty((w.n, 3), device=dev)
+    out = {"workload": w.name, "n": w.n}
+    for d in depths:
+        prob = w.problem.with_leaf_depth(d)
+        try:
+            ws = sr.new_workspace(sr.workspace_bytes(w.n, prob), dev)
+        except sr.SRError as e:
+            out[f"depth{d}"] = str(e)
+            continue
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        sr.bin(pos, mass, prob, w.n_active, ws=ws)
+        sr.force(pos, mass, prob, w.n_active, ws=ws, reuse_bins=True, out=acc)
+        sr.force_vjp(pos, mass, prob, g, w.n_active, ws=ws, reuse_bins=True, out=grad)
+        torch.cuda.synchronize()
+        bin_ms = 0.0
+        sr.timing_enable(True)
+        for _ in range(reps):
+            ev[0].record()
+            sr.bin(pos, mass, prob, w.n_active, ws=ws)
+            ev[1].record()
+            sr.force(pos, mass, prob, w.n_active, ws=ws, reuse_bins=True, out=acc)
+            sr.force_vjp(pos, mass, prob, g, w.n_active, ws=ws, reuse_bins=True, out=grad)
+            torch.cuda.synchronize()
+            bin_ms += ev[0].elapsed_time(ev[1])
+        f_ms, f_n = sr.timing_read("force")
+        v_ms, v_n = sr.timing_read("vjp")
+        sr.timing_enable(False)
+        out[f"depth{d}"] = {"bin_ms": round(bin_ms / reps, 3), "force_ms": round(f_ms / f_n, 3),
+                            "vjp_ms": round(v_ms / v_n, 3)}
+        log(f"leaves {w.name} depth {d}: {out[f'depth{d}']}")
+        del ws
+        torch.cuda.empty_cache()
+    return out
+
+
 FLOP_PER_POTENTIAL_PAIR = 12  # 3 sub, 3 FMA, rsqrt, 1 FMA
 
 
@@ -262,10 +310,13 @@ def main() -> int:
     ap.add_argument("--no-blocks", action="store_true")
     ap.add_argument("--no-centres", action="store_true")
     ap.add_argument("--no-pk", action="store_true")
+    ap.add_argument("--no-leaves", action="store_true")
+    ap.add_argument("--leaf-depth", type=int, default=1,
+                    help="octree depth of the in-cell order of the main workload (1: octants)")
     ap.add_argument("--sweep", action="store_true",
                     help="time the pair kernels under every launch configuration "
                          "(waves per CU, targets per lane, occupancy variant); one JSON line each")
-    ap.add_argument("--only", choices=["force", "vjp", "copy", "centres", "pk"],
+    ap.add_argument("--only", choices=["force", "vjp", "copy", "centres", "pk", "leaves"],
                     help="profiling mode: bin once, then run only this kernel --steps times "
                          "(copy: a 1 GiB device-to-device copy of known size; centres: the halo "
                          "catalogue's centre finder); prints no JSON")
@@ -288,6 +339,10 @@ def main() -> int:
         out = centres_measure(reps=args.steps)
         log(f"centres {args.steps} runs: {out['ms']} ms each")
         return 0
+    if args.only == "leaves":
+        for name in ("clustered_2m_extreme", args.workload):
+            print(json.dumps(leaf_comparison(synth.get(name), reps=args.steps)), flush=True)
+        return 0
     if args.only == "copy":
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -298,6 +353,8 @@ def main() -> int:
         return 0
     t0 = time.perf_counter()
     w = synth.get(args.workload)
+    if args.leaf_depth != 1:
+        w.problem = w.problem.with_leaf_depth(args.leaf_depth)
     g_np = synth.cotangent(w.n_active, 1)
     log(f"workload {w.name}: n={w.n} n_active={w.n_active} ({time.perf_counter() - t0:.1f} s to generate)")
     pos = torch.from_numpy(w.pos).to(dev)
@@ -427,6 +484,7 @@ def main() -> int:
         "config": {"workload": w.name, "n": w.n, "n_active": w.n_active,
                    "n_ghost": w.n - w.n_active, "cells": int(np.prod(sr.grid(w.problem))),
                    "r_s": w.problem.r_s, "eps": round(w.problem.eps, 6), "periodic": w.problem.periodic,
+                   "leaf_depth": w.problem.leaf_depth,
                    "step": "bin + force + adjoint + float64 momentum", "parallelism": "none"},
         "pairs_forward": pairs_fwd,
         "pairs_adjoint": pairs_bwd,
@@ -447,6 +505,9 @@ def main() -> int:
         log("overlapping data blocks")
         result["blocks"] = block_comparison(w, pos, mass, acc)
         result["blocks_force_ms_single_domain"] = round(phase["bin"] + phase["force"], 3)
+    if not args.no_leaves:
+        log("tree-leaf order on the extreme-clustering box")
+        result["leaves"] = leaf_comparison(synth.get("clustered_2m_extreme"))
     if not args.no_pk:
         log("power spectrum")
         result["pk"] = pk_measure()

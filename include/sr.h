@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SR_ABI_VERSION 1
+#define SR_ABI_VERSION 2
 
 typedef enum sr_status {
     SR_OK = 0,
@@ -83,7 +83,17 @@ typedef enum sr_status {
  *  periodic  1: minimum-image periodic box; 0: open domain.
  *  r_s       cutoff radius (> 0).
  *  eps       Plummer softening length (>= 0); eps^2 is added to s.
- *  poly      filter polynomial coefficients poly[k] of s^k. */
+ *  poly      filter polynomial coefficients poly[k] of s^k.
+ *  leaf_depth  depth D of the octree inside each chaining cell whose leaves
+ *            order the cell's particles (the tree-leaf variant of the binning
+ *            for strongly clustered matter; tree codes are the paper's
+ *            short-range solver on CPU systems, Sec. 2).  1..4; 0 means 1.
+ *            D = 1 orders a cell by octant; larger D by the Z-order (Morton)
+ *            code of 2^D x 2^D x 2^D sub-cells, so that each run of 64
+ *            targets the pair kernels take as one item is a compact leaf.
+ *            Every D gives the same interactions; only the grouping of
+ *            targets, and so the work per item, changes.  Needs
+ *            ncell * 2^(3 D + 1) < 2^31, else SR_E_UNSUPPORTED. */
 typedef struct sr_problem {
     float lo[3];
     float len[3];
@@ -91,6 +101,7 @@ typedef struct sr_problem {
     float r_s;
     float eps;
     float poly[6];
+    int32_t leaf_depth;
 } sr_problem;
 
 /* Device arrays of a binned workspace (all in binned order unless noted).
@@ -100,9 +111,14 @@ typedef struct sr_problem {
  *   i_d = clamp(floor(u * (nc/len)), 0, nc-1)   (u = w when periodic; NaN -> 0)
  *   cell = (i_x * nc_y + i_y) * nc_z + i_z
  *   offset = w - (lo + (i + 0.5) * (len/nc))    (distance from the cell centre)
- *   octant = 4 [off_x >= 0] + 2 [off_y >= 0] + [off_z >= 0]
- * Particles are ordered by (cell, passive, octant, input index): within a
- * cell the active particles come first, each group sorted by octant. */
+ *   leaf code, per axis: o = offset, q = (len/nc) * 0.25;  level 1 bit
+ *     b = [o >= 0];  each further level: o = b ? o - q : o + q (float32),
+ *     q = q * 0.5, b = [o >= 0].  Level l contributes 4 b_x + 2 b_y + b_z
+ *     as the l-th octal digit from the top: code = sum_l 8^(D-l) digit_l.
+ *     With D = 1 the code is the octant 4 [off_x >= 0] + 2 [off_y >= 0] +
+ *     [off_z >= 0].
+ * Particles are ordered by (cell, passive, leaf code, input index): within a
+ * cell the active particles come first, each group sorted by leaf code. */
 typedef struct sr_bin_layout {
     int32_t nc[3];
     int64_t ncell;

@@ -44,7 +44,8 @@ class SRError(RuntimeError):
 
 class Problem(C.Structure):
     _fields_ = [("lo", C.c_float * 3), ("len", C.c_float * 3), ("periodic", C.c_int32),
-                ("r_s", C.c_float), ("eps", C.c_float), ("poly", C.c_float * 6)]
+                ("r_s", C.c_float), ("eps", C.c_float), ("poly", C.c_float * 6),
+                ("leaf_depth", C.c_int32)]
 
 
 class Block(C.Structure):
@@ -57,6 +58,9 @@ class BinLayout(C.Structure):
                 ("off_x", C.c_void_p), ("off_y", C.c_void_p), ("off_z", C.c_void_p),
                 ("mass", C.c_void_p)]
 
+
+# sr_problem layout and entry points of include/sr.h (SR_ABI_VERSION)
+ABI_VERSION = 2
 
 _lib = None
 
@@ -107,6 +111,9 @@ def lib():
         for name in EXPORTS:
             if name not in ("sr_abi_version", "sr_status_str"):
                 getattr(L, name).restype = C.c_int
+        if L.sr_abi_version() != ABI_VERSION:
+            raise ImportError(f"libsr.so has ABI {L.sr_abi_version()}, this binding expects {ABI_VERSION}; "
+                              "rebuild with __graft_entry__.build()")
         _lib = L
     return _lib
 
@@ -117,7 +124,8 @@ def _check(code: int, what: str) -> None:
 
 
 def as_problem(prob) -> Problem:
-    """Problem struct from an object with lo, len, periodic, r_s, eps, poly."""
+    """Problem struct from an object with lo, len, periodic, r_s, eps, poly (and
+    optionally leaf_depth)."""
     if isinstance(prob, Problem):
         return prob
     s = Problem()
@@ -129,6 +137,7 @@ def as_problem(prob) -> Problem:
     s.eps = float(prob.eps)
     for k in range(6):
         s.poly[k] = float(prob.poly[k])
+    s.leaf_depth = int(getattr(prob, "leaf_depth", 1))
     return s
 
 

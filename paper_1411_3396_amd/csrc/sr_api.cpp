@@ -23,7 +23,7 @@ using namespace sr;
 namespace {
 
 constexpr int64_t kMaxParticles = (int64_t(1) << 31) - 1;
-constexpr int64_t kMaxCells = int64_t(1) << 26;  // cell << 4 fits the 31-bit sort key
+constexpr int64_t kMaxCells = int64_t(1) << 26;  // cell << 4 fits the 31-bit sort key at depth 1
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -36,6 +36,7 @@ sr_status grid_of(const sr_problem *p, int32_t nc[3])
     if (!(p->r_s > 0.0f) || !finitef(p->r_s)) return SR_E_ARG;
     if (!(p->eps >= 0.0f) || !finitef(p->eps)) return SR_E_ARG;
     if (p->periodic != 0 && p->periodic != 1) return SR_E_ARG;
+    if (p->leaf_depth < 0 || p->leaf_depth > kMaxLeafDepth) return SR_E_ARG;
     for (int k = 0; k < 6; ++k)
         if (!finitef(p->poly[k])) return SR_E_ARG;
     int64_t ncell = 1;
@@ -82,6 +83,16 @@ PairConsts pair_consts(const sr_problem *p)
     return pc;
 }
 
+int leaf_depth_of(const sr_problem *p) { return p->leaf_depth > 0 ? p->leaf_depth : 1; }
+
+// The sort key (cell << key_bits | passive << code_bits | code) must stay a
+// non-negative int32.
+bool key_fits(int64_t NC, int code_bits, bool any_passive)
+{
+    const int key_bits = code_bits + (any_passive ? 1 : 0);
+    return NC <= ((int64_t(1) << 31) - 1) >> key_bits;
+}
+
 SegParams seg_of(const sr_problem *p, const int32_t nc[3])
 {
     SegParams s{};
@@ -95,16 +106,18 @@ SegParams seg_of(const sr_problem *p, const int32_t nc[3])
     }
     s.periodic = p->periodic;
     s.pc = pair_consts(p);
+    s.leaf_depth = leaf_depth_of(p);
     return s;
 }
 
-Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_passive)
+Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_passive, int code_bits)
 {
     Layout L;
     L.N = N;
     L.NC = NC;
     L.B = B;
-    L.key_bits = any_passive ? 4 : 3;
+    L.code_bits = code_bits;
+    L.key_bits = code_bits + (any_passive ? 1 : 0);
     int bits = 1;
     while ((int64_t(1) << bits) < (NC << L.key_bits)) ++bits;
     L.passes = (bits + 7) / 8;
@@ -166,7 +179,9 @@ sr_status prepare_single(int64_t n, int64_t n_active, const sr_problem *p, Singl
     s.seg = seg_of(p, s.nc);
     s.seg.n = (int32_t)n;
     s.seg.n_active = (int32_t)n_active;
-    s.L = make_layout(n, s.NC, 1, mom_tiles_of(n), n_active < n);
+    const int code_bits = 3 * s.seg.leaf_depth;
+    if (!key_fits(s.NC, code_bits, n_active < n)) return SR_E_UNSUPPORTED;
+    s.L = make_layout(n, s.NC, 1, mom_tiles_of(n), n_active < n, code_bits);
     return SR_OK;
 }
 
@@ -715,8 +730,16 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets, const int64_t 
     P->summary = P->segs[0];
     P->summary.pc.softened = soft ? 1 : 0;
     bool any_passive = false;
-    for (int b = 0; b < B; ++b) any_passive = any_passive || (n_active[b] < offsets[b + 1] - offsets[b]);
-    P->L = make_layout(offsets[B], cell_off, B, tile_off, any_passive);
+    int depth = 1;
+    for (int b = 0; b < B; ++b) {
+        any_passive = any_passive || (n_active[b] < offsets[b + 1] - offsets[b]);
+        depth = std::max(depth, (int)P->segs[b].leaf_depth);
+    }
+    if (!key_fits(cell_off, 3 * depth, any_passive)) {
+        delete P;
+        return SR_E_UNSUPPORTED;
+    }
+    P->L = make_layout(offsets[B], cell_off, B, tile_off, any_passive, 3 * depth);
     // per-subvolume momentum scratch sits at the end of the workspace
     const size_t mom_tail = align256((size_t)(3 * mom_tiles_of(offsets[B]) + 3) * 8) + 512;
     P->ws_bytes = std::max(P->L.total, single_max + mom_tail);
@@ -735,7 +758,8 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets, const int64_t 
         std::ostringstream k;
         int nb = 0;
         while ((int64_t(1) << (nb + 1)) <= std::max<int64_t>(1, offsets[B])) ++nb;
-        k << arch_name() << "/force-v3/B" << B << "/log2N" << nb << "/soft" << (soft ? 1 : 0);
+        k << arch_name() << "/force-v3/B" << B << "/log2N" << nb << "/soft" << (soft ? 1 : 0)
+          << "/leaf" << P->L.code_bits / 3;
         P->tune_key = k.str();
     }
     *plan = P;

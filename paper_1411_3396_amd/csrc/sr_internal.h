@@ -19,6 +19,7 @@ constexpr int kClasses = 32;         // cost classes (floor log2 of the per-lane
 constexpr int kRadixTile = 2048;     // elements per radix-sort tile
 constexpr int kScanBlock = 2048;     // elements per scan block (256 threads x 8)
 constexpr int kMomTile = 65536;      // rows per momentum partial
+constexpr int kMaxLeafDepth = 4;     // deepest in-cell octree order
 
 // Constants of the pair kernel, evaluated in t = s + eps^2:
 //   f_SR = t^-3/2 - Q(t),  Q(t) = sum_k q[k] t^k = sum_k poly[k] (t - eps^2)^k,
@@ -48,7 +49,8 @@ struct SegParams {
     int32_t out_off;   // first output row of its accelerations
     int32_t tile_off;  // first momentum partial
     PairConsts pc;
-    int32_t pad[4];
+    int32_t leaf_depth;  // octree depth of the in-cell order (1 = octants)
+    int32_t pad[3];
 };
 static_assert(sizeof(SegParams) % 16 == 0, "SegParams must stay 16-byte sized");
 
@@ -72,7 +74,8 @@ struct Layout {
     int64_t NC = 0;    // cells (all segments)
     int32_t B = 1;     // segments
     int32_t passes = 0, digit_bits = 0;
-    int32_t key_bits = 3;   // low bits of the sort key below the cell: octant (+ passive flag)
+    int32_t code_bits = 3;  // leaf-code bits of the sort key: 3 per octree level
+    int32_t key_bits = 3;   // low bits of the sort key below the cell: (passive flag +) leaf code
     int64_t ntiles = 0;     // radix tiles
     int64_t table = 0;      // radix table entries (R * ntiles)
     int64_t item_cap = 0;   // upper bound on work items
@@ -88,7 +91,7 @@ struct Layout {
     uint32_t magic() const
     {
         uint32_t m = 0x9E3779B9u * (uint32_t)N ^ 0x85EBCA6Bu * (uint32_t)NC ^ 0xC2B2AE35u * (uint32_t)B ^
-                     0x27D4EB2Fu * (uint32_t)key_bits;
+                     0x27D4EB2Fu * (uint32_t)key_bits ^ 0x165667B1u * (uint32_t)code_bits;
         return m ? m : 1u;
     }
 };

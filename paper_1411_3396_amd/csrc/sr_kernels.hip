@@ -247,12 +247,36 @@ hipError_t scan_i32(const int *in, int *out, int64_t m, int *tmp, hipStream_t st
 
 // --------------------------------------------------------------- A1: cell index
 
-// Cell of each particle and its sort key: (cell, passive, octant), where the
-// octant holds the signs of the offsets from the cell centre, bit 2 = x.  With
-// key_bits = 3 there is no passive bit (every particle is active).
+// Leaf code of one particle: the path from the cell to its sub-cell of an
+// octree of the given depth, three bits (x, y, z) per level, the first level
+// on top.  Each level takes the signs of the offsets from the current
+// sub-cell's centre, then moves that centre a quarter of the current side
+// towards the particle.  Only float32 subtractions, halvings and sign tests.
+__device__ __forceinline__ int leaf_code(float ox, float oy, float oz, const SegParams &S)
+{
+    float qx = S.h[0] * 0.25f, qy = S.h[1] * 0.25f, qz = S.h[2] * 0.25f;
+    int bx = ox >= 0.f, by = oy >= 0.f, bz = oz >= 0.f;
+    int code = (bx << 2) | (by << 1) | bz;
+    for (int l = 1; l < S.leaf_depth; ++l) {
+        ox = bx ? ox - qx : ox + qx;
+        oy = by ? oy - qy : oy + qy;
+        oz = bz ? oz - qz : oz + qz;
+        qx *= 0.5f;
+        qy *= 0.5f;
+        qz *= 0.5f;
+        bx = ox >= 0.f;
+        by = oy >= 0.f;
+        bz = oz >= 0.f;
+        code = (code << 3) | (bx << 2) | (by << 1) | bz;
+    }
+    return code;
+}
+
+// Cell of each particle and its sort key: (cell, passive, leaf code).  With
+// key_bits == code_bits there is no passive bit (every particle is active).
 template <class Acc>
 __global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restrict__ pos, int N,
-                                                   int key_bits, int *__restrict__ cell_of,
+                                                   int key_bits, int code_bits, int *__restrict__ cell_of,
                                                    int *__restrict__ skey, uint32_t *hdr)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -268,10 +292,10 @@ __global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restr
     const int iz = bin_coord(pos[p + 2], S.lo[2], S.len[2], S.inv_len[2], S.h[2], S.inv_h[2],
                              S.nc[2], S.periodic, oz, fl);
     const int cell = S.cell_off + (ix * S.nc[1] + iy) * S.nc[2] + iz;
-    const int oct = (ox >= 0.f ? 4 : 0) | (oy >= 0.f ? 2 : 0) | (oz >= 0.f ? 1 : 0);
+    const int code = leaf_code(ox, oy, oz, S);
     const int passive = (i - S.part_off < S.n_active) ? 0 : 1;
     cell_of[i] = cell;
-    skey[i] = (cell << key_bits) | (key_bits > 3 ? passive << 3 : 0) | oct;
+    skey[i] = (cell << key_bits) | (key_bits > code_bits ? passive << code_bits : 0) | code;
     if (fl) atomicOr(&hdr[kHdrFlags], fl);
 }
 
@@ -1349,7 +1373,7 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
     if ((e = fill_u32(at<uint32_t>(a, L.nact), L.NC, 0, a.st)) != hipSuccess) return e;
     if (L.N == 0) return hipSuccess;
     e = with_acc(a, [&](auto acc) -> hipError_t {
-        k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, (int)L.N, L.key_bits,
+        k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, (int)L.N, L.key_bits, L.code_bits,
                                                              at<int>(a, L.cell_of), at<int>(a, L.skey),
                                                              at<uint32_t>(a, L.hdr));
         return hipGetLastError();

@@ -29,7 +29,7 @@ rounds up to the upper face folded back to the lower face):
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -54,15 +54,19 @@ class Problem:
     r_s: float
     eps: float
     poly: Tuple[float, ...]
+    leaf_depth: int = 1  # octree levels of the in-cell order (1 = octants)
 
     @staticmethod
-    def make(lo, length, periodic, r_s, eps, poly) -> "Problem":
+    def make(lo, length, periodic, r_s, eps, poly, leaf_depth: int = 1) -> "Problem":
         lo = tuple(f32(v) for v in lo)
         length = tuple(f32(v) for v in length)
         poly = tuple(f32(v) for v in poly)
         if len(poly) != 6:
             raise ValueError("poly needs 6 coefficients")
-        return Problem(lo, length, bool(periodic), f32(r_s), f32(eps), poly)
+        return Problem(lo, length, bool(periodic), f32(r_s), f32(eps), poly, int(leaf_depth))
+
+    def with_leaf_depth(self, depth: int) -> "Problem":
+        return replace(self, leaf_depth=int(depth))
 
 
 def filter_poly(r_s: float, eps: float) -> Tuple[float, ...]:

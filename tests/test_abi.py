@@ -28,7 +28,7 @@ def test_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(_sr.EXPORTS)
-    assert L.sr_abi_version() == 1
+    assert L.sr_abi_version() == 2
     assert L.sr_status_str(0) == b"ok"
 
 

@@ -65,6 +65,30 @@ def test_modes_agree_bitwise_and_match_oracle():
     plan.close()
 
 
+def test_mixed_leaf_depths_agree_bitwise():
+    # subvolumes with different in-cell octree depths in one batch: the
+    # batched key holds the deepest code, each subvolume orders by its own
+    b = mixed_batch()
+    depths = [1, 3, 2, 4, 3, 1, 2]
+    b.problems = [p.with_leaf_depth(d) for p, d in zip(b.problems, depths)]
+    plan = sr.BatchPlan(b.offsets, b.n_active, b.problems)
+    announce(f"batch leaf depths {depths}")
+    a_sub, _ = run(plan, b, "per_subvolume")
+    a_eag, _ = run(plan, b, "eager")
+    a_gra, _ = run(plan, b, "graph")
+    assert np.array_equal(a_sub.view(np.uint32), a_eag.view(np.uint32))
+    assert np.array_equal(a_eag.view(np.uint32), a_gra.view(np.uint32))
+    row = 0
+    for k in range(b.size):
+        part = b.part(k)
+        if part.n_active:
+            ref, _ = oracle.force(part.pos, part.mass, part.n_active, part.problem)
+            if np.any(ref != 0):
+                assert_force_close(a_gra[row: row + part.n_active], ref, what=f"subvolume {k} depth {depths[k]}")
+        row += part.n_active
+    plan.close()
+
+
 def test_graph_replays_with_eager_work_between():
     b = mixed_batch()
     plan = sr.BatchPlan(b.offsets, b.n_active, b.problems)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def check_bins(w):
-    announce(f"bin {w.name} n={w.n} n_active={w.n_active}")
+    announce(f"bin {w.name} n={w.n} n_active={w.n_active} leaf_depth={w.problem.leaf_depth}")
     pos, mass = to_dev(w.pos), to_dev(w.mass)
     ws = sr.bin(pos, mass, w.problem, w.n_active)
     v = sr.bin_view(ws, w.n, w.problem, w.n_active)
@@ -47,6 +47,37 @@ def test_bins_bit_exact(case):
         w = synth.uniform_box(3000, 9.0, 7)
         w.problem = synth.Problem.make((0, 0, 0), (2.5, 2.5, 2.5), False, 3.0, 0.05, w.problem.poly)
         w.pos = (w.pos / 9.0 * 2.5).astype(np.float32)
+    check_bins(w)
+
+
+def subcell_faces():
+    """Points on and one ulp either side of every sub-cell face of a depth-4
+    octree inside one cell (h = 4), plus a NaN and two outside the domain."""
+    f = np.float32
+    xs = [f(8 + 0.25 * j) for j in range(17)]
+    xs += [np.nextafter(f(10.0), f(0)), np.nextafter(f(10.0), f(20)), np.nextafter(f(9.0), f(0)),
+           np.nextafter(f(11.5), f(20)), np.nextafter(f(8.0), f(20)), np.nextafter(f(12.0), f(0))]
+    xs = np.array(xs, np.float32)
+    grid = np.array(np.meshgrid(xs, xs[::2], xs[1::2], indexing="ij")).reshape(3, -1).T
+    extra = np.array([[np.nan, 9.0, 9.0], [-1.0, 9.0, 9.0], [9.0, 40.0, 9.0]], np.float32)
+    w = synth.uniform_box(1, 32.0, 0)
+    w.pos = np.concatenate([grid, extra]).astype(np.float32)
+    w.mass = np.ones(w.pos.shape[0], np.float32)
+    w.n_active = w.pos.shape[0] - 500
+    w.problem = synth.Problem.make((0, 0, 0), (32.0, 32.0, 32.0), False, 4.0, 0.05, (0.0,) * 6)
+    return w
+
+
+@pytest.mark.parametrize("depth", [2, 3, 4])
+@pytest.mark.parametrize("case", ["clustered", "slab", "faces"])
+def test_leaf_order_bins_bit_exact(case, depth):
+    if case == "clustered":
+        w = synth.clustered_box(200000, 60.0, 40, 14)
+    elif case == "slab":
+        w = synth.slab_with_ghosts(40, 3.0, 150, 15)
+    else:
+        w = subcell_faces()
+    w.problem = w.problem.with_leaf_depth(depth)
     check_bins(w)
 
 

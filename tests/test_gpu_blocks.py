@@ -109,6 +109,20 @@ def test_block_forces_match_oracle(kind):
     bf.close()
 
 
+def test_block_forces_with_leaf_depth():
+    # the blocks inherit the domain's in-cell octree depth
+    w, ng, blocks = domain_case("refined")
+    w.problem = w.problem.with_leaf_depth(3)
+    announce("block forces refined, leaf depth 3")
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    bf = BlockForce(w.problem, blocks, w.n, w.n_active, ng=ng, device=DEV, tune_cache=None)
+    assert all(p.leaf_depth == 3 for p in bf.problems)
+    acc = bf.forward(pos, mass).cpu().numpy()
+    ref, _ = oracle.force(w.pos, w.mass, w.n_active, w.problem)
+    assert_force_close(acc, ref, what="blocks leaf depth 3")
+    bf.close()
+
+
 def test_block_vjp_matches_oracle():
     w, ng, blocks = domain_case("refined")
     announce("block vjp refined")

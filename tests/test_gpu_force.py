@@ -7,8 +7,8 @@ import torch
 import oracle
 import paper_1411_3396_amd as sr
 from paper_1411_3396_amd import synth
-from gpu_helpers import (DEV, FWD_TOL, announce, assert_force_close, gpu_force, oracle_force,
-                         to_dev)
+from gpu_helpers import (DEV, FWD_TOL, VJP_TOL, announce, assert_force_close, gpu_force, gpu_vjp,
+                         oracle_force, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -234,3 +234,31 @@ def test_item_boundaries():
             sr.launch_config(*v, kernel=k)
     assert np.array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
     assert np.array_equal(out[0][1].view(np.uint32), out[1][1].view(np.uint32))
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 4])
+def test_leaf_depths_match_oracle(depth):
+    # the tree-leaf order inside the cells (octree of `depth` levels): any
+    # depth gives the oracle's forces and gradients; only the grouping of
+    # targets into items changes
+    w = synth.clustered_box(60000, 30.0, 8, 23)
+    w.problem = w.problem.with_leaf_depth(depth)
+    announce(f"leaf depth {depth} n={w.n}")
+    assert_force_close(gpu_force(w), oracle_force(w), what=f"leaf depth {depth}")
+    g = synth.cotangent(w.n_active, 3)
+    err = oracle.rms_rel(gpu_vjp(w, g), oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g))
+    print(f"  vjp rms_rel={err:.3e}", flush=True)
+    assert err <= VJP_TOL
+    a1 = gpu_force(w)
+    assert np.array_equal(a1.view(np.uint32), gpu_force(w).view(np.uint32))
+
+
+def test_leaf_depth_extreme_clustering_sampled():
+    # the 2M-particle box with halos of absolute size (largest ~1e5 particles)
+    # at depth 3, sampled targets against the oracle
+    w = synth.clustered_2m_extreme()
+    w.problem = w.problem.with_leaf_depth(3)
+    announce(f"leaf depth 3 extreme n={w.n}")
+    tg = np.random.default_rng(3).choice(w.n_active, 1500, replace=False)
+    a = gpu_force(w)[tg]
+    assert_force_close(a, oracle_force(w, targets=tg), what="extreme depth 3 (sampled)")

@@ -85,6 +85,40 @@ def test_host_validation_codes():
     assert _force(ws_bytes=1024) == E_WS
 
 
+def test_leaf_depth_validation_and_key_width():
+    E_ARG, E_UNSUP = 1, 5
+    L = _sr.lib()
+    nc = (C.c_int32 * 3)()
+    nbytes = C.c_size_t()
+    for d in (-1, 5, 99):
+        p = prob()
+        p.leaf_depth = d
+        assert L.sr_grid(C.byref(p), nc) == E_ARG
+        assert _force(p=p) == E_ARG
+    for d in (0, 1, 2, 3, 4):  # 0 means 1
+        p = prob()
+        p.leaf_depth = d
+        assert L.sr_workspace_bytes(1000, C.byref(p), C.byref(nbytes)) == 0
+    # ncell * 2^(3D + 1) must fit the 31-bit key: 108^3 cells take D = 3, not D = 4
+    big = _sr.as_problem(synth.Problem.make((-3, -3, -3), (326.0,) * 3, False, 3.0, 0.05, (0,) * 6))
+    for d, want in ((3, 0), (4, E_UNSUP)):
+        big.leaf_depth = d
+        assert L.sr_workspace_bytes(1000, C.byref(big), C.byref(nbytes)) == want, d
+    # a batch keys on its deepest subvolume: each fits alone, not together
+    offs = np.array([0, 10, 20], np.int64)
+    nact = np.array([10, 10], np.int64)
+    small = prob()
+    small.leaf_depth = 4
+    big.leaf_depth = 1
+    assert L.sr_workspace_bytes(10, C.byref(small), C.byref(nbytes)) == 0
+    assert L.sr_workspace_bytes(10, C.byref(big), C.byref(nbytes)) == 0
+    probs = (_sr.Problem * 2)(small, big)
+    plan = C.c_void_p()
+    rc = L.sr_batch_plan_create(2, offs.ctypes.data_as(C.c_void_p), nact.ctypes.data_as(C.c_void_p), probs,
+                                None, C.byref(plan), C.byref(nbytes))
+    assert rc == E_UNSUP and not plan.value
+
+
 def test_empty_problem_is_a_noop_without_device():
     p = prob()
     assert _force(n=0, n_active=0, pos=None, mass=None, acc=None) == 0

@@ -767,6 +767,12 @@ __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float 
 
 // ------------------------------------------------------------- source culling
 
+// Survivors staged per pass of the pair loop (plus 64 padding entries): 4 KB
+// of LDS per forward wave, 6 KB per adjoint wave (two float4 per source), so
+// 32 forward or 24 adjoint waves fit in a CU's 160 KB.
+constexpr int kStageForce = 192;
+constexpr int kStageVjp = 128;
+
 // Bounding box of the targets an item holds (in the home-cell frame).
 struct Box {
     float lx, ly, lz, hx, hy, hz;
@@ -817,15 +823,25 @@ __device__ __forceinline__ bool may_reach(const Box &b, float x, float y, float 
 // Stream the stencil's sources through LDS.  Candidates are fetched 64 at a
 // time (the next batch is prefetched into registers), sources that cannot
 // reach the target box are dropped, and survivors are packed into stage0
-// (and stage1 for a second float4 per source) with a ballot.  compute(n)
-// consumes stage entries [0, n); entries [n, 64) are padding that the pair
-// terms mask out.  Every lane must call this (wave-uniform control flow).
-template <int kParts, class Fetch, class Compute>
+// (and stage1 for a second float4 per source) with a ballot.  The stage holds
+// kCap survivors plus 64 entries of padding; compute(n) consumes entries
+// [0, n) and may read up to 63 padding entries past n, which the pair terms
+// mask out (far away, zero mass).  A larger kCap means fewer, fuller passes
+// of the pair loop.  Every lane must call this (wave-uniform control flow).
+template <int kParts, int kCap, class Fetch, class Compute>
 __device__ __forceinline__ void stream_sources(const Stencil &st, const Box &box, float cull2,
                                                int lane, float4 *stage0, float4 *stage1,
                                                Fetch &&fetch, Compute &&compute)
 {
+    static_assert(kCap >= kWave && kCap % kWave == 0, "stage capacity in whole waves");
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    auto flush = [&](int n) {
+        stage0[n + lane] = make_float4(kFar, kFar, kFar, 0.f);
+        if (kParts == 2) stage1[n + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+        compute(n);
+        __syncthreads();
+    };
     int fill = 0;
     float4 c0, c1;
     fetch(lane, c0, c1);
@@ -833,14 +849,8 @@ __device__ __forceinline__ void stream_sources(const Stencil &st, const Box &box
         const bool keep = (base + lane < st.total) && may_reach(box, c0.x, c0.y, c0.z, cull2);
         const uint64_t m = __ballot(keep);
         const int cnt = __popcll(m);
-        if (fill + cnt > kWave) {
-            if (lane >= fill) {
-                stage0[lane] = make_float4(kFar, kFar, kFar, 0.f);
-                if (kParts == 2) stage1[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            __syncthreads();
-            compute(fill);
-            __syncthreads();
+        if (fill + cnt > kCap) {
+            flush(fill);
             fill = 0;
         }
         if (keep) {
@@ -851,15 +861,7 @@ __device__ __forceinline__ void stream_sources(const Stencil &st, const Box &box
         fill += cnt;
         if (base + kWave < st.total) fetch(base + kWave + lane, c0, c1);
     }
-    if (fill > 0) {
-        if (lane >= fill) {
-            stage0[lane] = make_float4(kFar, kFar, kFar, 0.f);
-            if (kParts == 2) stage1[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        __syncthreads();
-        compute(fill);
-        __syncthreads();
-    }
+    if (fill > 0) flush(fill);
 }
 
 // Source v of the stencil for the adjoint: position (shifted) and mass, and
@@ -939,7 +941,7 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
                 }
                 const Box box = target_box(va, pax, pay, paz, vb, pbx, pby, pbz);
                 float aax = 0.f, aay = 0.f, aaz = 0.f, abx = 0.f, aby = 0.f, abz = 0.f;
-                stream_sources<1>(st, box, cull2, lane, stage, stage, fetch_p, [&](int n) {
+                stream_sources<1, kStageForce>(st, box, cull2, lane, stage, stage, fetch_p, [&](int n) {
                     const int n4 = (n + 3) >> 2;
                     for (int u = 0; u < n4; ++u) {
 #pragma unroll
@@ -965,7 +967,7 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
             }
             const Box box = target_box(tv, px, py, pz, false, 0.f, 0.f, 0.f);
             float ax = 0.f, ay = 0.f, az = 0.f;
-            stream_sources<1>(st, box, cull2, lane, stage, stage, fetch_p, [&](int n) {
+            stream_sources<1, kStageForce>(st, box, cull2, lane, stage, stage, fetch_p, [&](int n) {
                 if (lk == 0) {
                     const int n8 = (n + 7) >> 3;
                     for (int u = 0; u < n8; ++u) {
@@ -997,7 +999,7 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
     Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
     const int *__restrict__ out_row, float *__restrict__ out, int n_out)
 {
-    __shared__ float4 stage[kWave];
+    __shared__ float4 stage[kStageForce + kWave];
     if (hdr[kHdrMassInfo] == 0)
         force_items<Acc, kSoft, true>(acc, items, hdr, start, src, out_row, out, n_out, stage);
     else
@@ -1056,7 +1058,7 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
                 }
                 const Box box = target_box(va, pax, pay, paz, vb, pbx, pby, pbz);
                 float rax = 0.f, ray = 0.f, raz = 0.f, rbx = 0.f, rby = 0.f, rbz = 0.f;
-                stream_sources<2>(st, box, cull2, lane, stage_p, stage_g, fetch_pg, [&](int n) {
+                stream_sources<2, kStageVjp>(st, box, cull2, lane, stage_p, stage_g, fetch_pg, [&](int n) {
                     const int n2 = (n + 1) >> 1;
                     for (int u = 0; u < n2; ++u) {
 #pragma unroll
@@ -1090,7 +1092,7 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
             }
             const Box box = target_box(tv, px, py, pz, false, 0.f, 0.f, 0.f);
             float rx = 0.f, ry = 0.f, rz = 0.f;
-            stream_sources<2>(st, box, cull2, lane, stage_p, stage_g, fetch_pg, [&](int n) {
+            stream_sources<2, kStageVjp>(st, box, cull2, lane, stage_p, stage_g, fetch_pg, [&](int n) {
                 if (lk == 0) {
                     const int n4 = (n + 3) >> 2;
                     for (int u = 0; u < n4; ++u) {
@@ -1124,8 +1126,8 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
     const float *__restrict__ gx, const float *__restrict__ gy, const float *__restrict__ gz,
     const int *__restrict__ perm, float *__restrict__ out, int n_out)
 {
-    __shared__ float4 stage_p[kWave];
-    __shared__ float4 stage_g[kWave];
+    __shared__ float4 stage_p[kStageVjp + kWave];
+    __shared__ float4 stage_g[kStageVjp + kWave];
     if (hdr[kHdrMassInfo] == 0)
         vjp_items<Acc, kSoft, true>(acc, items, hdr, start, src, gx, gy, gz, perm, out, n_out,
                                     stage_p, stage_g);

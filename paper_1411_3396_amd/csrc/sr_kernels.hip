@@ -330,33 +330,44 @@ __global__ __launch_bounds__(256) void k_radix_hist(const int *__restrict__ keys
     for (int d = threadIdx.x; d < R; d += 256) table[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
-// Stable scatter of one tile by one wave.  Elements are taken 64 at a time in
-// input order; lanes holding the same digit find each other with one ballot
-// per digit bit, rank by lane order and advance the digit's running offset.
-__global__ __launch_bounds__(64) void k_radix_scatter(const int *__restrict__ keys_in,
-                                                      const int *__restrict__ vals_in, int N,
-                                                      int shift, int bits,
-                                                      const int *__restrict__ table_x, int ntiles,
-                                                      int *__restrict__ keys_out,
-                                                      int *__restrict__ vals_out)
+// Stable scatter of one tile of kRadixTile elements by four waves.  Each
+// wave ranks its quarter of the tile (consecutive elements, 64 at a time)
+// with one ballot per digit bit and per-wave digit counters.  The tile is then
+// reordered by digit in LDS, keeping input order inside a digit (wave, then
+// step, then lane), and written out in that order: each digit's run of the
+// tile lands on consecutive global addresses.
+constexpr int kScatterWaves = 4;
+constexpr int kScatterSteps = kRadixTile / (kScatterWaves * kWave);
+
+__global__ __launch_bounds__(kScatterWaves * kWave) void k_radix_scatter(
+    const int *__restrict__ keys_in, const int *__restrict__ vals_in, int N, int shift, int bits,
+    const int *__restrict__ table_x, int ntiles, int *__restrict__ keys_out, int *__restrict__ vals_out)
 {
-    __shared__ int run[256];
-    const int lane = threadIdx.x;
+    constexpr int kThreads = kScatterWaves * kWave;
+    __shared__ int cnt[kScatterWaves][256];  // per-wave digit counts, then per-wave offsets
+    __shared__ int lstart[256];              // first slot of each digit in the reordered tile
+    __shared__ int gstart[256];              // first global slot of each digit of this tile
+    __shared__ int wsum[kScatterWaves];
+    __shared__ int lkey[kRadixTile];
+    __shared__ int lval[kRadixTile];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int R = 1 << bits;
     const int tile = blockIdx.x;
-    for (int d = lane; d < R; d += 64) run[d] = table_x[(int64_t)d * ntiles + tile];
+    gstart[tid] = tid < R ? table_x[(int64_t)tid * ntiles + tile] : 0;
+#pragma unroll
+    for (int w = 0; w < kScatterWaves; ++w) cnt[w][tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)tile * kRadixTile;
+    const int64_t tile0 = (int64_t)tile * kRadixTile;
+    const int64_t base = tile0 + (int64_t)wv * (kScatterSteps * kWave);
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int r = 0; r < kRadixTile / 64; ++r) {
-        const int64_t e = base + r * 64 + lane;
+    int key[kScatterSteps], val[kScatterSteps], rk[kScatterSteps];
+#pragma unroll
+    for (int r = 0; r < kScatterSteps; ++r) {
+        const int64_t e = base + r * kWave + lane;
         const bool valid = e < N;
-        int key = 0, val = 0;
-        if (valid) {
-            key = keys_in[e];
-            val = vals_in ? vals_in[e] : (int)e;
-        }
-        const int d = (key >> shift) & (R - 1);
+        key[r] = valid ? keys_in[e] : 0;
+        val[r] = valid ? (vals_in ? vals_in[e] : (int)e) : 0;
+        const int d = (key[r] >> shift) & (R - 1);
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
             const bool bit = (d >> b) & 1;
@@ -364,16 +375,51 @@ __global__ __launch_bounds__(64) void k_radix_scatter(const int *__restrict__ ke
             peers &= bit ? m : ~m;
         }
         const int rank = __popcll(peers & below);
-        const int cnt = __popcll(peers);
-        const int start = run[d];
+        const int before = cnt[wv][d];
+        rk[r] = valid ? before + rank : -1;
         __syncthreads();
-        if (valid) {
-            const int dest = start + rank;
-            if (keys_out) keys_out[dest] = key;
-            vals_out[dest] = val;
-            if (rank == 0) run[d] = start + cnt;
+        if (valid && rank == 0) cnt[wv][d] = before + __popcll(peers);
+        __syncthreads();
+    }
+    // per-wave offsets inside each digit, and the digit totals
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScatterWaves; ++w) {
+        const int c = cnt[w][tid];
+        cnt[w][tid] = tot;
+        tot += c;
+    }
+    // exclusive scan of the totals over the 256 digits (one per thread)
+    int incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    int prior = 0;
+#pragma unroll
+    for (int w = 0; w < kScatterWaves; ++w) prior += w < wv ? wsum[w] : 0;
+    lstart[tid] = prior + incl - tot;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kScatterSteps; ++r) {
+        if (rk[r] >= 0) {
+            const int d = (key[r] >> shift) & (R - 1);
+            const int at = lstart[d] + cnt[wv][d] + rk[r];
+            lkey[at] = key[r];
+            lval[at] = val[r];
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    const int n_tile = (int)min((int64_t)kRadixTile, (int64_t)N - tile0);
+    for (int i = tid; i < n_tile; i += kThreads) {
+        const int k = lkey[i];
+        const int d = (k >> shift) & (R - 1);
+        const int dest = gstart[d] + (i - lstart[d]);
+        if (keys_out) keys_out[dest] = k;
+        vals_out[dest] = lval[i];
     }
 }
 
@@ -1346,6 +1392,7 @@ hipError_t radix_sort_pairs(const int *keys_in, const int *vals_in, int64_t n, i
                             int digit_bits, int64_t ntiles, const RadixBufs &b, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
+    if (digit_bits < 1 || digit_bits > 8 || passes < 1) return hipErrorInvalidValue;
     const int *kin = keys_in;
     const int *vin = vals_in;
     const int R = 1 << digit_bits;
@@ -1358,7 +1405,8 @@ hipError_t radix_sort_pairs(const int *keys_in, const int *vals_in, int64_t n, i
                                                      (int)ntiles);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = scan_i32(b.tab, b.tabx, (int64_t)R * ntiles, b.scan_tmp, st)) != hipSuccess) return e;
-        k_radix_scatter<<<(unsigned)ntiles, 64, 0, st>>>(kin, vin, (int)n, shift, digit_bits, b.tabx,
+        k_radix_scatter<<<(unsigned)ntiles, kScatterWaves * kWave, 0, st>>>(kin, vin, (int)n, shift,
+                                                                           digit_bits, b.tabx,
                                                         (int)ntiles, kout, vout);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         kin = kout;

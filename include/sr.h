@@ -329,7 +329,8 @@ sr_status sr_centres(sr_centres_plan *plan, const float *pos, const float *mass,
  * u = x / h, wrapped into [0, ng), gives m (1 - f) to grid point floor(u) and
  * m f to floor(u) + 1 per axis (f = u - floor(u)), the product over axes to
  * each of 8 points; grid points sit at multiples of h.  The particles are
- * sorted by cell and every grid point sums its contributions in float64 in a
+ * sorted by cell, each cell's contributions are summed in float64 per
+ * 64-particle run, and every grid point adds its 8 cells' partials in a
  * fixed order (the grid is reproducible bit for bit).  The FFT is rocFFT's
  * single-precision real-to-complex transform, in place in the workspace;
  * mode sums are float64.  Non-finite positions make the spectrum

@@ -5,8 +5,9 @@
 // Device passes: the deposit into the FFT's padded in-place layout, a
 // float64 mass sum in a fixed order, the FFT (rocFFT, in place), and the
 // binning.  The deposit is atomic-free: particles are sorted by the cell of
-// their lower corner point (the binning's radix sort) and every grid point
-// gathers its 8 cells in float64, in a fixed order.  Binning: every mode of
+// their lower corner point (the binning's radix sort), a segmented scan sums
+// each cell's corner contributions per wave, and every grid point adds the
+// partials of its 8 cells in float64, in a fixed order.  Binning: every mode of
 // the half spectrum adds w |rho_k|^2 / W(k)^2 (w = 2 for modes whose mirror
 // is not stored) into per-workgroup float64 bins in LDS; a last pass adds
 // the workgroups' bins in workgroup order.
@@ -65,11 +66,57 @@ __global__ __launch_bounds__(256) void k_cic_pack(const int *__restrict__ perm, 
     if (i < n) spf[i] = pf[perm[i]];
 }
 
-// Sorted deposit, step 2: every grid point sums, in float64 and a fixed
-// order, the particles of the 8 cells whose lower corner is the point or its
-// lower neighbours (cells (p - c) for c in {0,1}^3, periodic).
-__global__ __launch_bounds__(256) void k_cic_gather(const int *__restrict__ cstart,
-                                                    const float4 *__restrict__ spf, int ng, int pad,
+// Sorted deposit, step 2: each particle's 8 corner contributions
+// m w_x w_y w_z (float products, widened to float64), summed over the runs of
+// equal cells inside each 64-slot wave of the sorted order by a segmented
+// scan.  The last slot of each run stores the run's 8 sums at seg[8 slot + k],
+// k = 4 c_x + 2 c_y + c_z for the corner point (lower corner + (c_x, c_y, c_z)).
+// A cell's particles thus end up as one partial per wave they touch, stored
+// at the wave's last slot inside the cell and at the cell's last slot.
+__global__ __launch_bounds__(256) void k_cic_runs(const int *__restrict__ skey,
+                                                  const float4 *__restrict__ spf, int n,
+                                                  double *__restrict__ seg)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool valid = i < n;
+    const int key = valid ? skey[i] : -1;
+    const float4 v = valid ? spf[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    double c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float wx = (k & 4) ? v.x : 1.f - v.x;
+        const float wy = (k & 2) ? v.y : 1.f - v.y;
+        const float wz = (k & 1) ? v.z : 1.f - v.z;
+        c[k] = (double)(v.w * wx * wy * wz);
+    }
+    const int prev = __shfl_up(key, 1);
+    const uint64_t heads = __ballot(lane == 0 || prev != key);
+    const uint64_t upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1));
+    const int first = 63 - __clzll(upto);  // first lane of this run
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double y = __shfl_up(c[k], o);
+            if (lane - o >= first) c[k] += y;
+        }
+    }
+    const int next = __shfl_down(key, 1);
+    if (valid && (lane == 63 || next != key)) {
+        double *out = seg + 8 * (int64_t)i;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) out[k] = c[k];
+    }
+}
+
+// Sorted deposit, step 3: every grid point adds, in float64 and a fixed order,
+// the partials of the 8 cells whose lower corner is the point or its lower
+// neighbours (cells (p - c) for c in {0,1}^3, periodic): for a cell of slots
+// [a, b), the partials at the last slot of each 64-slot wave below b - 1, then
+// at b - 1.
+__global__ __launch_bounds__(256) void k_cic_points(const int *__restrict__ cstart,
+                                                    const double *__restrict__ seg, int ng, int pad,
                                                     float *__restrict__ grid)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -89,14 +136,11 @@ __global__ __launch_bounds__(256) void k_cic_gather(const int *__restrict__ csta
             for (int cz = 0; cz < 2; ++cz) {
                 const int z = cz ? (iz == 0 ? ng - 1 : iz - 1) : iz;
                 const int c = (x * ng + y) * ng + z;
-                const int e = cstart[c + 1];
-                for (int p = cstart[c]; p < e; ++p) {
-                    const float4 v = spf[p];
-                    // this point is the particle's corner point + (cx, cy, cz)
-                    const float wx = cx ? v.x : 1.f - v.x;
-                    const float wy = cy ? v.y : 1.f - v.y;
-                    const float wz = cz ? v.z : 1.f - v.z;
-                    sum += (double)(v.w * wx * wy * wz);
+                const int a = cstart[c], b = cstart[c + 1];
+                if (a < b) {
+                    const int k = 4 * cx + 2 * cy + cz;
+                    for (int p = a | 63; p < b - 1; p += 64) sum += seg[8 * (int64_t)p + k];
+                    sum += seg[8 * (int64_t)(b - 1) + k];
                 }
             }
         }
@@ -219,7 +263,7 @@ struct sr_pk_plan {
     int passes = 1, digit_bits = 1;
     int64_t tiles = 1;
     size_t grid_off = 0, grid_bytes = 0, sinc_off = 0, mass_off = 0, part_off = 0, work_off = 0,
-           key_off[2] = {0, 0}, val_off[2] = {0, 0}, pf_off = 0, spf_off = 0, cstart_off = 0,
+           key_off[2] = {0, 0}, val_off[2] = {0, 0}, pf_off = 0, spf_off = 0, seg_off = 0, cstart_off = 0,
            tab_off = 0, tabx_off = 0, scan_off = 0, ws_bytes = 0;
     rocfft_plan fft = nullptr;
     size_t work_bytes = 0;
@@ -270,6 +314,7 @@ sr_status deposit(sr_pk_plan *P, const float *pos, const float *mass, int64_t n,
         const int64_t cells = (int64_t)P->ng * P->ng * P->ng;
         float4 *pf = reinterpret_cast<float4 *>(w + P->pf_off);
         float4 *spf = reinterpret_cast<float4 *>(w + P->spf_off);
+        double *seg = reinterpret_cast<double *>(w + P->seg_off);
         if (n > 0) {
             k_cic_key<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pos, mass, (int)n, P->ng, inv_h,
                                                                  I(P->key_off[1]), pf);
@@ -286,10 +331,12 @@ sr_status deposit(sr_pk_plan *P, const float *pos, const float *mass, int64_t n,
             if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
             if (dev_bounds(I(P->key_off[out]), n, cells, 0, I(P->cstart_off), s) != hipSuccess)
                 return SR_E_DEVICE;
+            k_cic_runs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(I(P->key_off[out]), spf, (int)n, seg);
+            if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         } else if (dev_zero(I(P->cstart_off), cells + 1, s) != hipSuccess) {
             return SR_E_DEVICE;
         }
-        k_cic_gather<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(I(P->cstart_off), spf, P->ng, pad, grid);
+        k_cic_points<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(I(P->cstart_off), seg, P->ng, pad, grid);
         if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
     }
     double *part = reinterpret_cast<double *>(w + P->mass_off);
@@ -352,6 +399,8 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
         o = align256(o + sizeof(float4) * m);
         P->spf_off = o;
         o = align256(o + sizeof(float4) * m);
+        P->seg_off = o;
+        o = align256(o + sizeof(double) * 8 * m);
         P->cstart_off = o;
         o = align256(o + sizeof(int) * (cells + 1));
         P->tab_off = o;

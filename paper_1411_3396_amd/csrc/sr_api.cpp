@@ -137,6 +137,7 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.seg = take((size_t)B * sizeof(SegParams));
     L.cell_of = take(n4);
     L.skey = take(n4);
+    L.packed = take((size_t)N * 16);  // offsets from the cell centre + mass, input order
     L.keys[0] = take(n4);
     L.keys[1] = take(n4);
     L.vals[0] = take(n4);

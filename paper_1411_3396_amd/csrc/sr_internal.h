@@ -80,7 +80,7 @@ struct Layout {
     int64_t table = 0;      // radix table entries (R * ntiles)
     int64_t item_cap = 0;   // upper bound on work items
     int64_t mom_tiles = 0;  // momentum partials
-    size_t hdr = 0, seg = 0, cell_of = 0, skey = 0, keys[2] = {0, 0}, vals[2] = {0, 0};
+    size_t hdr = 0, seg = 0, cell_of = 0, skey = 0, packed = 0, keys[2] = {0, 0}, vals[2] = {0, 0};
     size_t tab = 0, tabx = 0, nact = 0, start = 0, scan_tmp = 0;
     size_t bx = 0, by = 0, bz = 0, bm = 0, out_row = 0, gx = 0, gy = 0, gz = 0;
     size_t items = 0, info = 0, mom = 0;

@@ -274,10 +274,14 @@ __device__ __forceinline__ int leaf_code(float ox, float oy, float oz, const Seg
 
 // Cell of each particle and its sort key: (cell, passive, leaf code).  With
 // key_bits == code_bits there is no passive bit (every particle is active).
+// The offsets from the cell centre and the mass are kept in input order, one
+// float4 per particle, for the gather into binned order.
 template <class Acc>
-__global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restrict__ pos, int N,
+__global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restrict__ pos,
+                                                   const float *__restrict__ mass, int N,
                                                    int key_bits, int code_bits, int *__restrict__ cell_of,
-                                                   int *__restrict__ skey, uint32_t *hdr)
+                                                   int *__restrict__ skey, float4 *__restrict__ packed,
+                                                   uint32_t *hdr)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
@@ -296,6 +300,7 @@ __global__ __launch_bounds__(256) void k_bin_cells(Acc acc, const float *__restr
     const int passive = (i - S.part_off < S.n_active) ? 0 : 1;
     cell_of[i] = cell;
     skey[i] = (cell << key_bits) | (key_bits > code_bits ? passive << code_bits : 0) | code;
+    packed[i] = make_float4(ox, oy, oz, mass[i]);
     if (fl) atomicOr(&hdr[kHdrFlags], fl);
 }
 
@@ -429,8 +434,7 @@ template <class Acc>
 __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__restrict__ perm,
                                                 const int *__restrict__ key,
                                                 const int *__restrict__ start,
-                                                const float *__restrict__ pos,
-                                                const float *__restrict__ mass,
+                                                const float4 *__restrict__ packed,
                                                 float *__restrict__ bx, float *__restrict__ by,
                                                 float *__restrict__ bz, float *__restrict__ bm,
                                                 int *__restrict__ out_row, int *__restrict__ nact,
@@ -441,21 +445,13 @@ __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__res
     if (b >= N) return;
     const int i = perm[b];
     const SegParams &S = acc.get(acc.seg_of_particle(i));
-    uint32_t fl = 0;
-    float ox, oy, oz;
-    const int64_t p = 3 * (int64_t)i;
-    bin_coord(pos[p], S.lo[0], S.len[0], S.inv_len[0], S.h[0], S.inv_h[0], S.nc[0], S.periodic, ox,
-              fl);
-    bin_coord(pos[p + 1], S.lo[1], S.len[1], S.inv_len[1], S.h[1], S.inv_h[1], S.nc[1], S.periodic,
-              oy, fl);
-    bin_coord(pos[p + 2], S.lo[2], S.len[2], S.inv_len[2], S.h[2], S.inv_h[2], S.nc[2], S.periodic,
-              oz, fl);
-    bx[b] = ox;
-    by[b] = oy;
-    bz[b] = oz;
-    const float mi = mass[i];
+    const float4 v = packed[i];  // offsets from the cell centre and mass, from k_bin_cells
+    bx[b] = v.x;
+    by[b] = v.y;
+    bz[b] = v.z;
+    const float mi = v.w;
     bm[b] = mi;
-    if (!(mi == mass[0])) atomicOr(&hdr[kHdrMassInfo], 1u);  // not every mass equal
+    if (!(mi == packed[0].w)) atomicOr(&hdr[kHdrMassInfo], 1u);  // not every mass equal
     const int li = i - S.part_off;
     const bool act = li < S.n_active;
     out_row[b] = act ? S.out_off + li : -1;
@@ -1423,8 +1419,9 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
     if ((e = fill_u32(at<uint32_t>(a, L.nact), L.NC, 0, a.st)) != hipSuccess) return e;
     if (L.N == 0) return hipSuccess;
     e = with_acc(a, [&](auto acc) -> hipError_t {
-        k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, (int)L.N, L.key_bits, L.code_bits,
+        k_bin_cells<<<blocks_for(L.N, 256), 256, 0, a.st>>>(acc, pos, mass, (int)L.N, L.key_bits, L.code_bits,
                                                              at<int>(a, L.cell_of), at<int>(a, L.skey),
+                                                             at<float4>(a, L.packed),
                                                              at<uint32_t>(a, L.hdr));
         return hipGetLastError();
     });
@@ -1440,8 +1437,8 @@ hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass)
         return e;
     return with_acc(a, [&](auto acc) -> hipError_t {
         k_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
-            acc, (int)L.N, at<int>(a, L.perm()), at<int>(a, L.sorted_keys()), at<int>(a, L.start), pos,
-            mass, at<float>(a, L.bx), at<float>(a, L.by), at<float>(a, L.bz), at<float>(a, L.bm),
+            acc, (int)L.N, at<int>(a, L.perm()), at<int>(a, L.sorted_keys()), at<int>(a, L.start),
+            at<float4>(a, L.packed), at<float>(a, L.bx), at<float>(a, L.by), at<float>(a, L.bz), at<float>(a, L.bm),
             at<int>(a, L.out_row), at<int>(a, L.nact), L.key_bits, at<uint32_t>(a, L.hdr), L.magic());
         return hipGetLastError();
     });

@@ -327,8 +327,9 @@ def main() -> int:
     ap.add_argument("--no-centres", action="store_true")
     ap.add_argument("--no-pk", action="store_true")
     ap.add_argument("--no-leaves", action="store_true")
-    ap.add_argument("--leaf-depth", type=int, default=1,
-                    help="octree depth of the in-cell order of the main workload (1: octants)")
+    ap.add_argument("--leaf-depth", type=int, default=2,
+                    help="octree depth of the in-cell order of the main workload (1: octants; 2, "
+                         "4^3 leaves per cell, measured fastest on the node share)")
     ap.add_argument("--sweep", action="store_true",
                     help="time the pair kernels under every launch configuration "
                          "(waves per CU, targets per lane, occupancy variant); one JSON line each")
@@ -369,8 +370,7 @@ def main() -> int:
         return 0
     t0 = time.perf_counter()
     w = synth.get(args.workload)
-    if args.leaf_depth != 1:
-        w.problem = w.problem.with_leaf_depth(args.leaf_depth)
+    w.problem = w.problem.with_leaf_depth(args.leaf_depth)
     g_np = synth.cotangent(w.n_active, 1)
     log(f"workload {w.name}: n={w.n} n_active={w.n_active} ({time.perf_counter() - t0:.1f} s to generate)")
     pos = torch.from_numpy(w.pos).to(dev)

@@ -69,3 +69,29 @@ def test_power_spectrum_matches_oracle(name, ng, dn):
     p2 = plan.run(to_dev(pos), to_dev(mass), ws)[0].cpu().numpy()
     np.testing.assert_allclose(p2, p, rtol=1e-12)
     plan.close()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 128, 129, 5000])
+def test_deposit_crowded_cells_and_wrap(n):
+    # n particles in one cell and n // 2 in its neighbour: the sorted slots of a
+    # crowded cell are cut into 64-slot runs whose partials the grid points add
+    # back; plus particles on grid points and across the periodic faces
+    ng, box = 16, 16.0
+    rng = np.random.default_rng(n)
+    crowd = np.array([5.0, 7.0, 9.0]) + rng.random((n, 3)) * 0.999
+    nbr = np.array([6.0, 7.0, 9.0]) + rng.random((n // 2, 3)) * 0.999
+    faces = np.array([[0, 0, 0], [16, 16, 16], [15.5, 0, 8], [8, 8, 8], [31.5, 0.5, 0.5],
+                      [-0.5, 3.25, 15.75], [4, 4, 4]])
+    pos = np.concatenate([crowd, nbr, faces, rng.random((300, 3)) * 16]).astype(np.float32)
+    pos = pos[rng.permutation(len(pos))]
+    mass = rng.uniform(0.5, 2.0, len(pos)).astype(np.float32)
+    announce(f"cic deposit crowded cell n={n}")
+    plan = sr.PkPlan(ng, box, 8, n_max=len(pos))
+    ws = sr.new_workspace(plan.ws_bytes, DEV)
+    grid, _ = plan.deposit(to_dev(pos), to_dev(mass), ws)
+    got = grid.cpu().numpy()
+    ref = opk.cic_deposit(pos, mass, ng, box)
+    np.testing.assert_allclose(got.astype(np.float64), ref, rtol=GRID_RTOL, atol=1e-30)
+    again, _ = plan.deposit(to_dev(pos), to_dev(mass), ws)
+    assert np.array_equal(again.cpu().numpy().view(np.uint32), got.view(np.uint32))
+    plan.close()

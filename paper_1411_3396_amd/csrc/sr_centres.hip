@@ -101,13 +101,17 @@ __device__ __forceinline__ void sum_dense(const float4 *stage, float px, float p
                                           float eps2, int self, double &acc)
 {
     for (int k = 0; k < kTargetsPerWave; k += 8) {
-        float g = 0.f;
+        // even and odd sources in two float32 partial sums: two independent
+        // FMA chains instead of one
+        float g0 = 0.f, g1 = 0.f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float t = pot_term<kSoft>(stage[k + u], px, py, pz, eps2, g);
-            g = (kSelf && k + u == self) ? g : t;
+        for (int u = 0; u < 8; u += 2) {
+            const float t0 = pot_term<kSoft>(stage[k + u], px, py, pz, eps2, g0);
+            const float t1 = pot_term<kSoft>(stage[k + u + 1], px, py, pz, eps2, g1);
+            g0 = (kSelf && k + u == self) ? g0 : t0;
+            g1 = (kSelf && k + u + 1 == self) ? g1 : t1;
         }
-        acc += (double)g;
+        acc += (double)(g0 + g1);
     }
 }
 
@@ -118,17 +122,22 @@ __device__ __forceinline__ void sum_two(const float4 *stage, float ax, float ay,
                                         double &acc_a, double &acc_b)
 {
     for (int k = 0; k < kTargetsPerWave; k += 8) {
-        float ga = 0.f, gb = 0.f;
+        // per target, even and odd sources in two float32 partial sums
+        float ga0 = 0.f, ga1 = 0.f, gb0 = 0.f, gb1 = 0.f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float4 s = stage[k + u];
-            const float ta = pot_term<kSoft>(s, ax, ay, az, eps2, ga);
-            const float tb = pot_term<kSoft>(s, bx, by, bz, eps2, gb);
-            ga = (kSelf && k + u == self_a) ? ga : ta;
-            gb = (kSelf && k + u == self_b) ? gb : tb;
+        for (int u = 0; u < 8; u += 2) {
+            const float4 s0 = stage[k + u], s1 = stage[k + u + 1];
+            const float ta0 = pot_term<kSoft>(s0, ax, ay, az, eps2, ga0);
+            const float tb0 = pot_term<kSoft>(s0, bx, by, bz, eps2, gb0);
+            const float ta1 = pot_term<kSoft>(s1, ax, ay, az, eps2, ga1);
+            const float tb1 = pot_term<kSoft>(s1, bx, by, bz, eps2, gb1);
+            ga0 = (kSelf && k + u == self_a) ? ga0 : ta0;
+            gb0 = (kSelf && k + u == self_b) ? gb0 : tb0;
+            ga1 = (kSelf && k + u + 1 == self_a) ? ga1 : ta1;
+            gb1 = (kSelf && k + u + 1 == self_b) ? gb1 : tb1;
         }
-        acc_a += (double)ga;
-        acc_b += (double)gb;
+        acc_a += (double)(ga0 + ga1);
+        acc_b += (double)(gb0 + gb1);
     }
 }
 

@@ -124,7 +124,8 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.digit_bits = (bits + L.passes - 1) / L.passes;
     L.ntiles = std::max<int64_t>(1, (N + kRadixTile - 1) / kRadixTile);
     L.table = (int64_t(1) << L.digit_bits) * L.ntiles;
-    L.item_cap = NC + (N + kTargetsPerItem - 1) / kTargetsPerItem + 1;
+    // a cell of nt targets makes at most nt / kSparseGroup + 1 items
+    L.item_cap = NC + (N + kSparseGroup - 1) / kSparseGroup + 1;
     L.mom_tiles = mom_tiles;
     size_t o = 0;
     auto take = [&](size_t bytes) {

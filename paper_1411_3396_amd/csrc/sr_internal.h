@@ -13,6 +13,7 @@ namespace sr {
 
 constexpr int kWave = 64;
 constexpr int kTargetsPerItem = 64;  // one target per lane in a dense cell
+constexpr int kSparseGroup = 16;     // most targets per item of a cell with fewer than 64
 constexpr int kQueues = 8;           // one work queue per XCD
 constexpr int kQueueBlock = 32;      // consecutive items a queue takes from the list
 constexpr int kClasses = 32;         // cost classes (floor log2 of the per-lane pair count)

@@ -488,12 +488,15 @@ __global__ __launch_bounds__(256) void k_gather_g(int N, int n_rows,
 
 // --------------------------------------------------------------- work items
 
-// Items of a home cell with nt targets.  A cell of fewer than 64 targets is one
-// item with 2^lk lanes per target.  A larger cell is cut into items of 64
-// targets (128, two per lane, with `two`; then a last 64 when an odd number
-// of 64s remain), and its last nt mod 64 targets form one item of their own
-// with 2^lk lanes per target, so no item runs with mostly idle lanes.  Every
-// target is summed in the same order whether or not `two` is set.
+// Items of a home cell with nt targets.  A cell of fewer than 64 targets is cut
+// into items of at most kSparseGroup consecutive targets (leaf order), each with
+// 2^lk lanes per target: a smaller group has a tighter box, so fewer of the
+// sources it stages lie out of reach of its targets.  A larger cell is cut into
+// items of 64 targets (128, two per lane, with `two`; then a last 64 when an
+// odd number of 64s remain), and its last nt mod 64 targets form one item of
+// their own with 2^lk lanes per target, so no item runs with mostly idle lanes.
+// Every target is summed in the same order whether or not `two` is set.
+
 __device__ __forceinline__ int lanes_log2(int n)
 {
     return n >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / n));
@@ -501,7 +504,7 @@ __device__ __forceinline__ int lanes_log2(int n)
 
 __device__ __forceinline__ int cell_items(int nt, bool two)
 {
-    if (nt < kTargetsPerItem) return 1;
+    if (nt < kTargetsPerItem) return (nt + kSparseGroup - 1) / kSparseGroup;
     const int r = nt % kTargetsPerItem, groups = nt / kTargetsPerItem;
     const int dense = two ? (groups + 1) / 2 : groups;
     return dense + (r > 0 ? 1 : 0);
@@ -553,7 +556,8 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
             }
         }
     }
-    const int lk = nt >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / nt));
+    // cost class from the cell's widest item: a group of min(nt, kSparseGroup) targets when sparse
+    const int lk = nt >= kTargetsPerItem ? 0 : lanes_log2(min(nt, kSparseGroup));
     const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
     const int n_items = cell_items(nt, two);
     int64_t cost = ((src + (1 << lk) - 1) >> lk) * (chunk / kTargetsPerItem);
@@ -626,7 +630,10 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
     const uint32_t at = base[cls] + local;
     const int s0 = start[c];
     if (nt < kTargetsPerItem) {
-        items[at] = make_int4(c, s0, nt, lanes_log2(nt) | (seg << 5));
+        for (int t = 0, k = 0; t < nt; t += kSparseGroup, ++k) {
+            const int cn = min(kSparseGroup, nt - t);
+            items[at + k] = make_int4(c, s0 + t, cn, lanes_log2(cn) | (seg << 5));
+        }
         return;
     }
     const int r = nt % kTargetsPerItem, dense_end = nt - r;

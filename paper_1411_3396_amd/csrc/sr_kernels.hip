@@ -493,9 +493,9 @@ __global__ __launch_bounds__(256) void k_gather_g(int N, int n_rows,
 // 2^lk lanes per target: a smaller group has a tighter box, so fewer of the
 // sources it stages lie out of reach of its targets.  A larger cell is cut into
 // items of 64 targets (128, two per lane, with `two`; then a last 64 when an
-// odd number of 64s remain), and its last nt mod 64 targets form one item of
-// their own with 2^lk lanes per target, so no item runs with mostly idle lanes.
-// Every target is summed in the same order whether or not `two` is set.
+// odd number of 64s remain), and its last nt mod 64 targets are cut the same
+// way as a small cell, so no item runs with mostly idle lanes.  Every target
+// is summed in the same order whether or not `two` is set.
 
 __device__ __forceinline__ int lanes_log2(int n)
 {
@@ -507,7 +507,7 @@ __device__ __forceinline__ int cell_items(int nt, bool two)
     if (nt < kTargetsPerItem) return (nt + kSparseGroup - 1) / kSparseGroup;
     const int r = nt % kTargetsPerItem, groups = nt / kTargetsPerItem;
     const int dense = two ? (groups + 1) / 2 : groups;
-    return dense + (r > 0 ? 1 : 0);
+    return dense + (r + kSparseGroup - 1) / kSparseGroup;
 }
 
 // Per home cell: number of items and cost class (floor log2 of the pairs one
@@ -643,7 +643,10 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
         items[at + k] = make_int4(c, s0 + t0, cn, ((cn > kTargetsPerItem ? 1 : 0) << 4) | (seg << 5));
         t0 += cn;
     }
-    if (r > 0) items[at + k] = make_int4(c, s0 + dense_end, r, lanes_log2(r) | (seg << 5));
+    for (int t = dense_end; t < nt; t += kSparseGroup, ++k) {
+        const int cn = min(kSparseGroup, nt - t);
+        items[at + k] = make_int4(c, s0 + t, cn, lanes_log2(cn) | (seg << 5));
+    }
 }
 
 // --------------------------------------------------------------- pair kernels

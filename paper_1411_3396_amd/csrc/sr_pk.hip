@@ -125,6 +125,7 @@ __global__ __launch_bounds__(256) void k_cic_points(const int *__restrict__ csta
     const int iz = (int)(g % ng);
     const int64_t r = g / ng;
     const int iy = (int)(r % ng), ix = (int)(r / ng);
+    const int zm = iz == 0 ? ng - 1 : iz - 1;
     double sum = 0.0;
 #pragma unroll
     for (int cx = 0; cx < 2; ++cx) {
@@ -132,11 +133,14 @@ __global__ __launch_bounds__(256) void k_cic_points(const int *__restrict__ csta
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
             const int y = cy ? (iy == 0 ? ng - 1 : iy - 1) : iy;
+            // cells (x, y, iz) and (x, y, zm): their slot ranges share the bound at
+            // (x, y, iz) unless zm wrapped to the end of the row
+            const int row = (x * ng + y) * ng;
+            const int s0 = cstart[row + iz], e0 = cstart[row + iz + 1];
+            const int sm = cstart[row + zm], em = iz == 0 ? cstart[row + ng] : s0;
 #pragma unroll
             for (int cz = 0; cz < 2; ++cz) {
-                const int z = cz ? (iz == 0 ? ng - 1 : iz - 1) : iz;
-                const int c = (x * ng + y) * ng + z;
-                const int a = cstart[c], b = cstart[c + 1];
+                const int a = cz ? sm : s0, b = cz ? em : e0;
                 if (a < b) {
                     const int k = 4 * cx + 2 * cy + cz;
                     for (int p = a | 63; p < b - 1; p += 64) sum += seg[8 * (int64_t)p + k];

@@ -30,6 +30,10 @@ FLOP_PER_PAIR = {"force": 30, "vjp": 61}
 KERNEL_SYMBOL = {"force": "k_force", "vjp": "k_vjp"}
 
 
+# In-cell leaf order the workloads are timed at (octree depth; 1 = octants).
+LEAF_DEPTH = 2
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -327,7 +331,7 @@ def main() -> int:
     ap.add_argument("--no-centres", action="store_true")
     ap.add_argument("--no-pk", action="store_true")
     ap.add_argument("--no-leaves", action="store_true")
-    ap.add_argument("--leaf-depth", type=int, default=2,
+    ap.add_argument("--leaf-depth", type=int, default=LEAF_DEPTH,
                     help="octree depth of the in-cell order of the main workload (1: octants; 2, "
                          "4^3 leaves per cell, measured fastest on the node share)")
     ap.add_argument("--sweep", action="store_true",

@@ -1,5 +1,5 @@
-"""Parity at the full workload sizes, in the launch configuration the benchmark
-times, on sampled outputs the oracle computes one by one (its target-subset
+"""Parity at the full workload sizes, in the launch configuration and in-cell leaf
+order the benchmark times, on sampled outputs the oracle computes one by one (its target-subset
 mode): the 2M and 16M clustered boxes, the 96-subvolume batch and the
 34.6M-particle node share with its ghost shell."""
 import numpy as np
@@ -11,12 +11,19 @@ import oracle
 import paper_1411_3396_amd as sr
 from paper_1411_3396_amd import synth
 from gpu_helpers import DEV, FWD_TOL, VJP_TOL, announce, assert_force_close, to_dev
+from bench import LEAF_DEPTH
 
 pytestmark = pytest.mark.gpu
 
 
+def timed(w):
+    """The workload with the in-cell leaf order the benchmark times it at."""
+    w.problem = w.problem.with_leaf_depth(LEAF_DEPTH)
+    return w
+
+
 def test_clustered_2m_forward_sampled():
-    w = synth.clustered_2m()
+    w = timed(synth.clustered_2m())
     announce(f"clustered_2m n={w.n}")
     acc = sr.force(to_dev(w.pos), to_dev(w.mass), w.problem).cpu().numpy()
     idx = synth.sample_indices(w.n_active, 20000, 2)
@@ -25,7 +32,7 @@ def test_clustered_2m_forward_sampled():
 
 
 def test_clustered_16m_forward_and_adjoint():
-    w = synth.clustered_16m()
+    w = timed(synth.clustered_16m())
     g = synth.cotangent(w.n_active, 1)
     idx = synth.sample_indices(w.n, 4096, 2)
     announce(f"clustered_16m n={w.n}")
@@ -97,7 +104,7 @@ def test_clustered_16m_adjoint_finite_differences():
 
 
 def test_node_share_forward_and_adjoint_sampled():
-    w = synth.node_share()
+    w = timed(synth.node_share())
     announce(f"node_share n={w.n} n_active={w.n_active}")
     g = synth.cotangent(w.n_active, 1)
     pos, mass = to_dev(w.pos), to_dev(w.mass)

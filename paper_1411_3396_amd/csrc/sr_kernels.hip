@@ -430,6 +430,10 @@ __global__ __launch_bounds__(kScatterWaves * kWave) void k_radix_scatter(
 
 // --------------------------------------------------------------- A3: gather
 
+// Binned order: slot b takes particle perm[b]'s offsets and mass (the float4
+// the cell pass kept, one cache line per particle), its output row (-1 for a
+// passive particle), and the last active slot of each cell records the cell's
+// active count.  Slot 0 tags the workspace as binned for these sizes.
 template <class Acc>
 __global__ __launch_bounds__(256) void k_gather(Acc acc, int N, const int *__restrict__ perm,
                                                 const int *__restrict__ key,

@@ -462,12 +462,24 @@ int oracle_force_brute(const double *pos, const double *mass, int64_t n, int64_t
 
 /* Adjoint.  For L = sum_{i active} g_i . a_i (g_j = 0 for passive j), the
  * gradient with respect to x_k, any k, is
- *   sum_{j != k, 0 < s < r_s^2} [ f u + 2 f' (u . d) d ],
+ *   sum_{j != k, s < r_s^2} [ f u + 2 f' (u . d) d ],
  *   d = x_j - x_k,  u = m_k g_j - m_j g_k,  f = f_SR(s), f' = df_SR/ds.
  * (Differentiating a_k gives -m_j [f g_k + 2 f' (g_k.d) d]; differentiating
  * each a_j in which x_k is a source gives m_k [f g_j + 2 f' (g_j.d) d].)
- * The jump of the cutoff is not differentiated.  grad[3*q] for target q
- * (targets NULL: all n particles). */
+ * The jump of the cutoff is not differentiated.  A pair at s = 0 (a distinct
+ * particle at the same position) contributes nothing to the forces, but with
+ * softening its force term m d f(|d|^2) is smooth through d = 0 with
+ * Jacobian m f(0) I, so it adds f(0) u here; without softening f is
+ * singular there and the pair is left out, as in the forward sum.
+ * grad[3*q] for target q (targets NULL: all n particles). */
+
+/* Does the adjoint take a pair at squared distance s?  (j != k is checked
+ * by the caller.) */
+static int vjp_takes(const prob_t *P, double s)
+{
+    if (!(s < P->rs2)) return 0;
+    return s > 0.0 || P->eps2 > 0.0;
+}
 int oracle_vjp(const double *pos, const double *mass, int64_t n, int64_t n_active,
                const double lo[3], const double len[3], int periodic, double r_s, double eps,
                const double poly[6], const double *g, const int64_t *targets, int64_t n_targets,
@@ -506,7 +518,7 @@ int oracle_vjp(const double *pos, const double *mass, int64_t n, int64_t n_activ
                                pos[3 * j + 2] - pos[3 * k + 2]};
                 min_image(&P, d);
                 double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                if (!(s > 0.0 && s < P.rs2)) continue;
+                if (!vjp_takes(&P, s)) continue;
                 double gj[3] = {0, 0, 0};
                 if (j < n_active) {
                     gj[0] = g[3 * j];
@@ -563,7 +575,7 @@ int oracle_vjp_brute(const double *pos, const double *mass, int64_t n, int64_t n
                                        x[3 * j + 1] + sy * len[1] - x[3 * k + 1],
                                        x[3 * j + 2] + sz * len[2] - x[3 * k + 2]};
                         double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                        if (!(s > 0.0 && s < P.rs2)) continue;
+                        if (!vjp_takes(&P, s)) continue;
                         double f = f_sr(&P, s), fp = df_sr(&P, s);
                         double u[3], ud = 0;
                         for (int a = 0; a < 3; ++a) {

@@ -327,6 +327,55 @@ def test_vjp_matches_finite_differences(periodic):
     assert oracle.rms_rel(vj, fd) < 1e-6
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_vjp_coincident_particles_matches_finite_differences(periodic):
+    # particles duplicated at the same position: with softening the pair force
+    # m d f(|d|^2) is smooth through d = 0, so moving one copy changes the loss
+    # at the rate f(0) u; the adjoint must include that term (central
+    # differences of the forward sum, which itself ignores s = 0 pairs)
+    rng = RNG(27 + periodic)
+    P = prob(12.0, periodic, 3.0, 0.05, random_poly(rng))
+    n = 300
+    x = rng.random((n, 3)) * 12.0
+    dup = np.arange(0, 60, 2)
+    x[dup + 1] = x[dup]  # 30 coincident pairs, some active-passive when open
+    n_act = 300 if periodic else 250
+    extra = []
+    if n_act < n:
+        x[n_act - 1] = x[n_act]  # one pair across the active / passive split
+        extra = [n_act - 1, n_act]
+    m = rng.uniform(0.5, 2.0, n)
+    g = rng.standard_normal((n_act, 3))
+    h = 1e-6
+    close = near_cutoff(x, P, h)
+    idx = [k for k in list(dup[:12]) + list(dup[:12] + 1) + extra if not close[k].any()]
+    fd = _loss_grad_fd(x, m, n_act, P, g, idx, h)
+    vj = oracle.vjp(x, m, n_act, P, g, targets=np.array(idx))
+    assert len(idx) >= 20
+    assert oracle.rms_rel(vj, fd) < 1e-6
+    row = np.linalg.norm(vj - fd, axis=1) / np.linalg.norm(fd, axis=1)
+    assert row.max() < 1e-5
+    # the cell list and the all-images sum agree on the coincident pairs too
+    b = oracle.vjp_brute(x, m, n_act, P, g)
+    assert np.max(np.abs(oracle.vjp(x, m, n_act, P, g) - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_vjp_coincident_particles_unsoftened_left_out():
+    # eps = 0: f is singular at s = 0, so a coincident pair adds nothing (as in
+    # the forward sum): moving the duplicate far away leaves the other rows' sums
+    rng = RNG(33)
+    P = prob(12.0, True, 3.0, 0.0, (0.0,) * 6)
+    n = 200
+    x = rng.random((n, 3)) * 12.0
+    x[1] = x[0]
+    m = np.ones(n)
+    g = rng.standard_normal((n, 3))
+    v = oracle.vjp(x, m, n, P, g)
+    assert np.all(np.isfinite(v))
+    b = oracle.vjp_brute(x, m, n, P, g)
+    assert np.max(np.abs(v - b)) <= 1e-12 * np.max(np.abs(b))
+
+
 def test_vjp_equals_jvp_for_equal_masses():
     # equal masses, all active: the force is a gradient field, so its Jacobian
     # is symmetric and J^T g = J g = (a(x + h g) - a(x - h g)) / 2h

@@ -7,8 +7,13 @@ cotangent) and the float64 momentum check.  Inputs are resident in HBM before
 the timed region.  Prints one JSON line.
 
 value = pair interactions per second over the whole step: (useful pairs of
-the forward pass + useful pairs of the adjoint pass) / step time, a useful
-pair being an ordered (target, source) pair with 0 < r < r_s.
+the forward pass + useful pairs of the adjoint pass) / step time.  A useful
+pair is an ordered (target, source) pair with 0 < r < r_s; the forward's have
+an active target, the adjoint's at least one active end (a pair of two ghosts
+adds exactly nothing to the gradient and is not evaluated).  The forward
+kernel's own rate (useful forward pairs / forward kernel time) is
+forward_pairs_per_s.  `roofline` is the dominant kernel's (the adjoint's, the
+longest), with both kernels under roofline_forward and roofline_adjoint.
 """
 from __future__ import annotations
 
@@ -73,11 +78,29 @@ def cpu_baseline(w, g, target_seconds: float):
     t1 = time.perf_counter()
     oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g, targets=sample)
     t2 = time.perf_counter()
-    return {"value": 2.0 * pairs / (t2 - t0), "unit": "pair interactions/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{want} random active targets of {w.name} (seed 7), forward + adjoint, "
-                      f"float64 cell list incl. its own binning of all {w.n} particles per call; "
-                      f"{pairs} useful pairs per pass, {t1 - t0:.1f} s + {t2 - t1:.1f} s"}
+    out = {"value": 2.0 * pairs / (t2 - t0), "unit": "pair interactions/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"{want} random active targets of {w.name} (seed 7), forward + adjoint, "
+                     f"float64 cell list incl. its own binning of all {w.n} particles per call; "
+                     f"{pairs} useful pairs per pass, {t1 - t0:.1f} s + {t2 - t1:.1f} s"}
+    # one host thread, on a sample sized for a few seconds of pair work
+    one = np.sort(rng.choice(w.n_active, size=max(2000, want // (4 * max(1, oracle.num_threads()))),
+                             replace=False))
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, p1 = oracle.force(w.pos, w.mass, w.n_active, w.problem, targets=one)
+        t1 = time.perf_counter()
+        oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g, targets=one)
+        t2 = time.perf_counter()
+    finally:
+        oracle.set_num_threads(threads)
+    out["single_thread"] = {"value": 2.0 * p1 / (t2 - t0), "unit": "pair interactions/s", "cores": 1,
+                            "sample": f"{len(one)} random active targets (seed 7), forward + adjoint, "
+                                      f"{p1} useful pairs per pass, {t1 - t0:.1f} s + {t2 - t1:.1f} s "
+                                      f"(binning of all particles included)"}
+    return out
 
 
 def batch_comparison(reps: int = 5):
@@ -91,8 +114,7 @@ def batch_comparison(reps: int = 5):
     dev = "cuda:0"
     pos = torch.from_numpy(b.pos).to(dev)
     mass = torch.from_numpy(b.mass).to(dev)
-    cache = os.path.join(ROOT, "paper_1411_3396_amd", "tune_cache.json")
-    plan = sr.BatchPlan(b.offsets, b.n_active, b.problems, tune_cache=cache)
+    plan = sr.BatchPlan(b.offsets, b.n_active, b.problems, tune_cache=sr._sr.default_tune_cache())
     ws = sr.new_workspace(plan.ws_bytes, dev)
     acc = torch.empty((plan.total_active, 3), device=dev)
     mom = torch.empty((plan.B, 3), dtype=torch.float64, device=dev)
@@ -426,9 +448,7 @@ def main() -> int:
     # useful pairs of both passes, counted once outside the timed region
     sr.bin(pos, mass, w.problem, w.n_active, ws=ws)
     pairs_fwd = int(sr.count_pairs(ws, w.n, w.problem, w.n_active).item())
-    ws_all = sr.bin(pos, mass, w.problem, w.n)
-    pairs_bwd = int(sr.count_pairs(ws_all, w.n, w.problem, w.n).item())
-    del ws_all
+    pairs_bwd = int(sr.count_pairs(ws, w.n, w.problem, w.n_active, adjoint=True).item())
     torch.cuda.synchronize()
     log(f"useful pairs: forward {pairs_fwd:.4e}, adjoint {pairs_bwd:.4e}")
 
@@ -480,14 +500,15 @@ def main() -> int:
 
     rate = (pairs_fwd + pairs_bwd) / (ms_step * 1e-3)
     flops = {"force": FLOP_PER_PAIR["force"] * pairs_fwd, "vjp": FLOP_PER_PAIR["vjp"] * pairs_bwd}
-    dominant = max(kern, key=lambda k: kern[k])
-    achieved = flops[dominant] / (kern[dominant] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": KERNEL_SYMBOL[dominant], "achieved": round(achieved, 3),
+
+    def roof(k):
+        achieved = flops[k] / (kern[k] * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": KERNEL_SYMBOL[k], "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR, 4),
-                "traffic": measured_traffic(dominant, w.name),
-                "flop_per_useful_pair": FLOP_PER_PAIR[dominant], "kernel_ms": round(kern[dominant], 3)}
-    other = "force" if dominant == "vjp" else "vjp"
-    other_ach = flops[other] / (kern[other] * 1e-3) / 1e12
+                "traffic": measured_traffic(k, w.name), "flop_per_useful_pair": FLOP_PER_PAIR[k],
+                "kernel_ms": round(kern[k], 3)}
+
+    dominant = max(kern, key=lambda k: kern[k])
     result = {
         "metric": "short-range pair interactions/s (FP32) + backward/forward time ratio",
         "value": rate,
@@ -512,10 +533,9 @@ def main() -> int:
         "bwd_fwd_ratio_kernel": round(kern["vjp"] / kern["force"], 3),
         "bwd_fwd_ratio_step": round(phase["vjp"] / (phase["bin"] + phase["force"]), 3),
         "phase_ms": {k: round(v, 3) for k, v in phase.items()},
-        "roofline": roofline,
-        "roofline_other": {"kernel": KERNEL_SYMBOL[other], "achieved": round(other_ach, 3),
-                           "frac": round(other_ach / PEAK_FP32_VECTOR, 4),
-                           "kernel_ms": round(kern[other], 3)},
+        "roofline": roof(dominant),
+        "roofline_forward": roof("force"),
+        "roofline_adjoint": roof("vjp"),
         "peak_fp32_nonpacked": PEAK_FP32_NONPACKED,
     }
     if not args.no_batch:

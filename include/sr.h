@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SR_ABI_VERSION 2
+#define SR_ABI_VERSION 3
 
 typedef enum sr_status {
     SR_OK = 0,
@@ -66,12 +66,23 @@ typedef enum sr_status {
 /* sr_batch_force flags */
 #define SR_BATCH_PER_SUBVOLUME 1u /* reference mode: one sr_force per subvolume */
 #define SR_BATCH_EAGER 2u         /* batched kernels launched directly, no graph */
+#define SR_BATCH_RECAPTURE 4u     /* graph mode with pointers other than those the plan's
+                                     graph is bound to: capture it again (waits for the
+                                     stream) instead of returning SR_E_PLAN */
+
+/* sr_count_pairs flags */
+#define SR_COUNT_ADJOINT 1u /* count the pairs the adjoint evaluates (at least one
+                               active end) instead of those of the forward */
 
 /* sr_ws_flags bits */
 #define SR_FLAG_NONFINITE 1u     /* some position was NaN or infinite */
 #define SR_FLAG_OUT_OF_DOMAIN 2u /* open domain: some position outside [lo, lo+len) */
 #define SR_FLAG_NOT_BINNED 4u    /* SR_REUSE_BINS on a workspace without bins for these
                                     sizes: nothing was computed */
+#define SR_FLAG_QUEUE 8u         /* a persistent kernel's work loop was cut short: one of
+                                    its waves pulled an item out of order or more items
+                                    than exist (a defect of the build or a corrupted
+                                    workspace, never of the input); results incomplete */
 
 /* One short-range problem (paper Sec. 2; softening length from Sec. 3.1).
  *  lo, len   domain origin and extent per dimension.  Periodic boxes need
@@ -146,7 +157,16 @@ sr_status sr_workspace_bytes(int64_t n, const sr_problem *prob /*host*/, size_t 
 
 /* Bin the particles into the chaining mesh: cell of each particle, stable
  * counting sort by cell, binned offsets and masses (the layout above).
- * pos [n][3], mass [n]; 0 <= n_active <= n < 2^31. */
+ * The paper names the short-range solver's neighbour structures (chaining
+ * mesh, tree) only through the HACC method papers (Sec. 2); the binning rule
+ * above is this library's reading: cells of side >= r_s, so that every pair
+ * inside the cutoff lies in the 27 cells around a particle's own.
+ * pos [n][3], mass [n] (device, read only); 0 <= n_active <= n < 2^31.  The
+ * workspace receives the bins (read by sr_force / sr_force_vjp with
+ * SR_REUSE_BINS and by sr_bin_view).  Returns SR_E_ARG for a bad problem or
+ * a null pointer with n > 0, SR_E_WORKSPACE for a workspace that is null,
+ * misaligned or smaller than sr_workspace_bytes, SR_E_UNSUPPORTED when the
+ * cells and leaf depth do not fit the 31-bit sort key. */
 sr_status sr_bin(const float *pos, const float *mass, int64_t n, int64_t n_active,
                  const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, void *stream);
 
@@ -164,22 +184,31 @@ sr_status sr_force(const float *pos, const float *mass, int64_t n, int64_t n_act
                    float *acc, void *stream);
 
 /* Vector-Jacobian product of the accelerations with respect to the
- * positions: for L = sum_{i < n_active} g_i . a_i,
- *   grad_pos[k] = dL/dx_k = sum_{j != k, 0 < s < r_s^2} [ f u + 2 f' (u.d) d ],
+ * positions.  The paper has no adjoint: this is the derivative of the
+ * short-range sum above (Sec. 2), added so that the force step can sit
+ * inside a differentiable program.  For L = sum_{i < n_active} g_i . a_i,
+ *   grad_pos[k] = dL/dx_k = sum_{j != k, s < r_s^2} [ f u + 2 f' (u.d) d ],
  *   d = x_j - x_k, u = m_k g_j - m_j g_k (g = 0 on passive rows),
- * f = f_SR(s), f' = df_SR/ds.  Masses are constants; the jump of the cutoff
- * is not differentiated.  g [n_active][3]; grad_pos [n][3] (passive
- * particles receive gradient as sources), overwritten.  Pair terms are
- * recomputed, not stored.  Bins first unless flags has SR_REUSE_BINS. */
+ * f = f_SR(s), f' = df_SR/ds.  Pairs of two passive particles add nothing
+ * (u = 0) and are not evaluated.  A pair at s = 0 (a distinct particle at the
+ * same position) adds f(0) u when eps > 0, the derivative of its force term
+ * m d f(|d|^2), which is smooth through d = 0; with eps = 0 it is left out.
+ * Masses are constants; the jump of the cutoff is not differentiated.
+ * g [n_active][3] (device, read only); grad_pos [n][3] (device, overwritten;
+ * passive particles receive gradient as sources).  Pair terms are
+ * recomputed, not stored.  Bins first unless flags has SR_REUSE_BINS.
+ * Errors as for sr_force (SR_E_ARG also for g null with n_active > 0). */
 sr_status sr_force_vjp(const float *pos, const float *mass, int64_t n, int64_t n_active,
                        const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, unsigned flags,
                        const float *g, float *grad_pos, void *stream);
 
 /* Number of ordered pairs (i active, j) with 0 < s_ij < r_s^2, decided with
  * the same float32 arithmetic as sr_force, written to *pairs (device int64).
+ * With SR_COUNT_ADJOINT: the ordered pairs (k, j) with 0 < s < r_s^2 of
+ * which at least one end is active, the pairs sr_force_vjp evaluates.
  * Needs a workspace binned for these inputs. */
 sr_status sr_count_pairs(int64_t n, int64_t n_active, const sr_problem *prob /*host*/, void *ws,
-                         size_t ws_bytes, int64_t *pairs, void *stream);
+                         size_t ws_bytes, unsigned flags, int64_t *pairs, void *stream);
 
 /* Momentum check: out[0..2] = sum_{i < n_rows} mass[i] * acc[i] in float64
  * (device double[3]), summed in a fixed order.  Uses the workspace as
@@ -200,9 +229,12 @@ sr_status sr_ws_flags(const void *ws, void *stream, uint32_t *flags /*host out*/
  * sr_batch_plan_create (host) validates the batch, lays out the workspace
  * and reports its size in *ws_bytes.  tune_cache (host, nullable) names a
  * JSON file in which launch parameters measured on the first run are kept.
- * The plan owns only host memory, one HIP stream and, after the first run,
- * a captured HIP graph of the whole bin-then-force sequence bound to the
- * pointers of that run; a later run with other pointers captures again. */
+ * The plan owns only host memory, one HIP stream and, after the first run
+ * in graph mode, a captured HIP graph of the whole bin-then-force sequence
+ * bound to the pointers (pos, mass, ws, acc, momentum) of that run.  A later
+ * graph-mode run with other pointers returns SR_E_PLAN before enqueuing
+ * anything, unless flags has SR_BATCH_RECAPTURE: then it waits for the stream
+ * and captures again. */
 sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets /*host [B+1]*/,
                                const int64_t *n_active /*host [B]*/,
                                const sr_problem *probs /*host [B]*/, const char *tune_cache,
@@ -211,7 +243,9 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets /*host [B+1]*/,
 /* Run a batch: acc [sum n_active][3]; momentum (nullable) [B][3] float64 =
  * sum over active rows of mass * acc per subvolume.  flags:
  * SR_BATCH_PER_SUBVOLUME (one sr_force per subvolume, the reference mode),
- * SR_BATCH_EAGER (batched kernels without a graph), 0 (graph replay). */
+ * SR_BATCH_EAGER (batched kernels without a graph), 0 (graph replay; with
+ * SR_BATCH_RECAPTURE, capture again for new pointers).  The first run that
+ * is not per-subvolume tunes the launch parameters (it synchronises). */
 sr_status sr_batch_force(sr_batch_plan *plan, const float *pos, const float *mass, void *ws,
                          size_t ws_bytes, float *acc, double *momentum, unsigned flags,
                          void *stream);

@@ -31,6 +31,8 @@ def lib():
             _b.build()
         L = C.CDLL(_LIB_PATH)
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.argtypes = [C.c_int]
+        L.oracle_set_num_threads.restype = None
         L.oracle_grid.argtypes = [_p, C.c_float, C.c_int, _p]
         L.oracle_bin_reference.argtypes = [_p, _i64, _i64, _p, _p, C.c_int, C.c_float, C.c_int, _p, _p,
                                            _p, _p, _p]
@@ -52,6 +54,12 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the calling thread's later oracle calls (for callers that
+    run many small calls from a thread pool; ctypes releases the GIL)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

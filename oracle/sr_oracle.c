@@ -55,6 +55,17 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads the calling thread's later calls use (the caller runs many small
+ * oracle calls from its own pool of threads). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* float32 binning rule                                                 */
 /* ------------------------------------------------------------------ */

@@ -21,8 +21,12 @@ STATUS = {0: "SR_OK", 1: "SR_E_ARG", 2: "SR_E_WORKSPACE", 3: "SR_E_DEVICE", 4: "
 REUSE_BINS = 1
 BATCH_PER_SUBVOLUME = 1
 BATCH_EAGER = 2
+BATCH_RECAPTURE = 4
+COUNT_ADJOINT = 1
 FLAG_NONFINITE = 1
 FLAG_OUT_OF_DOMAIN = 2
+FLAG_NOT_BINNED = 4
+FLAG_QUEUE = 8
 
 # the exported names of sr.h, in declaration order
 EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "sr_bin",
@@ -34,6 +38,18 @@ EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "
            "sr_centres", "sr_pk_plan_create", "sr_pk_plan_destroy", "sr_pk_deposit", "sr_pk_grid",
            "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_timing_enable",
            "sr_timing_read")
+
+
+def default_tune_cache() -> str:
+    """Where batch plans keep tuned launch parameters: $SR_TUNE_CACHE, else a
+    file in the user's cache directory (never inside the package)."""
+    path = os.environ.get("SR_TUNE_CACHE")
+    if path:
+        return path
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    d = os.path.join(base, "paper_1411_3396_amd")
+    os.makedirs(d, exist_ok=True)
+    return os.path.join(d, "tune_cache.json")
 
 
 class SRError(RuntimeError):
@@ -60,7 +76,7 @@ class BinLayout(C.Structure):
 
 
 # sr_problem layout and entry points of include/sr.h (SR_ABI_VERSION)
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 _lib = None
 
@@ -82,7 +98,7 @@ def lib():
         L.sr_bin_view.argtypes = [p, i64, i64, p, p]
         L.sr_force.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p]
         L.sr_force_vjp.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p, p]
-        L.sr_count_pairs.argtypes = [i64, i64, p, p, C.c_size_t, p, p]
+        L.sr_count_pairs.argtypes = [i64, i64, p, p, C.c_size_t, u, p, p]
         L.sr_momentum.argtypes = [p, p, i64, p, C.c_size_t, p, p]
         L.sr_ws_flags.argtypes = [p, p, p]
         L.sr_batch_plan_create.argtypes = [C.c_int32, p, p, p, C.c_char_p, p, p]
@@ -266,13 +282,15 @@ def force_vjp(pos, mass, prob, g, n_active=None, ws=None, reuse_bins=False, out=
     return out
 
 
-def count_pairs(ws, n, prob, n_active=None, stream=None) -> torch.Tensor:
-    """Device int64 scalar: ordered pairs (active i, j) with 0 < s < r_s^2."""
+def count_pairs(ws, n, prob, n_active=None, adjoint=False, stream=None) -> torch.Tensor:
+    """Device int64 scalar: ordered pairs (active i, j) with 0 < s < r_s^2; with
+    adjoint=True the pairs with at least one active end (those the adjoint evaluates)."""
     n_active = int(n) if n_active is None else int(n_active)
     out = torch.zeros(1, dtype=torch.int64, device=ws.device)
     P = as_problem(prob)
-    _check(lib().sr_count_pairs(int(n), n_active, C.byref(P), _ptr(ws), ws.numel(), _ptr(out),
-                                _stream(stream)), "sr_count_pairs")
+    _check(lib().sr_count_pairs(int(n), n_active, C.byref(P), _ptr(ws), ws.numel(),
+                                COUNT_ADJOINT if adjoint else 0, _ptr(out), _stream(stream)),
+           "sr_count_pairs")
     return out
 
 
@@ -347,8 +365,14 @@ class BatchPlan:
         self.ws_bytes = int(nb.value)
         self.total_active = int(n_active.sum())
 
-    def run(self, pos, mass, ws, acc, momentum=None, mode: str = "graph", stream=None):
+    def run(self, pos, mass, ws, acc, momentum=None, mode: str = "graph", stream=None,
+            recapture: bool = False):
+        """mode: "graph" (replay of the captured graph; with recapture=True new
+        pointers capture again instead of raising SR_E_PLAN), "eager" or
+        "per_subvolume"."""
         flags = {"graph": 0, "eager": BATCH_EAGER, "per_subvolume": BATCH_PER_SUBVOLUME}[mode]
+        if recapture:
+            flags |= BATCH_RECAPTURE
         n = int(self.offsets[-1])
         pos = _dev_f32(pos, "pos", (n, 3))
         mass = _dev_f32(mass, "mass", (n,))

@@ -24,7 +24,6 @@ from . import _sr
 
 Rect = Tuple[int, int, int, int]  # (gx0, gx1, gy0, gy1), grid units, half-open
 
-TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
 def grid_units(domain) -> Tuple[int, int]:
@@ -115,7 +114,7 @@ class BlockForce:
 
     def __init__(self, domain, blocks: Sequence[Rect], n: int, n_active: Optional[int] = None,
                  ng: Optional[Sequence[int]] = None, capacity: Optional[int] = None, device="cuda",
-                 tune_cache: Optional[str] = TUNE_CACHE):
+                 tune_cache: Optional[str] = None):
         self.domain = domain
         self.ng = tuple(ng) if ng is not None else grid_units(domain)
         self.blocks = [tuple(int(v) for v in b) for b in blocks]
@@ -124,7 +123,7 @@ class BlockForce:
             capacity = int(1.3 * membership_estimate(domain, self.ng, self.blocks) * self.n) + 4096
         self.n_active = self.n if n_active is None else int(n_active)
         self.device = device
-        self.tune_cache = tune_cache
+        self.tune_cache = tune_cache if tune_cache is not None else _sr.default_tune_cache()
         self._make_plan(capacity)
         self.problems = self.plan.problems()
         self._batch = None
@@ -189,7 +188,9 @@ class BlockForce:
         self.plan.gather(pos, mass, self.ws, bpos=bpos, bmass=bmass, want_src=False)
         clock.tick("gather")
         plan = self.batch_plan()
-        plan.run(bpos, bmass, self._batch_ws, bacc, None, mode)
+        # the block buffers are reallocated when the membership count changes:
+        # let a graph-mode plan capture again for them
+        plan.run(bpos, bmass, self._batch_ws, bacc, None, mode, recapture=True)
         clock.tick("force")
         acc = self.plan.reconcile(bacc, self.ws)
         clock.tick("reconcile")

@@ -124,8 +124,9 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.digit_bits = (bits + L.passes - 1) / L.passes;
     L.ntiles = std::max<int64_t>(1, (N + kRadixTile - 1) / kRadixTile);
     L.table = (int64_t(1) << L.digit_bits) * L.ntiles;
-    // a cell of nt targets makes at most nt / kSparseGroup + 1 items
-    L.item_cap = NC + (N + kSparseGroup - 1) / kSparseGroup + 1;
+    // a run of n targets makes at most ceil(n / kSparseGroup) items, and a
+    // cell has up to two runs (active targets; passive ones in the adjoint)
+    L.item_cap = 2 * NC + (N + kSparseGroup - 1) / kSparseGroup + 1;
     L.mom_tiles = mom_tiles;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -225,6 +226,19 @@ struct EnvDefaults {
     }
 } g_env_defaults;
 
+// Most items one wave of a persistent kernel may pull.  The kernels bound
+// their loops by the item count themselves; SR_PULL_LIMIT (read on every
+// call) lowers the bound so that a test can make every wave stop early and
+// check that the workspace is flagged and the kernel still exits.
+int64_t pull_limit()
+{
+    if (const char *v = std::getenv("SR_PULL_LIMIT")) {
+        const long long q = std::atoll(v);
+        if (q >= 0) return (int64_t)q;
+    }
+    return INT64_MAX;
+}
+
 sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *seg_host,
                       const SegParams *seg_dev, void *stream, int waves_per_cu, int64_t n_rows,
                       int cfg = kCfgForce)
@@ -254,6 +268,7 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.n_rows = (int)n_rows;
     a.targets_per_lane = g_tpl_default[cfg].load();
     a.occupancy = g_occ_default[cfg].load();
+    a.pull_limit = pull_limit();
     return SR_OK;
 }
 
@@ -637,17 +652,17 @@ sr_status sr_force_vjp(const float *pos, const float *mass, int64_t n, int64_t n
 }
 
 sr_status sr_count_pairs(int64_t n, int64_t n_active, const sr_problem *prob, void *ws,
-                         size_t ws_bytes, int64_t *pairs, void *stream)
+                         size_t ws_bytes, unsigned flags, int64_t *pairs, void *stream)
 {
     Single s;
     sr_status st = prepare_single(n, n_active, prob, s);
     if (st != SR_OK) return st;
-    if (!pairs) return SR_E_ARG;
+    if (!pairs || (flags & ~SR_COUNT_ADJOINT)) return SR_E_ARG;
     if ((st = check_ws(ws, ws_bytes, s.L)) != SR_OK) return st;
     DevArgs a;
     if ((st = device_args(a, ws, &s.L, &s.seg, nullptr, stream, 0, n_active)) != SR_OK) return st;
     if (n == 0 || n_active == 0) return hip_status(dev_zero(pairs, 2, a.st));
-    return hip_status(dev_count_pairs(a, pairs));
+    return hip_status(dev_count_pairs(a, (flags & SR_COUNT_ADJOINT) != 0, pairs));
 }
 
 sr_status sr_momentum(const float *acc, const float *mass, int64_t n_rows, void *ws,
@@ -774,7 +789,7 @@ sr_status sr_batch_force(sr_batch_plan *P, const float *pos, const float *mass, 
                          void *stream)
 {
     if (!P || P->B < 1) return SR_E_PLAN;
-    if (flags & ~(SR_BATCH_PER_SUBVOLUME | SR_BATCH_EAGER)) return SR_E_ARG;
+    if (flags & ~(SR_BATCH_PER_SUBVOLUME | SR_BATCH_EAGER | SR_BATCH_RECAPTURE)) return SR_E_ARG;
     const int64_t N = P->offsets[P->B];
     if (N > 0 && (!pos || !mass)) return SR_E_ARG;
     if (P->total_active > 0 && !acc) return SR_E_ARG;
@@ -789,15 +804,19 @@ sr_status sr_batch_force(sr_batch_plan *P, const float *pos, const float *mass, 
     if (flags & SR_BATCH_EAGER) return run_batched(P, pos, mass, ws, acc, momentum, st);
     const bool bound = P->exec && P->b_pos == pos && P->b_mass == mass && P->b_ws == ws &&
                        P->b_acc == acc && P->b_mom == momentum;
+    if (P->exec && !bound && !(flags & SR_BATCH_RECAPTURE)) return SR_E_PLAN;
     if (!bound) {
-        drop_graph(P);
-        // capture waits for nothing on the caller's stream: order it first
+        // Capture waits for nothing on the caller's stream: order it first.
+        // The old graph may still run there (an earlier replay), so it is
+        // destroyed only once the stream has drained.
         hipEvent_t ev;
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return SR_E_DEVICE;
         (void)hipEventRecord(ev, st);
         (void)hipStreamWaitEvent(P->cap, ev, 0);
-        (void)hipStreamSynchronize(P->cap);
+        const hipError_t se = hipStreamSynchronize(P->cap);
         (void)hipEventDestroy(ev);
+        if (se != hipSuccess) return SR_E_DEVICE;
+        drop_graph(P);
         if (hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return SR_E_DEVICE;
         sr_status s = run_batched(P, pos, mass, ws, acc, momentum, P->cap);

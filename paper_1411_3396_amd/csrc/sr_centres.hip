@@ -16,6 +16,7 @@
 // every sum is fixed by the item table, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -27,9 +28,13 @@ namespace {
 constexpr float kFarAway = 1.0e18f;  // padding source: contributes m q = 0 * q
 constexpr int kTargetsPerWave = 64;
 
+// Workspace header: the condition word first (read by sr_ws_flags, like a
+// force workspace's), the queue counter on its own 128-byte line.
 struct CentreHeader {
+    uint32_t flags;
+    uint32_t pad0[31];
     uint32_t next;  // queue counter
-    uint32_t pad[63];
+    uint32_t pad1[31];
 };
 
 // Item: x = halo, y = first target, z = targets, w = lk | two << 4 | slot << 5.
@@ -163,10 +168,18 @@ template <bool kSoft>
 __global__ __launch_bounds__(64, 4) void k_centre_potential(
     const int4 *__restrict__ items, uint32_t n_items, const int *__restrict__ hoff,
     const float *__restrict__ pos, const float *__restrict__ mass, float eps2,
-    float *__restrict__ phi, int2 *__restrict__ partial, CentreHeader *hdr)
+    float *__restrict__ phi, int2 *__restrict__ partial, CentreHeader *hdr, int64_t pull_limit)
 {
     __shared__ float4 stage[kTargetsPerWave];
     const int lane = threadIdx.x;
+    // Loop bound: the counter hands out increasing values, so one wave's
+    // items increase strictly and it cannot pull more than exist.  A pull
+    // that breaks either rule ends the loop and flags the workspace instead
+    // of spinning; pull_limit below the item count (a test hook) ends every
+    // wave early on purpose.
+    const int64_t limit = min((int64_t)n_items, pull_limit);
+    int64_t pulls = 0, last = -1;
+    bool bad = false;
     for (;;) {
         // Lane 0 takes the next item; the loop body below ends with no other
         // lane-0-only branch, so the compiler cannot merge the two into one
@@ -176,6 +189,11 @@ __global__ __launch_bounds__(64, 4) void k_centre_potential(
         if (lane == 0) g = atomicAdd(&hdr->next, 1u);
         g = __builtin_amdgcn_readfirstlane(g);
         if (g >= n_items) break;
+        if ((int64_t)g <= last || ++pulls > limit) {
+            bad = true;
+            break;
+        }
+        last = g;
         const int4 it = uniform_item(items, g);
         const int h = it.x, t0 = it.y, nt = it.z, lk = it.w & 15;
         const bool two = (it.w >> 4) & 1;
@@ -247,6 +265,7 @@ __global__ __launch_bounds__(64, 4) void k_centre_potential(
         const MinIdx m = wave_argmin(v, idx);
         partial[slot] = make_int2(__float_as_int(m.v), m.i);
     }
+    if (bad && lane == 0) atomicOr(&hdr->flags, (uint32_t)SR_FLAG_QUEUE);
 }
 
 // Per halo: the best of its items' minima (one wave per halo).
@@ -416,12 +435,15 @@ sr_status sr_centres(sr_centres_plan *P, const float *pos, const float *mass, fl
     if (P->n_items > 0) {
         const int64_t grid = std::min<int64_t>(P->n_items, (int64_t)P->num_cu * 32);
         const float eps2 = eps * eps;
+        int64_t limit = INT64_MAX;
+        if (const char *v = std::getenv("SR_PULL_LIMIT"))
+            if (std::atoll(v) >= 0) limit = std::atoll(v);
         if (eps2 > 0.f)
             k_centre_potential<true><<<(unsigned)grid, 64, 0, s>>>(items, (uint32_t)P->n_items, hoff, pos,
-                                                                 mass, eps2, phi, partial, hdr);
+                                                                 mass, eps2, phi, partial, hdr, limit);
         else
             k_centre_potential<false><<<(unsigned)grid, 64, 0, s>>>(items, (uint32_t)P->n_items, hoff, pos,
-                                                                  mass, 0.f, phi, partial, hdr);
+                                                                  mass, 0.f, phi, partial, hdr, limit);
         if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
     }
     k_centre_argmin<<<(unsigned)((P->H + 3) / 4), 256, 0, s>>>(partial, hbase, P->H, mbp, phi_min);

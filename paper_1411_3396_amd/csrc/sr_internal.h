@@ -113,12 +113,13 @@ struct DevArgs {
     int n_rows;  // rows of the force output (sum of n_active)
     int targets_per_lane;  // 1 or 2 for cells with more than 64 targets
     int occupancy;         // register-allocation hint of the pair kernels: 0, 6 or 8 waves/SIMD
+    int64_t pull_limit;    // most items one wave of a persistent kernel may pull (test hook)
 };
 
 hipError_t dev_bin(const DevArgs &a, const float *pos, const float *mass);
 hipError_t dev_force(const DevArgs &a, float *acc);
 hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad);
-hipError_t dev_count_pairs(const DevArgs &a, int64_t *pairs);
+hipError_t dev_count_pairs(const DevArgs &a, bool adjoint, int64_t *pairs);
 hipError_t dev_zero(void *p, int64_t words, hipStream_t st);
 
 // Shared building blocks (sr_kernels.hip) for other device passes.

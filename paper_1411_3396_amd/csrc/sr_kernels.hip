@@ -514,8 +514,62 @@ __device__ __forceinline__ int cell_items(int nt, bool two)
     return dense + (r + kSparseGroup - 1) / kSparseGroup;
 }
 
+// Work item: x = home cell, y = first target slot, z = targets,
+// w = lk | two << 3 | psrc << 4 | seg << 5 (lk: log2 lanes per target; two:
+// two targets per lane; psrc: the targets are passive and their sources are
+// the active particles of the 27 cells only; seg: the problem of a batch).
+__device__ __forceinline__ int item_word(int lk, int two, int psrc, int seg)
+{
+    return lk | (two << 3) | (psrc << 4) | (seg << 5);
+}
+__device__ __forceinline__ int item_lk(int w) { return w & 7; }
+__device__ __forceinline__ bool item_two(int w) { return (w >> 3) & 1; }
+__device__ __forceinline__ bool item_psrc(int w) { return (w >> 4) & 1; }
+__device__ __forceinline__ int item_seg(int w) { return w >> 5; }
+
+// Items of a run of nt consecutive targets from slot s0 (the cut described
+// above); returns the number written, cell_items(nt, two).
+__device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, int c, int s0, int nt,
+                                         bool two, int seg, int psrc)
+{
+    if (nt <= 0) return 0;
+    int k = 0;
+    if (nt < kTargetsPerItem) {
+        for (int t = 0; t < nt; t += kSparseGroup, ++k) {
+            const int cn = min(kSparseGroup, nt - t);
+            items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg));
+        }
+        return k;
+    }
+    const int r = nt % kTargetsPerItem, dense_end = nt - r;
+    for (int t0 = 0; t0 < dense_end; ++k) {
+        const int cn = (two && dense_end - t0 >= 2 * kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
+        items[at + k] = make_int4(c, s0 + t0, cn, item_word(0, cn > kTargetsPerItem ? 1 : 0, psrc, seg));
+        t0 += cn;
+    }
+    for (int t = dense_end; t < nt; t += kSparseGroup, ++k) {
+        const int cn = min(kSparseGroup, nt - t);
+        items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg));
+    }
+    return k;
+}
+
+// Cost of the widest item of a run of nt targets that sees src sources:
+// pairs one lane evaluates.
+__device__ __forceinline__ int64_t run_cost(int nt, int64_t src, bool two)
+{
+    if (nt <= 0) return 0;
+    const int lk = nt >= kTargetsPerItem ? 0 : lanes_log2(min(nt, kSparseGroup));
+    const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
+    return ((src + (1 << lk) - 1) >> lk) * (chunk / kTargetsPerItem);
+}
+
 // Per home cell: number of items and cost class (floor log2 of the pairs one
-// lane evaluates); counts items per class.
+// lane evaluates); counts items per class.  The forward takes the cell's
+// active targets against every source of the 27 cells.  The adjoint also
+// takes its passive targets, as items of their own whose sources are only
+// the active particles of the 27 cells: a pair of two passive particles has
+// u = m_k g_j - m_j g_k = 0, so it adds exactly nothing.
 template <class Acc, bool kActiveOnly>
 __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
                                                  const int *__restrict__ start,
@@ -528,15 +582,16 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
         info[c] = 0;
         return;
     }
-    const int nt = kActiveOnly ? nact[c] : (start[c + 1] - start[c]);
-    if (nt <= 0 || nt > N) {
+    const int na = nact[c];
+    const int np = kActiveOnly ? 0 : (start[c + 1] - start[c]) - na;
+    if (na < 0 || np < 0 || na + np <= 0 || na + np > N) {
         info[c] = 0;
         return;
     }
     const SegParams &S = acc.get(acc.seg_of_cell(c));
     int ix, iy, iz;
     decode_cell(S, c, ix, iy, iz);
-    int64_t src = 0;
+    int64_t src = 0, src_act = 0;
     for (int dx = -1; dx <= 1; ++dx) {
         int jx = ix + dx;
         if (jx < 0 || jx >= S.nc[0]) {
@@ -557,14 +612,13 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
                 }
                 const int cc = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
                 src += start[cc + 1] - start[cc];
+                if (np > 0) src_act += nact[cc];
             }
         }
     }
     // cost class from the cell's widest item: a group of min(nt, kSparseGroup) targets when sparse
-    const int lk = nt >= kTargetsPerItem ? 0 : lanes_log2(min(nt, kSparseGroup));
-    const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
-    const int n_items = cell_items(nt, two);
-    int64_t cost = ((src + (1 << lk) - 1) >> lk) * (chunk / kTargetsPerItem);
+    const int n_items = cell_items(na, two) + cell_items(np, two);
+    int64_t cost = max(run_cost(na, src, two), run_cost(np, src_act, two));
     if (cost < 1) cost = 1;
     int cls = 63 - __clzll((unsigned long long)cost);
     cls = cls > 31 ? 31 : cls;
@@ -629,28 +683,14 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
                             atomicAdd(&hdr[kHdrBucketCursor + threadIdx.x], cnt[threadIdx.x]);
     __syncthreads();
     if (!inf) return;
-    const int nt = kActiveOnly ? nact[c] : (start[c + 1] - start[c]);
+    const int na = nact[c];
+    const int nt = start[c + 1] - start[c];
     const int seg = acc.seg_of_cell(c);
     const uint32_t at = base[cls] + local;
     const int s0 = start[c];
-    if (nt < kTargetsPerItem) {
-        for (int t = 0, k = 0; t < nt; t += kSparseGroup, ++k) {
-            const int cn = min(kSparseGroup, nt - t);
-            items[at + k] = make_int4(c, s0 + t, cn, lanes_log2(cn) | (seg << 5));
-        }
-        return;
-    }
-    const int r = nt % kTargetsPerItem, dense_end = nt - r;
-    int k = 0;
-    for (int t0 = 0; t0 < dense_end; ++k) {
-        const int cn = (two && dense_end - t0 >= 2 * kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
-        items[at + k] = make_int4(c, s0 + t0, cn, ((cn > kTargetsPerItem ? 1 : 0) << 4) | (seg << 5));
-        t0 += cn;
-    }
-    for (int t = dense_end; t < nt; t += kSparseGroup, ++k) {
-        const int cn = min(kSparseGroup, nt - t);
-        items[at + k] = make_int4(c, s0 + t, cn, lanes_log2(cn) | (seg << 5));
-    }
+    // active targets (all sources), then for the adjoint the passive ones (active sources)
+    const int k = write_run(items, at, c, s0, na, two, seg, 0);
+    if (!kActiveOnly) write_run(items, at + k, c, s0 + na, nt - na, two, seg, 1);
 }
 
 // --------------------------------------------------------------- pair kernels
@@ -663,8 +703,11 @@ struct Stencil {
     int total;
 };
 
+// With act_only each cell contributes only its active particles (they lead
+// the cell): the sources of an item of passive targets.
 __device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
-                                              const int *__restrict__ start, int lane,
+                                              const int *__restrict__ start,
+                                              const int *__restrict__ nact, bool act_only, int lane,
                                               Stencil &st)
 {
     int ix, iy, iz;
@@ -681,7 +724,7 @@ __device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
         if (ok) {
             const int c = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
             st.nstart = start[c];
-            cnt = start[c + 1] - st.nstart;
+            cnt = act_only ? nact[c] : start[c + 1] - st.nstart;
         }
     }
     int incl = cnt;
@@ -746,11 +789,33 @@ __device__ __forceinline__ int64_t next_item(uint32_t *hdr, int q, int lane)
     return ((int64_t)(c / kQueueBlock) * kQueues + q) * kQueueBlock + (c % kQueueBlock);
 }
 
-// Work item: x = home cell, y = first target slot, z = targets, w = lk | two << 4 |
-// seg << 5 (lk: log2 lanes per target; two: two targets per lane).
-__device__ __forceinline__ int item_lk(int w) { return w & 15; }
-__device__ __forceinline__ bool item_two(int w) { return (w >> 4) & 1; }
-__device__ __forceinline__ int item_seg(int w) { return w >> 5; }
+// Bound of a persistent loop.  A queue hands out increasing counter values,
+// so the items one wave pulls from one queue increase strictly, and no wave
+// can pull more items than exist.  A pull that breaks either rule (a loop
+// whose lanes lost the item lane 0 was given, or a corrupted counter) ends
+// the wave's loop and flags the workspace, so the kernel exits instead of
+// spinning.  limit is at most the item count; a smaller one (the host's test
+// hook) ends every wave early on purpose.  All values are wave-uniform.
+struct PullGuard {
+    int64_t limit, pulls = 0, last = -1;
+    bool bad = false;
+    __device__ __forceinline__ explicit PullGuard(int64_t lim) : limit(lim) {}
+    __device__ __forceinline__ void next_queue() { last = -1; }
+    // false: leave the loop (bad is set)
+    __device__ __forceinline__ bool accept(int64_t g)
+    {
+        if (g <= last || ++pulls > limit) {
+            bad = true;
+            return false;
+        }
+        last = g;
+        return true;
+    }
+    __device__ __forceinline__ void report(uint32_t *hdr, int lane) const
+    {
+        if (bad && lane == 0) atomicOr(&hdr[kHdrFlags], (uint32_t)SR_FLAG_QUEUE);
+    }
+};
 
 // Work item with every field wave-uniform (scalar registers).
 __device__ __forceinline__ int4 load_item(const int4 *__restrict__ items, int64_t g)
@@ -798,12 +863,18 @@ __device__ __forceinline__ void force_pair(const float4 s, float px, float py, f
 
 // One adjoint pair term: r += f u + 2 f' (u.d) d, u = m_k g_j - m_j g_k.
 // With kUM, u / m = g_j - g_k is summed and the mass applied once at the end.
+// Both products of u are rounded before the difference (no fused form), so u
+// is exactly antisymmetric and the target's own entry (j = k, d = 0) adds
+// exactly zero.  A distinct particle at the same position (d = 0) adds
+// f(0) u: with softening the pair force m d f(|d|^2) is smooth through
+// d = 0 and this is its derivative.
 template <bool kSoft, bool kUM>
 __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float px, float py,
                                          float pz, float mk, float gkx, float gky, float gkz,
                                          float eps2, float tc2, const float *cq, const float *cd,
                                          float &rx, float &ry, float &rz)
 {
+#pragma clang fp contract(off)
     const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
     const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
     const float qi = __builtin_amdgcn_rsqf(tt);
@@ -812,9 +883,9 @@ __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float 
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
     const float f = in ? q3 - horner5(cq, tt) : 0.f;
     const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
-    const float ux = kUM ? gj.x - gkx : fmaf(mk, gj.x, -s.w * gkx);
-    const float uy = kUM ? gj.y - gky : fmaf(mk, gj.y, -s.w * gky);
-    const float uz = kUM ? gj.z - gkz : fmaf(mk, gj.z, -s.w * gkz);
+    const float ux = kUM ? gj.x - gkx : mk * gj.x - s.w * gkx;
+    const float uy = kUM ? gj.y - gky : mk * gj.y - s.w * gky;
+    const float uz = kUM ? gj.z - gkz : mk * gj.z - s.w * gkz;
     const float c = fp2 * fmaf(ux, dx, fmaf(uy, dy, uz * dz));
     rx = fmaf(c, dx, fmaf(f, ux, rx));
     ry = fmaf(c, dy, fmaf(f, uy, ry));
@@ -961,17 +1032,20 @@ template <class Acc, bool kSoft, bool kUM>
 __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restrict__ items,
                                             uint32_t *hdr, const int *__restrict__ start,
                                             const Src &src, const int *__restrict__ out_row,
-                                            float *__restrict__ out, int n_out, float4 *stage)
+                                            float *__restrict__ out, int n_out, float4 *stage,
+                                            int64_t pull_limit)
 {
     const int lane = threadIdx.x;
     const float m0 = kUM ? src.m[0] : 1.0f;
     const int64_t n_items = hdr[kHdrNItems];
     const int q0 = blockIdx.x & (kQueues - 1);
-    for (int qq = 0; qq < kQueues; ++qq) {
+    PullGuard guard(min(n_items, pull_limit));
+    for (int qq = 0; qq < kQueues && !guard.bad; ++qq) {
         const int q = (q0 + qq) & (kQueues - 1);
+        guard.next_queue();
         for (;;) {
             const int64_t g = next_item(hdr, q, lane);
-            if (g >= n_items) break;
+            if (g >= n_items || !guard.accept(g)) break;
             const int4 it = load_item(items, g);
             const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
             const SegParams &S = acc.get(item_seg(it.w));
@@ -980,7 +1054,7 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
 #pragma unroll
             for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
             Stencil st;
-            stencil_setup(S, it.x, start, lane, st);
+            stencil_setup(S, it.x, start, start, false, lane, st);
             auto fetch_p = [&](int v, float4 &c0, float4 &) { c0 = fetch_pos(st, v, src); };
             if (item_two(it.w)) {
                 const bool va = lane < nt, vb = kWave + lane < nt;
@@ -1048,18 +1122,19 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
             if (tv) store3(out, n_out, out_row[t0 + t], m0 * ax, m0 * ay, m0 * az);
         }
     }
+    guard.report(hdr, lane);
 }
 
 template <class Acc, bool kSoft, int kOcc>
 __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
     Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
-    const int *__restrict__ out_row, float *__restrict__ out, int n_out)
+    const int *__restrict__ out_row, float *__restrict__ out, int n_out, int64_t pull_limit)
 {
     __shared__ float4 stage[kStageForce + kWave];
     if (hdr[kHdrMassInfo] == 0)
-        force_items<Acc, kSoft, true>(acc, items, hdr, start, src, out_row, out, n_out, stage);
+        force_items<Acc, kSoft, true>(acc, items, hdr, start, src, out_row, out, n_out, stage, pull_limit);
     else
-        force_items<Acc, kSoft, false>(acc, items, hdr, start, src, out_row, out, n_out, stage);
+        force_items<Acc, kSoft, false>(acc, items, hdr, start, src, out_row, out, n_out, stage, pull_limit);
 }
 
 // ------------------------------------------------------------- adjoint kernel
@@ -1070,21 +1145,25 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
 template <class Acc, bool kSoft, bool kUM>
 __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict__ items,
                                           uint32_t *hdr, const int *__restrict__ start,
-                                          const Src &src, const float *__restrict__ gx,
+                                          const int *__restrict__ nact, const Src &src,
+                                          const float *__restrict__ gx,
                                           const float *__restrict__ gy,
                                           const float *__restrict__ gz,
                                           const int *__restrict__ perm, float *__restrict__ out,
-                                          int n_out, float4 *stage_p, float4 *stage_g)
+                                          int n_out, float4 *stage_p, float4 *stage_g,
+                                          int64_t pull_limit)
 {
     const int lane = threadIdx.x;
     const float m0 = kUM ? src.m[0] : 1.0f;
     const int64_t n_items = hdr[kHdrNItems];
     const int q0 = blockIdx.x & (kQueues - 1);
-    for (int qq = 0; qq < kQueues; ++qq) {
+    PullGuard guard(min(n_items, pull_limit));
+    for (int qq = 0; qq < kQueues && !guard.bad; ++qq) {
         const int q = (q0 + qq) & (kQueues - 1);
+        guard.next_queue();
         for (;;) {
             const int64_t g = next_item(hdr, q, lane);
-            if (g >= n_items) break;
+            if (g >= n_items || !guard.accept(g)) break;
             const int4 it = load_item(items, g);
             const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
             const SegParams &S = acc.get(item_seg(it.w));
@@ -1095,7 +1174,7 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
 #pragma unroll
             for (int k = 0; k < 5; ++k) cd[k] = S.pc.dq[k];
             Stencil st;
-            stencil_setup(S, it.x, start, lane, st);
+            stencil_setup(S, it.x, start, nact, item_psrc(it.w), lane, st);
             auto fetch_pg = [&](int v, float4 &c0, float4 &c1) {
                 fetch_vjp(st, v, src, gx, gy, gz, c0, c1);
             };
@@ -1174,47 +1253,54 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
             if (tv) store3(out, n_out, perm[t0 + t], m0 * rx, m0 * ry, m0 * rz);
         }
     }
+    guard.report(hdr, lane);
 }
 
 template <class Acc, bool kSoft, int kOcc>
 __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp(
-    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
-    const float *__restrict__ gx, const float *__restrict__ gy, const float *__restrict__ gz,
-    const int *__restrict__ perm, float *__restrict__ out, int n_out)
+    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start,
+    const int *__restrict__ nact, Src src, const float *__restrict__ gx,
+    const float *__restrict__ gy, const float *__restrict__ gz, const int *__restrict__ perm,
+    float *__restrict__ out, int n_out, int64_t pull_limit)
 {
     __shared__ float4 stage_p[kStageVjp + kWave];
     __shared__ float4 stage_g[kStageVjp + kWave];
     if (hdr[kHdrMassInfo] == 0)
-        vjp_items<Acc, kSoft, true>(acc, items, hdr, start, src, gx, gy, gz, perm, out, n_out,
-                                    stage_p, stage_g);
+        vjp_items<Acc, kSoft, true>(acc, items, hdr, start, nact, src, gx, gy, gz, perm, out, n_out,
+                                    stage_p, stage_g, pull_limit);
     else
-        vjp_items<Acc, kSoft, false>(acc, items, hdr, start, src, gx, gy, gz, perm, out, n_out,
-                                     stage_p, stage_g);
+        vjp_items<Acc, kSoft, false>(acc, items, hdr, start, nact, src, gx, gy, gz, perm, out, n_out,
+                                     stage_p, stage_g, pull_limit);
 }
 
-// Ordered pairs (active target, source) with 0 < s < r_s^2, decided exactly as
-// in k_force.
+// Ordered pairs (target, source) with 0 < s < r_s^2 over the items of one
+// pass, decided exactly as in the pair kernels: with the forward items the
+// pairs of an active target, with the adjoint items the pairs with at least
+// one active end.
 template <class Acc>
 __global__ __launch_bounds__(64) void k_count(Acc acc, const int4 *__restrict__ items,
                                               uint32_t *hdr, const int *__restrict__ start,
-                                              Src src)
+                                              const int *__restrict__ nact, Src src,
+                                              int64_t pull_limit)
 {
     __shared__ float4 stage[kWave];
     const int lane = threadIdx.x;
     const int64_t n_items = hdr[kHdrNItems];
     const int q0 = blockIdx.x & (kQueues - 1);
     unsigned long long pairs = 0;
-    for (int qq = 0; qq < kQueues; ++qq) {
+    PullGuard guard(min(n_items, pull_limit));
+    for (int qq = 0; qq < kQueues && !guard.bad; ++qq) {
         const int q = (q0 + qq) & (kQueues - 1);
+        guard.next_queue();
         for (;;) {
             const int64_t g = next_item(hdr, q, lane);
-            if (g >= n_items) break;
+            if (g >= n_items || !guard.accept(g)) break;
             const int4 it = load_item(items, g);
             const int t0 = it.y, nt = it.z, lk = item_lk(it.w);
             const SegParams &S = acc.get(item_seg(it.w));
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2;
             Stencil st;
-            stencil_setup(S, it.x, start, lane, st);
+            stencil_setup(S, it.x, start, nact, item_psrc(it.w), lane, st);
             const int kl = 1 << lk;
             const int t = lane >> lk, sub = lane & (kl - 1);
             const bool tv = t < nt;
@@ -1244,6 +1330,7 @@ __global__ __launch_bounds__(64) void k_count(Acc acc, const int4 *__restrict__ 
             if (tv) pairs += cnt_lane;
         }
     }
+    guard.report(hdr, lane);
     for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o);
     if (lane == 0 && pairs)
         atomicAdd((unsigned long long *)&hdr[kHdrPairs], pairs);
@@ -1464,7 +1551,7 @@ void launch_force(const DevArgs &a, Acc acc, float *acc_out)
     const Layout &L = *a.L;
     k_force<Acc, kSoft, kOcc><<<persistent_grid(a), kWave, 0, a.st>>>(
         acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
-        at<int>(a, L.out_row), acc_out, a.n_rows);
+        at<int>(a, L.out_row), acc_out, a.n_rows, a.pull_limit);
 }
 
 template <class Acc, bool kSoft, int kOcc>
@@ -1472,9 +1559,9 @@ void launch_vjp(const DevArgs &a, Acc acc, float *grad)
 {
     const Layout &L = *a.L;
     k_vjp<Acc, kSoft, kOcc><<<persistent_grid(a), kWave, 0, a.st>>>(
-        acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
-        at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz), at<int>(a, L.perm()), grad,
-        (int)L.N);
+        acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+        src_of(a), at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz), at<int>(a, L.perm()),
+        grad, (int)L.N, a.pull_limit);
 }
 
 hipError_t dev_force(const DevArgs &a, float *acc_out)
@@ -1534,16 +1621,16 @@ __global__ void k_copy_pairs(const uint32_t *hdr, int64_t *out)
     if (threadIdx.x == 0) *out = *(const int64_t *)&hdr[kHdrPairs];
 }
 
-hipError_t dev_count_pairs(const DevArgs &a, int64_t *pairs)
+hipError_t dev_count_pairs(const DevArgs &a, bool adjoint, int64_t *pairs)
 {
     const Layout &L = *a.L;
-    hipError_t e = build_items<true>(a, 0);
+    hipError_t e = adjoint ? build_items<false>(a, 0) : build_items<true>(a, 0);
     if (e != hipSuccess) return e;
     if ((e = fill_u32(at<uint32_t>(a, L.hdr) + kHdrPairs, 2, 0, a.st)) != hipSuccess) return e;
     e = with_acc(a, [&](auto acc) -> hipError_t {
         k_count<<<persistent_grid(a), kWave, 0, a.st>>>(acc, at<int4>(a, L.items),
                                                        at<uint32_t>(a, L.hdr), at<int>(a, L.start),
-                                                       src_of(a));
+                                                       at<int>(a, L.nact), src_of(a), a.pull_limit);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;

@@ -28,8 +28,27 @@ def test_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(_sr.EXPORTS)
-    assert L.sr_abi_version() == 2
+    assert L.sr_abi_version() == 3 == _sr.ABI_VERSION
     assert L.sr_status_str(0) == b"ok"
+
+
+def header_defines(prefix):
+    text = open(HEADER).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(" + prefix + r"\w+)\s+(\d+)u?", text)}
+
+
+def test_flag_and_option_constants_match_the_header():
+    # the binding decodes sr_ws_flags and passes flags with the header's values;
+    # a renumbered bit would silently change their meaning
+    flags = header_defines("SR_FLAG_")
+    assert flags == {"SR_FLAG_NONFINITE": _sr.FLAG_NONFINITE, "SR_FLAG_OUT_OF_DOMAIN": _sr.FLAG_OUT_OF_DOMAIN,
+                     "SR_FLAG_NOT_BINNED": _sr.FLAG_NOT_BINNED, "SR_FLAG_QUEUE": _sr.FLAG_QUEUE}
+    assert len(set(flags.values())) == len(flags) and all(v & (v - 1) == 0 for v in flags.values())
+    opts = header_defines("SR_(?:REUSE|BATCH|COUNT)_")
+    assert opts == {"SR_REUSE_BINS": _sr.REUSE_BINS, "SR_BATCH_PER_SUBVOLUME": _sr.BATCH_PER_SUBVOLUME,
+                    "SR_BATCH_EAGER": _sr.BATCH_EAGER, "SR_BATCH_RECAPTURE": _sr.BATCH_RECAPTURE,
+                    "SR_COUNT_ADJOINT": _sr.COUNT_ADJOINT}
+    assert header_defines("SR_ABI_")["SR_ABI_VERSION"] == _sr.ABI_VERSION
 
 
 def prob(length=32.0, periodic=True, r_s=3.0, eps=0.05, lo=(0, 0, 0)):
@@ -137,7 +156,8 @@ def test_vjp_and_bin_validation():
     assert L.sr_bin(FAKE, FAKE, 100, 101, C.byref(p), FAKE, nb, None) == 1
     assert L.sr_bin(FAKE, FAKE, 100, 100, C.byref(p), FAKE, nb - 256, None) == 2
     assert L.sr_momentum(FAKE, FAKE, -1, FAKE, 4096, FAKE, None) == 1
-    assert L.sr_count_pairs(100, 100, C.byref(p), FAKE, nb, None, None) == 1
+    assert L.sr_count_pairs(100, 100, C.byref(p), FAKE, nb, 0, None, None) == 1
+    assert L.sr_count_pairs(100, 100, C.byref(p), FAKE, nb, 2, FAKE, None) == 1  # unknown flag
 
 
 def test_launch_config_validation():

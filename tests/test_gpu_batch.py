@@ -110,11 +110,25 @@ def test_graph_replays_with_eager_work_between():
         # unrelated eager work on the same workspace in between
         sr.force(pos[:5000], mass[:5000], b.problems[0], ws=ws)
         torch.cuda.synchronize()
-    # new output pointers: the plan captures again
-    acc2 = torch.empty_like(acc)
+    # new output pointers: the captured graph is bound to the old ones, so a
+    # graph run refuses them (SR_E_PLAN, nothing enqueued) unless asked to
+    # capture again
+    acc2 = torch.full_like(acc, float("nan"))
+    with pytest.raises(sr.SRError) as err:
+        plan.run(pos, mass, ws, acc2, mom, "graph")
+    assert err.value.code == 4
+    torch.cuda.synchronize()
+    assert torch.isnan(acc2).all()
+    plan.run(pos, mass, ws, acc2, mom, "graph", recapture=True)
+    torch.cuda.synchronize()
+    assert torch.equal(acc2, ref)
+    # the new graph replays; the old pointers are refused in turn
+    acc2.fill_(float("nan"))
     plan.run(pos, mass, ws, acc2, mom, "graph")
     torch.cuda.synchronize()
     assert torch.equal(acc2, ref)
+    with pytest.raises(sr.SRError):
+        plan.run(pos, mass, ws, acc, mom, "graph")
     plan.close()
 
 
@@ -130,3 +144,15 @@ def test_tune_cache_roundtrip(tmp_path):
     assert np.array_equal(a1.view(np.uint32), a2.view(np.uint32))
     import json
     assert p1.info()["tune_key"] in json.load(open(path))
+
+
+def test_batch_force_rejects_unknown_flags():
+    # host validation before the workspace or any enqueue
+    import ctypes as C
+    b = mixed_batch()
+    plan = sr.BatchPlan(b.offsets, b.n_active, b.problems)
+    L = sr._sr.lib()
+    fake = C.c_void_p(0x10000)
+    assert L.sr_batch_force(plan._plan, fake, fake, fake, plan.ws_bytes, fake, None, 8, None) == 1
+    assert L.sr_batch_force(plan._plan, fake, fake, None, plan.ws_bytes, fake, None, 4, None) == 2
+    plan.close()

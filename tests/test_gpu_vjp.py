@@ -125,3 +125,60 @@ def test_vjp_against_finite_differences():
     err = oracle.rms_rel(got[keep], fd)
     print(f"  fd points={len(keep)} rms_rel={err:.3e}", flush=True)
     assert len(keep) >= 100 and err <= VJP_TOL
+
+
+@pytest.mark.parametrize("eps,masses", [(0.01, "random"), (0.02, "random"), (0.01, "equal")])
+def test_vjp_duplicated_positions_per_particle(eps, masses):
+    # 400 particles placed exactly on others: the target's own entry must add
+    # exactly zero (u is exactly antisymmetric), and a distinct particle at the
+    # same position adds f(0) u, the derivative of its smooth softened force
+    # term.  Checked per particle, not only in RMS: the own entry's rounding
+    # would be amplified by f(0) ~ eps^-3 on every row.
+    rng = np.random.default_rng(14)
+    w = synth.uniform_box(30000, 31.0, 13)
+    dst = rng.choice(w.n, 400, replace=False)
+    src = rng.choice(np.setdiff1d(np.arange(w.n), dst), 400, replace=False)
+    w.pos[dst] = w.pos[src]
+    w.mass = (rng.uniform(0.5, 2.0, w.n) if masses == "random" else np.ones(w.n)).astype(np.float32)
+    w.problem = synth.Problem.make((0, 0, 0), (31.0,) * 3, True, 3.0, eps, synth.filter_poly(3.0, eps))
+    g = synth.cotangent(w.n, 6)
+    announce(f"vjp duplicates eps={eps} masses={masses}")
+    got = gpu_vjp(w, g)
+    ref = oracle.vjp(w.pos, w.mass, w.n, w.problem, g)
+    err = oracle.rms_rel(got, ref)
+    row = np.linalg.norm(got - ref, axis=1)
+    mag = np.linalg.norm(ref, axis=1)
+    med = np.median(mag)
+    worst = np.max(row / (mag + 0.1 * med))
+    print(f"  rms_rel={err:.3e} worst row={worst:.3e} median row rel={np.median(row / mag):.3e}", flush=True)
+    assert err <= VJP_TOL
+    assert worst <= 1e-4
+    # the forward sum is unchanged by the duplicates' zero separation
+    a = sr.force(to_dev(w.pos), to_dev(w.mass), w.problem).cpu().numpy()
+    aref, _ = oracle.force(w.pos, w.mass, w.n, w.problem)
+    assert oracle.rms_rel(a, aref) <= 1e-5
+
+
+def test_adjoint_pair_count_has_an_active_end():
+    # the adjoint evaluates the ordered pairs with at least one active end:
+    # all pairs of the domain minus those between two passive particles (both
+    # counted by the oracle); the forward those with an active target
+    w = synth.slab_with_ghosts(40, 3.0, 300, 2)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    ws = sr.bin(pos, mass, w.problem, w.n_active)
+    fwd = int(sr.count_pairs(ws, w.n, w.problem, w.n_active).item())
+    adj = int(sr.count_pairs(ws, w.n, w.problem, w.n_active, adjoint=True).item())
+    _, ref_fwd = oracle.force(w.pos, w.mass, w.n_active, w.problem)
+    _, ref_all = oracle.force(w.pos, w.mass, w.n, w.problem)
+    npas = w.n - w.n_active
+    _, ref_pp = oracle.force(w.pos[w.n_active:], w.mass[w.n_active:], npas, w.problem)
+    announce(f"pairs forward {fwd} ({ref_fwd}) adjoint {adj} ({ref_all - ref_pp}), passive-passive {ref_pp}")
+    assert ref_pp > 0 and w.n_active < w.n
+    assert abs(fwd - ref_fwd) <= 4
+    assert abs(adj - (ref_all - ref_pp)) <= 4
+    # the adjoint's gradients on the passive rows still match the oracle
+    g = synth.cotangent(w.n_active, 9)
+    got = sr.force_vjp(pos, mass, w.problem, to_dev(g), w.n_active, ws=ws, reuse_bins=True).cpu().numpy()
+    ref = oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g)
+    assert oracle.rms_rel(got[w.n_active:], ref[w.n_active:]) <= VJP_TOL
+    assert oracle.rms_rel(got, ref) <= VJP_TOL

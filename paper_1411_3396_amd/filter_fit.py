@@ -98,7 +98,7 @@ def load(r_s: float, eps: float) -> np.ndarray:
 
 
 def main() -> None:
-    pairs = [(3.0, 0.05), (3.0, 0.02)]
+    pairs = [(3.0, 0.05), (3.0, 0.02), (3.0, 0.01)]
     table = {
         "form": "f_SR(s) = (s+eps^2)^-1.5 - sum_k c[k] s^k, s = r^2, lengths in grid cells",
         "target": "Gaussian force split, long-range kernel, sigma=%g" % SIGMA,

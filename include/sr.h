@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SR_ABI_VERSION 3
+#define SR_ABI_VERSION 4
 
 typedef enum sr_status {
     SR_OK = 0,
@@ -201,6 +201,31 @@ sr_status sr_force(const float *pos, const float *mass, int64_t n, int64_t n_act
 sr_status sr_force_vjp(const float *pos, const float *mass, int64_t n, int64_t n_active,
                        const sr_problem *prob /*host*/, void *ws, size_t ws_bytes, unsigned flags,
                        const float *g, float *grad_pos, void *stream);
+
+/* Size of the fixed device workspace of sr_force_static (64 MiB). */
+#define SR_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* Forward without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Computes what sr_force computes without SR_REUSE_BINS (bin,
+ * then the forward pair kernels; the same kernels, so bitwise the same
+ * accelerations), but its workspace is a fixed device array of
+ * SR_STATIC_WORKSPACE_BYTES inside the library, one per GPU, held until the
+ * process ends.  The caller passes only inputs and outputs: pos [n][3], mass
+ * [n] (device, read only), acc [n_active][3] (device, overwritten).
+ * Returns SR_E_UNSUPPORTED, before touching the device, when the problem
+ * needs a larger workspace than that (sr_workspace_bytes gives the need:
+ * about 80 B per particle plus 12 B per cell); SR_E_DEVICE if the array's
+ * address cannot be looked up; other errors as sr_force.  Never calls
+ * hipMalloc or hipFree.  Every call on one GPU shares that GPU's array and
+ * leaves its contents there (each call re-initialises what it reads), so
+ * calls that overlap on one GPU (two streams or threads at once) race and
+ * give wrong results: serialise them.  Device conditions are flagged inside
+ * the array, which sr_ws_flags cannot reach.  The first call on a device
+ * looks the array's address up (no allocation); make it outside stream
+ * capture. */
+sr_status sr_force_static(const float *pos, const float *mass, int64_t n, int64_t n_active,
+                          const sr_problem *prob /*host*/, float *acc, void *stream);
 
 /* Number of ordered pairs (i active, j) with 0 < s_ij < r_s^2, decided with
  * the same float32 arithmetic as sr_force, written to *pairs (device int64).

@@ -30,7 +30,7 @@ FLAG_QUEUE = 8
 
 # the exported names of sr.h, in declaration order
 EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "sr_bin",
-           "sr_bin_view", "sr_force", "sr_force_vjp", "sr_count_pairs", "sr_momentum",
+           "sr_bin_view", "sr_force", "sr_force_static", "sr_force_vjp", "sr_count_pairs", "sr_momentum",
            "sr_ws_flags", "sr_batch_plan_create", "sr_batch_force", "sr_batch_plan_destroy",
            "sr_batch_plan_info", "sr_blocks_plan_create", "sr_blocks_plan_destroy",
            "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
@@ -76,7 +76,7 @@ class BinLayout(C.Structure):
 
 
 # sr_problem layout and entry points of include/sr.h (SR_ABI_VERSION)
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 _lib = None
 
@@ -97,6 +97,7 @@ def lib():
         L.sr_bin.argtypes = [p, p, i64, i64, p, p, C.c_size_t, p]
         L.sr_bin_view.argtypes = [p, i64, i64, p, p]
         L.sr_force.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p]
+        L.sr_force_static.argtypes = [p, p, i64, i64, p, p, p]
         L.sr_force_vjp.argtypes = [p, p, i64, i64, p, p, C.c_size_t, u, p, p, p]
         L.sr_count_pairs.argtypes = [i64, i64, p, p, C.c_size_t, u, p, p]
         L.sr_momentum.argtypes = [p, p, i64, p, C.c_size_t, p, p]
@@ -257,6 +258,23 @@ def force(pos, mass, prob, n_active=None, ws=None, reuse_bins=False, out=None, s
         out = _out_f32(out, "out", (n_active, 3))
     _check(lib().sr_force(_ptr(pos), _ptr(mass), n, n_active, C.byref(P), _ptr(ws), ws.numel(),
                           REUSE_BINS if reuse_bins else 0, _ptr(out), _stream(stream)), "sr_force")
+    return out
+
+
+def force_static(pos, mass, prob, n_active=None, out=None, stream=None):
+    """sr_force_static: the forward on the library's fixed device workspace (no allocation
+    by the library; `out` may be passed so that nothing is allocated here either)."""
+    n = int(pos.shape[0])
+    n_active = n if n_active is None else int(n_active)
+    pos = _dev_f32(pos, "pos", (n, 3))
+    mass = _dev_f32(mass, "mass", (n,))
+    P = as_problem(prob)
+    if out is None:
+        out = torch.empty((n_active, 3), dtype=torch.float32, device=pos.device)
+    else:
+        out = _out_f32(out, "out", (n_active, 3))
+    _check(lib().sr_force_static(_ptr(pos), _ptr(mass), n, n_active, C.byref(P), _ptr(out), _stream(stream)),
+           "sr_force_static")
     return out
 
 

@@ -12,6 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsr.so")
 SOURCES = [os.path.join(CSRC, "sr_kernels.hip"), os.path.join(CSRC, "sr_blocks.hip"),
            os.path.join(CSRC, "sr_centres.hip"), os.path.join(CSRC, "sr_pk.hip"),
+           os.path.join(CSRC, "sr_static.hip"),
            os.path.join(CSRC, "sr_api.cpp")]
 LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")

@@ -633,6 +633,22 @@ sr_status sr_force(const float *pos, const float *mass, int64_t n, int64_t n_act
     return hip_status(dev_force(a, acc));
 }
 
+sr_status sr_force_static(const float *pos, const float *mass, int64_t n, int64_t n_active,
+                          const sr_problem *prob, float *acc, void *stream)
+{
+    Single s;
+    sr_status st = prepare_single(n, n_active, prob, s);
+    if (st != SR_OK) return st;
+    if (s.L.total > (size_t)SR_STATIC_WORKSPACE_BYTES) return SR_E_UNSUPPORTED;
+    if (n > 0 && (!pos || !mass)) return SR_E_ARG;
+    if (n_active > 0 && !acc) return SR_E_ARG;
+    if (n == 0) return SR_OK;
+    void *ws = nullptr;
+    size_t bytes = 0;
+    if (sr::static_workspace(&ws, &bytes) != hipSuccess) return SR_E_DEVICE;
+    return sr_force(pos, mass, n, n_active, prob, ws, bytes, 0, acc, stream);
+}
+
 sr_status sr_force_vjp(const float *pos, const float *mass, int64_t n, int64_t n_active,
                        const sr_problem *prob, void *ws, size_t ws_bytes, unsigned flags,
                        const float *g, float *grad_pos, void *stream)

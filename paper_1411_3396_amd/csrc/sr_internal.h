@@ -136,6 +136,9 @@ hipError_t dev_scan(const int *in, int *out, int64_t m, int *tmp, hipStream_t st
 hipError_t dev_bounds(const int *sorted_keys, int64_t n, int64_t nk, int key_bits, int *start,
                       hipStream_t st);
 hipError_t dev_momentum(const DevArgs &a, const float *acc, const float *mass, double *out);
+// Device address and size of the fixed workspace of sr_force_static on the
+// current device (looked up on the first call per device).
+hipError_t static_workspace(void **ptr, size_t *bytes);
 
 // Event timing hooks (sr_api.cpp).
 void timing_begin(const char *name, hipStream_t st, void **token);

@@ -28,7 +28,7 @@ def test_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(_sr.EXPORTS)
-    assert L.sr_abi_version() == 3 == _sr.ABI_VERSION
+    assert L.sr_abi_version() == 4 == _sr.ABI_VERSION
     assert L.sr_status_str(0) == b"ok"
 
 
@@ -196,3 +196,26 @@ def test_batch_plan_validation_and_layout():
     bad = (_sr.Problem * 2)(prob(), prob(length=5.0))
     assert L.sr_batch_plan_create(2, ptr(off), ptr(act), bad, None, C.byref(plan), C.byref(nb)) == 1
     assert L.sr_batch_force(None, FAKE, FAKE, FAKE, 1 << 20, FAKE, None, 0, None) == 4
+
+
+def test_static_forward_validation_before_the_device():
+    # the allocation-free forward rejects, on the host, inputs whose workspace
+    # would not fit its fixed array, and bad arguments, without a device call
+    E_ARG, E_UNSUP = 1, 5
+    L = _sr.lib()
+    p = prob()
+    limit = header_defines("SR_STATIC_")  # "((size_t)64 << 20)" is not a plain number
+    assert limit == {}
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+SR_STATIC_WORKSPACE_BYTES\s+\(\(size_t\)(\d+)\s*<<\s*(\d+)\)", text)
+    cap = int(m.group(1)) << int(m.group(2))
+    fits = max(n for n in range(0, 2_000_000, 1000) if _sr.workspace_bytes(n, p) <= cap)
+    assert 100_000 < fits < 2_000_000
+    big = fits + 1000
+    assert _sr.workspace_bytes(big, p) > cap
+    assert L.sr_force_static(FAKE, FAKE, big, big, C.byref(p), FAKE, None) == E_UNSUP
+    assert L.sr_force_static(FAKE, FAKE, 100, 101, C.byref(p), FAKE, None) == E_ARG
+    assert L.sr_force_static(None, FAKE, 100, 100, C.byref(p), FAKE, None) == E_ARG
+    assert L.sr_force_static(FAKE, FAKE, 100, 100, C.byref(p), None, None) == E_ARG
+    assert L.sr_force_static(FAKE, FAKE, 100, 100, None, FAKE, None) == E_ARG
+    assert L.sr_force_static(None, None, 0, 0, C.byref(p), None, None) == 0

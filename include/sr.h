@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SR_ABI_VERSION 4
+#define SR_ABI_VERSION 5
 
 typedef enum sr_status {
     SR_OK = 0,
@@ -446,6 +446,24 @@ sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy
  * "vjp"; cur receives that kernel's values. */
 sr_status sr_launch_config_kernel(const char *kernel /*host*/, int waves_per_cu,
                                   int targets_per_lane, int occupancy, int *cur /*host out*/);
+
+/* Host only.  Tiles of the symmetric pair kernels of one kernel ("force" or
+ * "vjp").  Inside cells with at least 64 active particles (their full
+ * blocks of 64 are the dense particles) each unordered pair of dense
+ * particles is evaluated once and its opposite term kept as well (Newton's
+ * third law on the short-range sum of Sec. 2); the rest is summed from both
+ * ends as before.  blocks_per_item: blocks of 64 targets one work item takes
+ * (1..256; 0 switches the symmetric tiles off; -1 keeps the value); window:
+ * sources per work item, 256 or 512 (-1 keeps).  Larger tiles need fewer
+ * partial slots but make longer items.  The partial slots (12 bytes each)
+ * fill the tail of the workspace: sr_workspace_bytes reserves about 11 per
+ * particle, and a larger workspace passed to sr_force / sr_force_vjp lends
+ * its whole tail to them.  A problem that needs more (very large cells) runs
+ * without symmetric tiles.  Results differ from the one-sided sums only in rounding
+ * order; for fixed tiles they are bitwise reproducible.  cur (nullable)
+ * receives {blocks_per_item, window}. */
+sr_status sr_tile_config(const char *kernel /*host*/, int blocks_per_item, int window,
+                         int *cur /*host out*/);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * launch of the pair kernels ("force", "vjp").  sr_timing_enable(1) clears

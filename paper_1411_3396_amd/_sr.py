@@ -36,7 +36,7 @@ EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "
            "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
            "sr_blocks_reconcile_grad", "sr_centres_plan_create", "sr_centres_plan_destroy",
            "sr_centres", "sr_pk_plan_create", "sr_pk_plan_destroy", "sr_pk_deposit", "sr_pk_grid",
-           "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_timing_enable",
+           "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_tile_config", "sr_timing_enable",
            "sr_timing_read")
 
 
@@ -76,7 +76,7 @@ class BinLayout(C.Structure):
 
 
 # sr_problem layout and entry points of include/sr.h (SR_ABI_VERSION)
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 _lib = None
 
@@ -123,6 +123,7 @@ def lib():
         L.sr_power_spectrum.argtypes = [p, p, p, i64, p, C.c_size_t, p, p, p, p]
         L.sr_launch_config.argtypes = [C.c_int, C.c_int, C.c_int, p]
         L.sr_launch_config_kernel.argtypes = [C.c_char_p, C.c_int, C.c_int, C.c_int, p]
+        L.sr_tile_config.argtypes = [C.c_char_p, C.c_int, C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
         for name in EXPORTS:
@@ -665,6 +666,14 @@ def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: i
         _check(lib().sr_launch_config_kernel(kernel.encode(), int(waves_per_cu), int(targets_per_lane),
                                              int(occupancy), cur), "sr_launch_config_kernel")
     return int(cur[0]), int(cur[1]), int(cur[2])
+
+
+def tile_config(blocks_per_item: int = -1, window: int = -1, kernel: str = "force"):
+    """Set and return (blocks_per_item, window) of the symmetric tiles of one pair kernel
+    ("force" or "vjp"); blocks_per_item 0 switches them off, -1 keeps a value."""
+    cur = (C.c_int * 2)()
+    _check(lib().sr_tile_config(kernel.encode(), int(blocks_per_item), int(window), cur), "sr_tile_config")
+    return int(cur[0]), int(cur[1])
 
 
 def timing_enable(on: bool = True) -> None:

@@ -23,6 +23,7 @@ using namespace sr;
 namespace {
 
 constexpr int64_t kMaxParticles = (int64_t(1) << 31) - 1;
+constexpr int64_t kSymMaxSlots = (int64_t(1) << 31) - 1;  // partial slots are indexed in int32
 constexpr int64_t kMaxCells = int64_t(1) << 26;  // cell << 4 fits the 31-bit sort key at depth 1
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -110,6 +111,26 @@ SegParams seg_of(const sr_problem *p, const int32_t nc[3])
     return s;
 }
 
+// Bytes of a tail holding `cap` partial slots and the items they allow (an
+// item writes at least 64 target slots).
+size_t sym_tail_bytes(int64_t cap)
+{
+    return align256((size_t)(cap / kWave + 1) * 16) + align256((size_t)cap * 12);
+}
+
+// Lays the symmetric items and the pool over the workspace tail from
+// L.sym_items to ws_bytes: the most slots that fit (at most 2^31 - 1).
+void sym_tail(Layout &L, size_t ws_bytes)
+{
+    const size_t tail = ws_bytes > L.sym_items ? ws_bytes - L.sym_items : 0;
+    int64_t cap = (int64_t)std::min<size_t>(tail > 512 ? (tail - 512) / 784 * 64 : 0, (size_t)kSymMaxSlots);
+    while (cap > 0 && sym_tail_bytes(cap) > tail) cap -= 1 + cap / 256;
+    if (cap < 0) cap = 0;
+    L.sym_cap = cap;
+    L.sym_item_cap = cap / kWave + 1;
+    L.sym_pool = L.sym_items + align256((size_t)L.sym_item_cap * 16);
+}
+
 Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_passive, int code_bits)
 {
     Layout L;
@@ -148,7 +169,7 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.tabx = take((size_t)(L.table + 1) * 4);
     L.nact = take((size_t)NC * 4);
     L.start = take((size_t)(NC + 1) * 4);
-    L.scan_tmp = take((size_t)std::max(scan_scratch_elems(L.table), scan_scratch_elems(NC)) * 4);
+    L.scan_tmp = take((size_t)std::max(scan_scratch_elems(L.table), scan_scratch_elems(kSymStride * NC)) * 4);
     L.bx = take(n4);
     L.by = take(n4);
     L.bz = take(n4);
@@ -160,9 +181,21 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.items = take((size_t)L.item_cap * 16);
     L.info = take((size_t)NC * 4);
     L.mom = take((size_t)(3 * mom_tiles + 3) * 8);
-    L.total = o;
+    // symmetric tiles: per cell and direction the partial-slot counts and their
+    // exclusive scan, per cell the item count and cost class, the items, and
+    // the pool of 12-byte partial slots (at most 2^31 - 1 of them)
+    L.sym_cnt = take((size_t)kSymStride * NC * 4);
+    L.sym_base = take(((size_t)kSymStride * NC + 1) * 4);
+    L.sym_info = take((size_t)NC * 4);
+    // the tail: symmetric items and the pool, sized for the default number of
+    // slots per particle; a larger workspace lends the tail more (sym_tail)
+    const int64_t cap = std::min<int64_t>((int64_t)kSymSlotsPerParticle * N, kSymMaxSlots);
+    L.sym_items = o;
+    L.total = o + sym_tail_bytes(cap);
+    sym_tail(L, L.total);
     return L;
 }
+
 
 int64_t mom_tiles_of(int64_t rows) { return (rows + kMomTile - 1) / kMomTile; }
 
@@ -203,6 +236,10 @@ constexpr int kCfgForce = 0, kCfgVjp = 1;
 std::atomic<int> g_waves_default[2] = {{32}, {24}};
 std::atomic<int> g_tpl_default[2] = {{1}, {2}};
 std::atomic<int> g_occ_default[2] = {{6}, {0}};
+// Symmetric tiles of the dense cells, per kernel: blocks of 64 targets per
+// item (0: off) and sources per window (256 or 512).
+std::atomic<int> g_sym_blocks[2] = {{16}, {16}};
+std::atomic<int> g_sym_window[2] = {{512}, {256}};
 
 // Launch defaults may be overridden for experiments (both kernels):
 // SR_WAVES_PER_CU, SR_TARGETS_PER_LANE, SR_OCCUPANCY.
@@ -221,6 +258,14 @@ struct EnvDefaults {
             if (const char *v = std::getenv("SR_OCCUPANCY")) {
                 const int o = std::atoi(v);
                 if (o == 0 || o == 6 || o == 8) g_occ_default[k] = o;
+            }
+            if (const char *v = std::getenv("SR_SYM_BLOCKS")) {
+                const int b = std::atoi(v);
+                if (b >= 0 && b <= 256) g_sym_blocks[k] = b;
+            }
+            if (const char *v = std::getenv("SR_SYM_WINDOW")) {
+                const int w = std::atoi(v);
+                if (w == 256 || w == 512) g_sym_window[k] = w;
             }
         }
     }
@@ -268,6 +313,8 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.n_rows = (int)n_rows;
     a.targets_per_lane = g_tpl_default[cfg].load();
     a.occupancy = g_occ_default[cfg].load();
+    a.sym_blocks = g_sym_blocks[cfg].load();
+    a.sym_window = g_sym_window[cfg].load();
     a.pull_limit = pull_limit();
     return SR_OK;
 }
@@ -626,6 +673,7 @@ sr_status sr_force(const float *pos, const float *mass, int64_t n, int64_t n_act
     if (n_active > 0 && !acc) return SR_E_ARG;
     if ((st = check_ws(ws, ws_bytes, s.L)) != SR_OK) return st;
     if (n == 0) return SR_OK;
+    sym_tail(s.L, ws_bytes);  // the whole tail of the caller's workspace holds partial slots
     DevArgs a;
     if ((st = device_args(a, ws, &s.L, &s.seg, nullptr, stream, 0, n_active)) != SR_OK) return st;
     if (!(flags & SR_REUSE_BINS) && dev_bin(a, pos, mass) != hipSuccess) return SR_E_DEVICE;
@@ -661,6 +709,7 @@ sr_status sr_force_vjp(const float *pos, const float *mass, int64_t n, int64_t n
     if (n_active > 0 && !g) return SR_E_ARG;
     if ((st = check_ws(ws, ws_bytes, s.L)) != SR_OK) return st;
     if (n == 0) return SR_OK;
+    sym_tail(s.L, ws_bytes);
     DevArgs a;
     if ((st = device_args(a, ws, &s.L, &s.seg, nullptr, stream, 0, n_active, kCfgVjp)) != SR_OK) return st;
     if (!(flags & SR_REUSE_BINS) && dev_bin(a, pos, mass) != hipSuccess) return SR_E_DEVICE;
@@ -913,6 +962,24 @@ sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy
     if (st != SR_OK) return st;
     (void)set_config(kCfgVjp, waves_per_cu, targets_per_lane, occupancy);
     get_config(kCfgForce, cur);
+    return SR_OK;
+}
+
+sr_status sr_tile_config(const char *kernel, int blocks_per_item, int window, int *cur)
+{
+    if (!kernel) return SR_E_ARG;
+    int k = -1;
+    if (std::strcmp(kernel, "force") == 0) k = kCfgForce;
+    if (std::strcmp(kernel, "vjp") == 0) k = kCfgVjp;
+    if (k < 0) return SR_E_ARG;
+    if (blocks_per_item < -1 || blocks_per_item > 256) return SR_E_ARG;
+    if (window != -1 && window != 256 && window != 512) return SR_E_ARG;
+    if (blocks_per_item >= 0) g_sym_blocks[k] = blocks_per_item;
+    if (window > 0) g_sym_window[k] = window;
+    if (cur) {
+        cur[0] = g_sym_blocks[k].load();
+        cur[1] = g_sym_window[k].load();
+    }
     return SR_OK;
 }
 

@@ -66,8 +66,22 @@ enum HdrWord : int {
     kHdrBucketCursor = 192, // [32]
     kHdrQueue = 256,        // queue q at kHdrQueue + 32*q (separate 128-byte lines)
     kHdrPairs = 512,        // int64 pair counter (2 words)
+    kHdrSymTotal = 516,     // int64 partial slots the symmetric tiles need (2 words)
+    kHdrSymOk = 518,        // 1: symmetric tiles run (their partial slots fit the pool)
+    kHdrSymNItems = 519,    // symmetric work items
+    kHdrSymBucketCount = 544,   // [32]
+    kHdrSymBucketBase = 576,    // [33]
+    kHdrSymBucketCursor = 640,  // [32]
+    kHdrSymQueue = 768,     // symmetric queue q at kHdrSymQueue + 32*q
     kHdrWords = 1024
 };
+
+// Symmetric (Newton's third law) tiles of the dense cells: every unordered
+// pair of two dense particles is evaluated once, its two opposite terms kept
+// as partial sums in fixed slots and added up in a fixed order afterwards.
+constexpr int kSymDirs = 14;        // the cell itself and the 13 directions of the upper half stencil
+constexpr int kSymStride = 15;      // per cell: target slots, then source slots of the 14 directions
+constexpr int kSymSlotsPerParticle = 12;  // partial-slot pool: this many 12-byte slots per particle
 
 // Byte offsets of every buffer inside a workspace.
 struct Layout {
@@ -85,6 +99,9 @@ struct Layout {
     size_t tab = 0, tabx = 0, nact = 0, start = 0, scan_tmp = 0;
     size_t bx = 0, by = 0, bz = 0, bm = 0, out_row = 0, gx = 0, gy = 0, gz = 0;
     size_t items = 0, info = 0, mom = 0;
+    int64_t sym_cap = 0;    // partial slots of the pool
+    int64_t sym_item_cap = 0;
+    size_t sym_cnt = 0, sym_base = 0, sym_info = 0, sym_items = 0, sym_pool = 0;
     size_t total = 0;
     size_t perm() const { return vals[(passes - 1) & 1]; }
     size_t sorted_keys() const { return keys[(passes - 1) & 1]; }
@@ -113,6 +130,8 @@ struct DevArgs {
     int n_rows;  // rows of the force output (sum of n_active)
     int targets_per_lane;  // 1 or 2 for cells with more than 64 targets
     int occupancy;         // register-allocation hint of the pair kernels: 0, 6 or 8 waves/SIMD
+    int sym_blocks;        // symmetric tiles: blocks of 64 targets per item (0: symmetric tiles off)
+    int sym_window;        // symmetric tiles: sources per item window (256 or 512)
     int64_t pull_limit;    // most items one wave of a persistent kernel may pull (test hook)
 };
 

@@ -515,22 +515,31 @@ __device__ __forceinline__ int cell_items(int nt, bool two)
 }
 
 // Work item: x = home cell, y = first target slot, z = targets,
-// w = lk | two << 3 | psrc << 4 | seg << 5 (lk: log2 lanes per target; two:
-// two targets per lane; psrc: the targets are passive and their sources are
-// the active particles of the 27 cells only; seg: the problem of a batch).
-__device__ __forceinline__ int item_word(int lk, int two, int psrc, int seg)
+// w = lk | two << 3 | psrc << 4 | nd << 5 | seg << 6 (lk: log2 lanes per
+// target; two: two targets per lane; psrc: the targets are passive and their
+// sources are the active particles of the 27 cells only; nd: the targets are
+// dense and their sources here are only the non-dense particles of the 27
+// cells, the dense ones being summed by the symmetric tiles; seg: the problem
+// of a batch).
+__device__ __forceinline__ int item_word(int lk, int two, int psrc, int seg, int nd = 0)
 {
-    return lk | (two << 3) | (psrc << 4) | (seg << 5);
+    return lk | (two << 3) | (psrc << 4) | (nd << 5) | (seg << 6);
 }
 __device__ __forceinline__ int item_lk(int w) { return w & 7; }
 __device__ __forceinline__ bool item_two(int w) { return (w >> 3) & 1; }
 __device__ __forceinline__ bool item_psrc(int w) { return (w >> 4) & 1; }
-__device__ __forceinline__ int item_seg(int w) { return w >> 5; }
+__device__ __forceinline__ bool item_nd(int w) { return (w >> 5) & 1; }
+__device__ __forceinline__ int item_seg(int w) { return w >> 6; }
+
+// Dense part of a cell with na active particles: its full blocks of 64 (the
+// leading active particles), none when it has fewer than 64.  Dense blocks
+// are the targets of the symmetric tiles.
+__device__ __forceinline__ int dense_count(int na) { return na >= kWave ? (na & ~(kWave - 1)) : 0; }
 
 // Items of a run of nt consecutive targets from slot s0 (the cut described
 // above); returns the number written, cell_items(nt, two).
 __device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, int c, int s0, int nt,
-                                         bool two, int seg, int psrc)
+                                         bool two, int seg, int psrc, int nd = 0)
 {
     if (nt <= 0) return 0;
     int k = 0;
@@ -544,7 +553,7 @@ __device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, 
     const int r = nt % kTargetsPerItem, dense_end = nt - r;
     for (int t0 = 0; t0 < dense_end; ++k) {
         const int cn = (two && dense_end - t0 >= 2 * kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
-        items[at + k] = make_int4(c, s0 + t0, cn, item_word(0, cn > kTargetsPerItem ? 1 : 0, psrc, seg));
+        items[at + k] = make_int4(c, s0 + t0, cn, item_word(0, cn > kTargetsPerItem ? 1 : 0, psrc, seg, nd));
         t0 += cn;
     }
     for (int t = dense_end; t < nt; t += kSparseGroup, ++k) {
@@ -575,7 +584,7 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
                                                  const int *__restrict__ start,
                                                  const int *__restrict__ nact,
                                                  uint32_t *__restrict__ info, uint32_t *blk,
-                                                 bool ok, int N, bool two)
+                                                 bool ok, int N, bool two, bool sym)
 {
     if (c >= NC) return;
     if (!ok) {
@@ -591,7 +600,7 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
     const SegParams &S = acc.get(acc.seg_of_cell(c));
     int ix, iy, iz;
     decode_cell(S, c, ix, iy, iz);
-    int64_t src = 0, src_act = 0;
+    int64_t src = 0, src_act = 0, src_nd = 0;
     for (int dx = -1; dx <= 1; ++dx) {
         int jx = ix + dx;
         if (jx < 0 || jx >= S.nc[0]) {
@@ -613,12 +622,17 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
                 const int cc = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
                 src += start[cc + 1] - start[cc];
                 if (np > 0) src_act += nact[cc];
+                if (sym) src_nd += start[cc + 1] - start[cc] - dense_count(nact[cc]);
             }
         }
     }
     // cost class from the cell's widest item: a group of min(nt, kSparseGroup) targets when sparse
     const int n_items = cell_items(na, two) + cell_items(np, two);
-    int64_t cost = max(run_cost(na, src, two), run_cost(np, src_act, two));
+    // with symmetric tiles a dense block's own item sees only the non-dense sources
+    const int dn = sym ? dense_count(na) : 0;
+    int64_t cost = dn > 0 ? max(run_cost(dn, src_nd, two), run_cost(na - dn, src, two))
+                          : run_cost(na, src, two);
+    cost = max(cost, run_cost(np, src_act, two));
     if (cost < 1) cost = 1;
     int cls = 63 - __clzll((unsigned long long)cost);
     cls = cls > 31 ? 31 : cls;
@@ -639,7 +653,8 @@ __global__ __launch_bounds__(256) void k_items_count(Acc acc, int NC, const int 
     const bool ok = hdr[kHdrMagic] == magic;
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (!ok && c == 0) atomicOr(&hdr[kHdrFlags], (uint32_t)SR_FLAG_NOT_BINNED);
-    items_count_cell<Acc, kActiveOnly>(acc, c, NC, start, nact, info, blk, ok, N, two != 0);
+    items_count_cell<Acc, kActiveOnly>(acc, c, NC, start, nact, info, blk, ok, N, two != 0,
+                                       hdr[kHdrSymOk] != 0);
     __syncthreads();
     if (threadIdx.x < kClasses && blk[threadIdx.x])
         atomicAdd(&hdr[kHdrBucketCount + threadIdx.x], blk[threadIdx.x]);
@@ -689,7 +704,7 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
     const uint32_t at = base[cls] + local;
     const int s0 = start[c];
     // active targets (all sources), then for the adjoint the passive ones (active sources)
-    const int k = write_run(items, at, c, s0, na, two, seg, 0);
+    const int k = write_run(items, at, c, s0, na, two, seg, 0, hdr[kHdrSymOk] != 0 && dense_count(na) > 0);
     if (!kActiveOnly) write_run(items, at + k, c, s0 + na, nt - na, two, seg, 1);
 }
 
@@ -705,10 +720,12 @@ struct Stencil {
 
 // With act_only each cell contributes only its active particles (they lead
 // the cell): the sources of an item of passive targets.
+// With nd each cell contributes only its non-dense particles (those after its
+// dense blocks): the one-sided sources of a dense block.
 __device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
                                               const int *__restrict__ start,
                                               const int *__restrict__ nact, bool act_only, int lane,
-                                              Stencil &st)
+                                              Stencil &st, bool nd = false)
 {
     int ix, iy, iz;
     decode_cell(S, cell, ix, iy, iz);
@@ -724,7 +741,12 @@ __device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
         if (ok) {
             const int c = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
             st.nstart = start[c];
-            cnt = act_only ? nact[c] : start[c + 1] - st.nstart;
+            if (nd) {
+                st.nstart += dense_count(nact[c]);
+                cnt = start[c + 1] - st.nstart;
+            } else {
+                cnt = act_only ? nact[c] : start[c + 1] - st.nstart;
+            }
         }
     }
     int incl = cnt;
@@ -781,10 +803,10 @@ __device__ __forceinline__ float4 fetch_pos(const Stencil &st, int v, const Src 
 // The persistent loops that call this end their bodies without a lane-0-only
 // branch: otherwise the compiler may merge that branch with this one across
 // the back edge and let the other lanes start the next item without lane 0.
-__device__ __forceinline__ int64_t next_item(uint32_t *hdr, int q, int lane)
+__device__ __forceinline__ int64_t next_item(uint32_t *hdr, int q, int lane, int qbase = kHdrQueue)
 {
     uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(&hdr[kHdrQueue + 32 * q], 1u);
+    if (lane == 0) c = atomicAdd(&hdr[qbase + 32 * q], 1u);
     c = __builtin_amdgcn_readfirstlane(c);
     return ((int64_t)(c / kQueueBlock) * kQueues + q) * kQueueBlock + (c % kQueueBlock);
 }
@@ -1031,6 +1053,7 @@ __device__ __forceinline__ void store3(float *__restrict__ out, int n_out, int r
 template <class Acc, bool kSoft, bool kUM>
 __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restrict__ items,
                                             uint32_t *hdr, const int *__restrict__ start,
+                                            const int *__restrict__ nact,
                                             const Src &src, const int *__restrict__ out_row,
                                             float *__restrict__ out, int n_out, float4 *stage,
                                             int64_t pull_limit)
@@ -1054,7 +1077,7 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
 #pragma unroll
             for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
             Stencil st;
-            stencil_setup(S, it.x, start, start, false, lane, st);
+            stencil_setup(S, it.x, start, nact, false, lane, st, item_nd(it.w));
             auto fetch_p = [&](int v, float4 &c0, float4 &) { c0 = fetch_pos(st, v, src); };
             if (item_two(it.w)) {
                 const bool va = lane < nt, vb = kWave + lane < nt;
@@ -1127,14 +1150,15 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
 
 template <class Acc, bool kSoft, int kOcc>
 __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force(
-    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start, Src src,
-    const int *__restrict__ out_row, float *__restrict__ out, int n_out, int64_t pull_limit)
+    Acc acc, const int4 *__restrict__ items, uint32_t *hdr, const int *__restrict__ start,
+    const int *__restrict__ nact, Src src, const int *__restrict__ out_row, float *__restrict__ out,
+    int n_out, int64_t pull_limit)
 {
     __shared__ float4 stage[kStageForce + kWave];
     if (hdr[kHdrMassInfo] == 0)
-        force_items<Acc, kSoft, true>(acc, items, hdr, start, src, out_row, out, n_out, stage, pull_limit);
+        force_items<Acc, kSoft, true>(acc, items, hdr, start, nact, src, out_row, out, n_out, stage, pull_limit);
     else
-        force_items<Acc, kSoft, false>(acc, items, hdr, start, src, out_row, out, n_out, stage, pull_limit);
+        force_items<Acc, kSoft, false>(acc, items, hdr, start, nact, src, out_row, out, n_out, stage, pull_limit);
 }
 
 // ------------------------------------------------------------- adjoint kernel
@@ -1174,7 +1198,7 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
 #pragma unroll
             for (int k = 0; k < 5; ++k) cd[k] = S.pc.dq[k];
             Stencil st;
-            stencil_setup(S, it.x, start, nact, item_psrc(it.w), lane, st);
+            stencil_setup(S, it.x, start, nact, item_psrc(it.w), lane, st, item_nd(it.w));
             auto fetch_pg = [&](int v, float4 &c0, float4 &c1) {
                 fetch_vjp(st, v, src, gx, gy, gz, c0, c1);
             };
@@ -1336,6 +1360,706 @@ __global__ __launch_bounds__(64) void k_count(Acc acc, const int4 *__restrict__ 
         atomicAdd((unsigned long long *)&hdr[kHdrPairs], pairs);
 }
 
+// --------------------------------------------------------------- symmetric tiles
+//
+// Newton's third law halves the pair work between dense particles (the full
+// blocks of 64 active particles of a cell, dense_count).  The dense particles
+// of a home cell A meet those of A itself and of the 13 cells of the upper
+// half of its stencil (first nonzero offset positive): every unordered pair of
+// dense particles within reach lies in exactly one such meeting, since a cell
+// pair {A, B} is in the upper half of A or of B, never both (at least three
+// cells per dimension).  The dense particles of these 14 cells, concatenated
+// in a fixed order, are A's virtual source list, cut into windows of W
+// sources; A's dense blocks are taken K at a time (a run).  A work item
+// (A, run g, window k) sums, for every block of the run, the block's targets
+// against the window's sources (culled by the block's box) and the opposite
+// terms onto those sources.  Inside the cell only pairs with the source after
+// the target count (the block itself as a triangle).  Both sums go to fixed
+// partial slots of a pool:
+//   target slots  for cell A, window k and dense particle i of A;
+//   source slots  for cell B, direction e, run g of the cell A = B - dir_e and
+//                 dense particle j of B.
+// Every slot has exactly one writer.  k_sym_gather then adds the slots of each
+// dense particle in a fixed order to what its one-sided item (non-dense
+// sources only) wrote.  Each pair term equals, bit for bit, the one the
+// one-sided kernels evaluate from either end (subtraction and the products of
+// u are antisymmetric in float32); only the order of the sums differs.
+//
+// A tile pairs 64 targets (one per lane) with 64 staged sources: at step s
+// lane l takes source (l + s) mod 64, and the lane's running sum for that
+// source moves one lane down after the step (a rotation of the wave), so
+// after all 64 steps lane l holds the opposite sum of source l.  No cross-lane
+// reduction is needed per source.
+
+// Direction e of the symmetric stencil: 0 is the cell itself, 1..13 the upper
+// half (dx = 1: 9 directions; dx = 0, dy = 1: 3; dx = dy = 0, dz = 1: 1).
+__device__ __forceinline__ void half_dir(int e, int &dx, int &dy, int &dz)
+{
+    const int q = e - 1;
+    dx = e == 0 ? 0 : (q < 9 ? 1 : 0);
+    dy = e == 0 ? 0 : (q < 9 ? q / 3 - 1 : (q < 12 ? 1 : 0));
+    dz = e == 0 ? 0 : (q < 9 ? q % 3 - 1 : (q < 12 ? q - 10 : 1));
+}
+
+// Cell at offset (dx, dy, dz) from cell (ix, iy, iz) of a problem and the
+// shift of its centre (image) from the home centre; false outside an open domain.
+__device__ __forceinline__ bool cell_at(const SegParams &S, int ix, int iy, int iz, int dx, int dy,
+                                        int dz, int &cell, float &sx, float &sy, float &sz)
+{
+    int jx, jy, jz;
+    if (!neighbour(ix, dx, S.nc[0], S.lo[0], S.h[0], S.len[0], S.periodic, jx, sx)) return false;
+    if (!neighbour(iy, dy, S.nc[1], S.lo[1], S.h[1], S.len[1], S.periodic, jy, sy)) return false;
+    if (!neighbour(iz, dz, S.nc[2], S.lo[2], S.h[2], S.len[2], S.periodic, jz, sz)) return false;
+    cell = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
+    return true;
+}
+
+// Per cell c: partial-slot counts in cnt[15 c .. 15 c + 14] (target slots:
+// windows of c times its dense particles; source slots of direction e: runs
+// of the cell c - dir_e times the dense particles of c), its items as a home
+// cell (runs times windows) and their cost class in info[c], and the slot
+// total of all cells (int64, header).
+template <class Acc>
+__global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *__restrict__ nact,
+                                                   int K, int W, int *__restrict__ cnt,
+                                                   uint32_t *__restrict__ info, uint32_t *hdr,
+                                                   uint32_t magic)
+{
+    __shared__ uint32_t blk[kClasses];
+    __shared__ unsigned long long tot;
+    if (threadIdx.x < kClasses) blk[threadIdx.x] = 0;
+    if (threadIdx.x == 0) tot = 0;
+    __syncthreads();
+    const bool ok = hdr[kHdrMagic] == magic;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < NC) {
+        const int D = ok ? dense_count(nact[c]) : 0;
+        int *row = cnt + (int64_t)kSymStride * c;
+        uint32_t inf = 0;
+        unsigned long long slots = 0;
+        if (D > 0) {
+            const SegParams &S = acc.get(acc.seg_of_cell(c));
+            int ix, iy, iz;
+            decode_cell(S, c, ix, iy, iz);
+            int64_t sv = 0;
+            for (int e = 0; e < kSymDirs; ++e) {
+                int dx, dy, dz, b;
+                float sx, sy, sz;
+                half_dir(e, dx, dy, dz);
+                if (cell_at(S, ix, iy, iz, dx, dy, dz, b, sx, sy, sz)) sv += dense_count(nact[b]);
+                int64_t sc = 0;
+                if (cell_at(S, ix, iy, iz, -dx, -dy, -dz, b, sx, sy, sz)) {
+                    const int nba = dense_count(nact[b]) / kWave;
+                    sc = (int64_t)((nba + K - 1) / K) * D;
+                }
+                row[1 + e] = (int)min(sc, (int64_t)INT32_MAX);
+                slots += (unsigned long long)sc;
+            }
+            const int nb = D / kWave;
+            const int64_t C = (sv + W - 1) / W;
+            const int64_t G = (nb + K - 1) / K;
+            row[0] = (int)min(C * D, (int64_t)INT32_MAX);
+            slots += (unsigned long long)(C * D);
+            const int64_t n_items = G * C;
+            // tile steps of the widest item: its blocks times its window
+            int64_t cost = (int64_t)min(nb, K) * min((int64_t)W, sv);
+            if (cost < 1) cost = 1;
+            int cls = 63 - __clzll((unsigned long long)cost);
+            cls = cls > 31 ? 31 : cls;
+            if (n_items < (int64_t(1) << 27)) {
+                inf = ((uint32_t)n_items << 5) | (uint32_t)cls;
+                atomicAdd(&blk[cls], (uint32_t)n_items);
+            } else {
+                slots = ~0ull >> 2;  // beyond any pool: the symmetric tiles stay off
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kSymStride; ++e) row[e] = 0;
+        }
+        info[c] = inf;
+        if (slots) atomicAdd(&tot, slots);
+    }
+    __syncthreads();
+    if (threadIdx.x < kClasses && blk[threadIdx.x])
+        atomicAdd(&hdr[kHdrSymBucketCount + threadIdx.x], blk[threadIdx.x]);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&hdr[kHdrSymTotal], tot);
+}
+
+// Class bases of the symmetric items, heaviest first; the tiles run only when
+// enabled, on bins of these sizes, and when every partial slot fits the pool.
+__global__ void k_sym_base(uint32_t *hdr, uint32_t magic, long long cap, int enabled)
+{
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int cls = kClasses - 1; cls >= 0; --cls) {
+            hdr[kHdrSymBucketBase + cls] = run;
+            run += hdr[kHdrSymBucketCount + cls];
+        }
+        const unsigned long long tot = *(const unsigned long long *)&hdr[kHdrSymTotal];
+        const bool ok = enabled && hdr[kHdrMagic] == magic && run > 0 && tot <= (unsigned long long)cap;
+        hdr[kHdrSymOk] = ok ? 1u : 0u;
+        hdr[kHdrSymNItems] = ok ? run : 0u;
+    }
+    if (threadIdx.x < kClasses) hdr[kHdrSymBucketCursor + threadIdx.x] = 0;
+    if (threadIdx.x < kQueues) hdr[kHdrSymQueue + 32 * threadIdx.x] = 0;
+}
+
+// Symmetric items (A, run, window, problem), in cost-class order.
+template <class Acc>
+__global__ __launch_bounds__(256) void k_sym_write(Acc acc, int NC, const int *__restrict__ nact,
+                                                   int K, const uint32_t *__restrict__ info,
+                                                   uint32_t *hdr, int4 *__restrict__ items)
+{
+    __shared__ uint32_t cnt[kClasses];
+    __shared__ uint32_t base[kClasses];
+    if (hdr[kHdrSymOk] == 0) return;  // uniform over the block
+    if (threadIdx.x < kClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t inf = c < NC ? info[c] : 0u;
+    const int n_items = (int)(inf >> 5);
+    const int cls = (int)(inf & 31);
+    uint32_t local = 0;
+    if (inf) local = atomicAdd(&cnt[cls], (uint32_t)n_items);
+    __syncthreads();
+    if (threadIdx.x < kClasses && cnt[threadIdx.x])
+        base[threadIdx.x] = hdr[kHdrSymBucketBase + threadIdx.x] +
+                            atomicAdd(&hdr[kHdrSymBucketCursor + threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (!inf) return;
+    const int nb = dense_count(nact[c]) / kWave;
+    const int G = (nb + K - 1) / K;
+    const int C = n_items / G;
+    const int seg = acc.seg_of_cell(c);
+    const uint32_t at = base[cls] + local;
+    for (int g = 0; g < G; ++g)
+        for (int k = 0; k < C; ++k) items[at + (uint32_t)(g * C + k)] = make_int4(c, g, k, seg);
+}
+
+// The 14 source segments of a symmetric item, one per lane (lanes 0..13):
+// first binned slot and dense count of the cell in direction e, prefix of the
+// counts, centre shift, and the base of its source slots for direction e.
+struct SymStencil {
+    int nstart, cnt, excl, sbase;
+    float sx, sy, sz;
+    int total;
+};
+
+__device__ __forceinline__ void sym_stencil_setup(const SegParams &S, int cell,
+                                                  const int *__restrict__ start,
+                                                  const int *__restrict__ nact,
+                                                  const int *__restrict__ sym_base, int lane,
+                                                  SymStencil &st)
+{
+    int ix, iy, iz;
+    decode_cell(S, cell, ix, iy, iz);
+    st.nstart = 0;
+    st.cnt = 0;
+    st.sbase = 0;
+    st.sx = st.sy = st.sz = 0.f;
+    if (lane < kSymDirs) {
+        int dx, dy, dz, b;
+        half_dir(lane, dx, dy, dz);
+        if (cell_at(S, ix, iy, iz, dx, dy, dz, b, st.sx, st.sy, st.sz)) {
+            st.nstart = start[b];
+            st.cnt = dense_count(nact[b]);
+            st.sbase = sym_base[(int64_t)kSymStride * b + 1 + lane];
+        }
+    }
+    int incl = st.cnt;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    st.excl = incl - st.cnt;
+    st.total = __builtin_amdgcn_readfirstlane(__shfl(incl, kSymDirs - 1));
+}
+
+// Segment of virtual source v (clamped to the list); every lane must call it.
+__device__ __forceinline__ int sym_locate(const SymStencil &st, int v)
+{
+    const int vv = min(v, st.total - 1);
+    int q = 0;
+#pragma unroll
+    for (int step = 8; step >= 1; step >>= 1) {
+        const int cand = q + step;
+        const int e = __shfl(st.excl, min(cand, kSymDirs - 1));
+        if (cand < kSymDirs && e <= vv) q = cand;
+    }
+    return q;
+}
+
+// Position (shifted into the home frame) and mass of virtual source v;
+// padding (v >= end) is far away with zero mass.
+__device__ __forceinline__ float4 sym_fetch_pos(const SymStencil &st, int v, int end, const Src &s,
+                                                int &slot)
+{
+    const int q = sym_locate(st, v);
+    const int j = __shfl(st.nstart, q) + (min(v, st.total - 1) - __shfl(st.excl, q));
+    float4 r = make_float4(s.x[j] + __shfl(st.sx, q), s.y[j] + __shfl(st.sy, q),
+                           s.z[j] + __shfl(st.sz, q), s.m[j]);
+    slot = j;
+    if (v >= end) r = make_float4(kFar, kFar, kFar, 0.f);
+    return r;
+}
+
+// Lane l takes lane l + 1's value (mod 64): the rotation of a tile step.
+__device__ __forceinline__ float rotate_down(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xf, 0xf,
+                                                              false));
+}
+
+// One forward step: target (px, py, pz, mi) gets m_j d f, the source's running
+// sum gets -m_i d f (t = s + eps^2 < tc2).  With kUM both masses are applied
+// once, by the gather.
+template <bool kSoft, bool kUM>
+__device__ __forceinline__ void sym_force_step(const float4 s, float px, float py, float pz, float mi,
+                                               float eps2, float tc2, const float *cq, float &ax,
+                                               float &ay, float &az, float &bx, float &by, float &bz)
+{
+    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    const float qi = __builtin_amdgcn_rsqf(tt);
+    const float q2 = qi * qi;
+    const float f = fmaf(q2, qi, -horner5(cq, tt));
+    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
+    const float fm = in ? f : 0.f;
+    const float wt = kUM ? fm : s.w * fm;
+    const float ws = kUM ? fm : mi * fm;
+    ax = fmaf(wt, dx, ax);
+    ay = fmaf(wt, dy, ay);
+    az = fmaf(wt, dz, az);
+    bx = fmaf(-ws, dx, bx);
+    by = fmaf(-ws, dy, by);
+    bz = fmaf(-ws, dz, bz);
+}
+
+// One adjoint step: the target gets T = f u + 2 f' (u.d) d, the source -T
+// (u = m_k g_j - m_j g_k, d = x_j - x_k; with kUM, u / m).
+template <bool kSoft, bool kUM>
+__device__ __forceinline__ void sym_vjp_step(const float4 s, const float4 gj, float px, float py,
+                                             float pz, float mk, float gkx, float gky, float gkz,
+                                             float eps2, float tc2, const float *cq, const float *cd,
+                                             float &rx, float &ry, float &rz, float &bx, float &by,
+                                             float &bz)
+{
+#pragma clang fp contract(off)
+    const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+    const float tt = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    const float qi = __builtin_amdgcn_rsqf(tt);
+    const float q2 = qi * qi;
+    const float q3 = q2 * qi;
+    const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
+    const float f = in ? q3 - horner5(cq, tt) : 0.f;
+    const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
+    const float ux = kUM ? gj.x - gkx : mk * gj.x - s.w * gkx;
+    const float uy = kUM ? gj.y - gky : mk * gj.y - s.w * gky;
+    const float uz = kUM ? gj.z - gkz : mk * gj.z - s.w * gkz;
+    const float c = fp2 * fmaf(ux, dx, fmaf(uy, dy, uz * dz));
+    const float tx = fmaf(c, dx, f * ux);
+    const float ty = fmaf(c, dy, f * uy);
+    const float tz = fmaf(c, dz, f * uz);
+    rx += tx;
+    ry += ty;
+    rz += tz;
+    bx -= tx;
+    by -= ty;
+    bz -= tz;
+}
+
+// Window partial sums of the sources (opposite terms), one float per source
+// and axis, in LDS.
+template <int kW>
+struct SymRed {
+    float x[kW], y[kW], z[kW];
+};
+
+// Stream the window's sources [vs, w1) through the culling test against the
+// block's box, collect survivors (with their window index) in `coll`, and run
+// `tile(my)` on every 64 of them: the tile reads tile0 (and tile1), filled
+// here with the 64 survivors stored twice, and my is this lane's survivor's
+// window index (-1 for padding).  Every lane must call this.
+template <int kParts, class Fetch, class Tile>
+__device__ __forceinline__ void sym_stream(int vs, int w1, int w0, const Box &box, float cull2, int lane,
+                                           float4 *coll0, float4 *coll1, int *cix, float4 *tile0,
+                                           float4 *tile1, Fetch &&fetch, Tile &&tile)
+{
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int fill = 0;
+    auto run = [&](int n) {
+        // n <= 64 collected; pad the rest of the tile
+        __syncthreads();
+        float4 a0 = coll0[lane], a1 = kParts == 2 ? coll1[lane] : a0;
+        int my = cix[lane];
+        if (lane >= n) {
+            a0 = make_float4(kFar, kFar, kFar, 0.f);
+            a1 = make_float4(0.f, 0.f, 0.f, 0.f);
+            my = -1;
+        }
+        tile0[lane] = a0;
+        tile0[lane + kWave] = a0;
+        if (kParts == 2) {
+            tile1[lane] = a1;
+            tile1[lane + kWave] = a1;
+        }
+        // the survivors beyond the first 64 move to the front
+        const int rest = fill - n;
+        float4 m0, m1;
+        int mi = -1;
+        if (lane < rest) {
+            m0 = coll0[kWave + lane];
+            if (kParts == 2) m1 = coll1[kWave + lane];
+            mi = cix[kWave + lane];
+        }
+        __syncthreads();
+        if (lane < rest) {
+            coll0[lane] = m0;
+            if (kParts == 2) coll1[lane] = m1;
+            cix[lane] = mi;
+        }
+        fill = rest;
+        __syncthreads();
+        tile(my);
+    };
+    if (vs >= w1) return;
+    float4 c0, c1;
+    fetch(vs + lane, c0, c1);
+    for (int base = vs; base < w1; base += kWave) {
+        const bool keep = (base + lane < w1) && may_reach(box, c0.x, c0.y, c0.z, cull2);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int at = fill + __popcll(m & below);
+            coll0[at] = c0;
+            if (kParts == 2) coll1[at] = c1;
+            cix[at] = base + lane - w0;
+        }
+        fill += __popcll(m);
+        if (base + kWave < w1) fetch(base + kWave + lane, c0, c1);
+        if (fill >= kWave) run(kWave);
+    }
+    if (fill > 0) run(fill);
+}
+
+// Forward symmetric items.
+template <class Acc, bool kSoft, bool kUM, int kW>
+__device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__restrict__ items,
+                                                uint32_t *hdr, const int *__restrict__ start,
+                                                const int *__restrict__ nact,
+                                                const int *__restrict__ sym_base, const Src &src,
+                                                float *__restrict__ pool, int K, float4 *coll,
+                                                int *cix, float4 *tile, SymRed<kW> &red,
+                                                int64_t pull_limit)
+{
+    const int lane = threadIdx.x;
+    const int64_t n_items = hdr[kHdrSymNItems];
+    const int q0 = blockIdx.x & (kQueues - 1);
+    PullGuard guard(min(n_items, pull_limit));
+    for (int qq = 0; qq < kQueues && !guard.bad; ++qq) {
+        const int q = (q0 + qq) & (kQueues - 1);
+        guard.next_queue();
+        for (;;) {
+            const int64_t gi = next_item(hdr, q, lane, kHdrSymQueue);
+            if (gi >= n_items || !guard.accept(gi)) break;
+            const int4 it = load_item(items, gi);
+            const int c = it.x, g = it.y, k = it.z;
+            const SegParams &S = acc.get(it.w);
+            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
+            float cq[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) cq[i] = S.pc.q[i];
+            SymStencil st;
+            sym_stencil_setup(S, c, start, nact, sym_base, lane, st);
+            const int D = __shfl(st.cnt, 0);  // segment 0 is the cell itself
+            const int c0s = start[c];
+            const int w0 = k * kW, w1 = min(w0 + kW, st.total);
+            const int tbase = sym_base[(int64_t)kSymStride * c] + k * D;
+            for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
+            const int p0 = g * K, p1 = min(p0 + K, D / kWave);
+            auto fetch_p = [&](int v, float4 &a, float4 &) {
+                int slot;
+                a = sym_fetch_pos(st, v, w1, src, slot);
+            };
+            for (int p = p0; p < p1; ++p) {
+                const int b = c0s + p * kWave + lane;
+                const float px = src.x[b], py = src.y[b], pz = src.z[b];
+                const float mi = kUM ? 1.f : src.m[b];
+                const Box box = target_box(true, px, py, pz, false, 0.f, 0.f, 0.f);
+                float ax = 0.f, ay = 0.f, az = 0.f;
+                if (p * kWave >= w0 && p * kWave < w1) {
+                    // the block against itself: steps 1..32, the last one on half the lanes
+                    __syncthreads();
+                    tile[lane] = make_float4(px, py, pz, src.m[b]);
+                    tile[lane + kWave] = tile[lane];
+                    __syncthreads();
+                    float bx = 0.f, by = 0.f, bz = 0.f;
+                    for (int s = 1; s <= kWave / 2; ++s) {
+                        float4 sj = tile[lane + s];
+                        if (s == kWave / 2 && lane >= kWave / 2) sj = make_float4(kFar, kFar, kFar, 0.f);
+                        sym_force_step<kSoft, kUM>(sj, px, py, pz, mi, eps2, tc2, cq, ax, ay, az, bx, by, bz);
+                        bx = rotate_down(bx);
+                        by = rotate_down(by);
+                        bz = rotate_down(bz);
+                    }
+                    const int r = p * kWave - w0 + ((lane + kWave / 2 + 1) & (kWave - 1));
+                    red.x[r] += bx;
+                    red.y[r] += by;
+                    red.z[r] += bz;
+                }
+                const int vs = max(w0, (p + 1) * kWave);
+                sym_stream<1>(vs, w1, w0, box, cull2, lane, coll, coll, cix, tile, tile, fetch_p, [&](int my) {
+                    float bx = 0.f, by = 0.f, bz = 0.f;
+                    const float4 *t = tile + lane;
+                    for (int s = 0; s < kWave; s += 8) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            sym_force_step<kSoft, kUM>(t[s + u], px, py, pz, mi, eps2, tc2, cq, ax, ay, az,
+                                                       bx, by, bz);
+                            bx = rotate_down(bx);
+                            by = rotate_down(by);
+                            bz = rotate_down(bz);
+                        }
+                    }
+                    if (my >= 0) {
+                        red.x[my] += bx;
+                        red.y[my] += by;
+                        red.z[my] += bz;
+                    }
+                });
+                const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
+                pool[o] = ax;
+                pool[o + 1] = ay;
+                pool[o + 2] = az;
+            }
+            __syncthreads();
+            // the window's opposite sums to their source slots
+            for (int i = 0; i < w1 - w0; i += kWave) {
+                const int v = w0 + i + lane;
+                const int q = sym_locate(st, v);
+                const int64_t slot = (int64_t)__shfl(st.sbase, q) + (int64_t)g * __shfl(st.cnt, q) +
+                                     (min(v, st.total - 1) - __shfl(st.excl, q));
+                if (v < w1) {
+                    pool[3 * slot] = red.x[i + lane];
+                    pool[3 * slot + 1] = red.y[i + lane];
+                    pool[3 * slot + 2] = red.z[i + lane];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    guard.report(hdr, lane);
+}
+
+template <class Acc, bool kSoft, int kW>
+__global__ __launch_bounds__(64) void k_force_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
+                                                  const int *__restrict__ start,
+                                                  const int *__restrict__ nact,
+                                                  const int *__restrict__ sym_base, Src src,
+                                                  float *__restrict__ pool, int K, int64_t pull_limit)
+{
+    __shared__ float4 coll[2 * kWave];
+    __shared__ int cix[2 * kWave];
+    __shared__ float4 tile[2 * kWave];
+    __shared__ SymRed<kW> red;
+    if (hdr[kHdrMassInfo] == 0)
+        force_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, coll,
+                                              cix, tile, red, pull_limit);
+    else
+        force_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, coll,
+                                               cix, tile, red, pull_limit);
+}
+
+// Adjoint symmetric items: as the forward, with the cotangent staged beside
+// each source.
+template <class Acc, bool kSoft, bool kUM, int kW>
+__device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__restrict__ items,
+                                              uint32_t *hdr, const int *__restrict__ start,
+                                              const int *__restrict__ nact,
+                                              const int *__restrict__ sym_base, const Src &src,
+                                              const float *__restrict__ gx, const float *__restrict__ gy,
+                                              const float *__restrict__ gz, float *__restrict__ pool,
+                                              int K, float4 *coll_p, float4 *coll_g, int *cix,
+                                              float4 *tile_p, float4 *tile_g, SymRed<kW> &red,
+                                              int64_t pull_limit)
+{
+    const int lane = threadIdx.x;
+    const int64_t n_items = hdr[kHdrSymNItems];
+    const int q0 = blockIdx.x & (kQueues - 1);
+    PullGuard guard(min(n_items, pull_limit));
+    for (int qq = 0; qq < kQueues && !guard.bad; ++qq) {
+        const int q = (q0 + qq) & (kQueues - 1);
+        guard.next_queue();
+        for (;;) {
+            const int64_t gi = next_item(hdr, q, lane, kHdrSymQueue);
+            if (gi >= n_items || !guard.accept(gi)) break;
+            const int4 it = load_item(items, gi);
+            const int c = it.x, g = it.y, k = it.z;
+            const SegParams &S = acc.get(it.w);
+            const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
+            float cq[6], cd[5];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) cq[i] = S.pc.q[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) cd[i] = S.pc.dq[i];
+            SymStencil st;
+            sym_stencil_setup(S, c, start, nact, sym_base, lane, st);
+            const int D = __shfl(st.cnt, 0);
+            const int c0s = start[c];
+            const int w0 = k * kW, w1 = min(w0 + kW, st.total);
+            const int tbase = sym_base[(int64_t)kSymStride * c] + k * D;
+            for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
+            const int p0 = g * K, p1 = min(p0 + K, D / kWave);
+            auto fetch_pg = [&](int v, float4 &a, float4 &gv) {
+                int slot;
+                a = sym_fetch_pos(st, v, w1, src, slot);
+                gv = make_float4(gx[slot], gy[slot], gz[slot], 0.f);
+                if (v >= w1) gv = make_float4(0.f, 0.f, 0.f, 0.f);
+            };
+            for (int p = p0; p < p1; ++p) {
+                const int b = c0s + p * kWave + lane;
+                const float px = src.x[b], py = src.y[b], pz = src.z[b], mk = src.m[b];
+                const float gkx = gx[b], gky = gy[b], gkz = gz[b];
+                const Box box = target_box(true, px, py, pz, false, 0.f, 0.f, 0.f);
+                float rx = 0.f, ry = 0.f, rz = 0.f;
+                if (p * kWave >= w0 && p * kWave < w1) {
+                    __syncthreads();
+                    tile_p[lane] = make_float4(px, py, pz, mk);
+                    tile_p[lane + kWave] = tile_p[lane];
+                    tile_g[lane] = make_float4(gkx, gky, gkz, 0.f);
+                    tile_g[lane + kWave] = tile_g[lane];
+                    __syncthreads();
+                    float bx = 0.f, by = 0.f, bz = 0.f;
+                    for (int s = 1; s <= kWave / 2; ++s) {
+                        float4 sj = tile_p[lane + s];
+                        float4 sg = tile_g[lane + s];
+                        if (s == kWave / 2 && lane >= kWave / 2) {
+                            sj = make_float4(kFar, kFar, kFar, 0.f);
+                            sg = make_float4(0.f, 0.f, 0.f, 0.f);
+                        }
+                        sym_vjp_step<kSoft, kUM>(sj, sg, px, py, pz, mk, gkx, gky, gkz, eps2, tc2, cq, cd, rx,
+                                                 ry, rz, bx, by, bz);
+                        bx = rotate_down(bx);
+                        by = rotate_down(by);
+                        bz = rotate_down(bz);
+                    }
+                    const int r = p * kWave - w0 + ((lane + kWave / 2 + 1) & (kWave - 1));
+                    red.x[r] += bx;
+                    red.y[r] += by;
+                    red.z[r] += bz;
+                }
+                const int vs = max(w0, (p + 1) * kWave);
+                sym_stream<2>(vs, w1, w0, box, cull2, lane, coll_p, coll_g, cix, tile_p, tile_g, fetch_pg,
+                              [&](int my) {
+                                  float bx = 0.f, by = 0.f, bz = 0.f;
+                                  const float4 *tp = tile_p + lane;
+                                  const float4 *tg = tile_g + lane;
+                                  for (int s = 0; s < kWave; s += 4) {
+#pragma unroll
+                                      for (int u = 0; u < 4; ++u) {
+                                          sym_vjp_step<kSoft, kUM>(tp[s + u], tg[s + u], px, py, pz, mk, gkx,
+                                                                   gky, gkz, eps2, tc2, cq, cd, rx, ry, rz,
+                                                                   bx, by, bz);
+                                          bx = rotate_down(bx);
+                                          by = rotate_down(by);
+                                          bz = rotate_down(bz);
+                                      }
+                                  }
+                                  if (my >= 0) {
+                                      red.x[my] += bx;
+                                      red.y[my] += by;
+                                      red.z[my] += bz;
+                                  }
+                              });
+                const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
+                pool[o] = rx;
+                pool[o + 1] = ry;
+                pool[o + 2] = rz;
+            }
+            __syncthreads();
+            for (int i = 0; i < w1 - w0; i += kWave) {
+                const int v = w0 + i + lane;
+                const int q = sym_locate(st, v);
+                const int64_t slot = (int64_t)__shfl(st.sbase, q) + (int64_t)g * __shfl(st.cnt, q) +
+                                     (min(v, st.total - 1) - __shfl(st.excl, q));
+                if (v < w1) {
+                    pool[3 * slot] = red.x[i + lane];
+                    pool[3 * slot + 1] = red.y[i + lane];
+                    pool[3 * slot + 2] = red.z[i + lane];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    guard.report(hdr, lane);
+}
+
+template <class Acc, bool kSoft, int kW>
+__global__ __launch_bounds__(64) void k_vjp_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
+                                                const int *__restrict__ start,
+                                                const int *__restrict__ nact,
+                                                const int *__restrict__ sym_base, Src src,
+                                                const float *__restrict__ gx, const float *__restrict__ gy,
+                                                const float *__restrict__ gz, float *__restrict__ pool, int K,
+                                                int64_t pull_limit)
+{
+    __shared__ float4 coll_p[2 * kWave];
+    __shared__ float4 coll_g[2 * kWave];
+    __shared__ int cix[2 * kWave];
+    __shared__ float4 tile_p[2 * kWave];
+    __shared__ float4 tile_g[2 * kWave];
+    __shared__ SymRed<kW> red;
+    if (hdr[kHdrMassInfo] == 0)
+        vjp_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, src, gx, gy, gz, pool, K,
+                                            coll_p, coll_g, cix, tile_p, tile_g, red, pull_limit);
+    else
+        vjp_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, src, gx, gy, gz, pool, K,
+                                             coll_p, coll_g, cix, tile_p, tile_g, red, pull_limit);
+}
+
+// Adds the partial slots of every dense particle, in a fixed order (its target
+// slots over the windows, then its source slots over the directions and
+// runs), to the row its one-sided item wrote: out[row] += m0 * sum (m0 the
+// common mass when every mass is equal, else 1).  rows: out_row (forward,
+// n_out = rows of acc) or perm (adjoint, n_out = N).
+__global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const int *__restrict__ key,
+                                                    const int *__restrict__ start,
+                                                    const int *__restrict__ nact,
+                                                    const int *__restrict__ sym_cnt,
+                                                    const int *__restrict__ sym_base,
+                                                    const float *__restrict__ pool,
+                                                    const int *__restrict__ rows,
+                                                    const float *__restrict__ mass /*binned*/,
+                                                    const uint32_t *hdr,
+                                                    float *__restrict__ out, int n_out)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= N || hdr[kHdrSymOk] == 0) return;
+    const int c = key[b] >> key_bits;
+    const int jl = b - start[c];
+    const int D = dense_count(nact[c]);
+    if (jl >= D) return;
+    const int r = rows[b];
+    if (r < 0 || r >= n_out) return;
+    const int *cn = sym_cnt + (int64_t)kSymStride * c;
+    const int *bs = sym_base + (int64_t)kSymStride * c;
+    float x = 0.f, y = 0.f, z = 0.f;
+    for (int e = 0; e < kSymStride; ++e) {
+        const int n = cn[e] / D;
+        int64_t o = (int64_t)bs[e] + jl;
+        for (int t = 0; t < n; ++t, o += D) {
+            x += pool[3 * o];
+            y += pool[3 * o + 1];
+            z += pool[3 * o + 2];
+        }
+    }
+    const float m0 = hdr[kHdrMassInfo] == 0 ? mass[0] : 1.0f;
+    const int64_t q = 3 * (int64_t)r;
+    out[q] += m0 * x;
+    out[q + 1] += m0 * y;
+    out[q + 2] += m0 * z;
+}
+
 // --------------------------------------------------------------- A8: momentum
 
 __device__ __forceinline__ double block_sum_d(double v, double *lds)
@@ -1437,6 +2161,35 @@ hipError_t build_items(const DevArgs &a, int two)
         k_items_write<decltype(acc), kActiveOnly><<<nb, 256, 0, a.st>>>(
             acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact), at<uint32_t>(a, L.info), hdr,
             at<int4>(a, L.items), two);
+        return hipGetLastError();
+    });
+}
+
+// Symmetric tiles: partial-slot counts and their scan, the go/no-go decision
+// (hdr[kHdrSymOk]) and the items.  Must precede build_items, whose dense
+// items then take only the non-dense sources.  With the tiles switched off
+// the decision is no.
+hipError_t build_sym(const DevArgs &a)
+{
+    const Layout &L = *a.L;
+    uint32_t *hdr = at<uint32_t>(a, L.hdr);
+    hipError_t e = fill_u32(hdr + kHdrSymTotal, 4, 0, a.st);  // total, ok, n_items
+    if (e != hipSuccess || a.sym_blocks <= 0) return e;
+    if ((e = fill_u32(hdr + kHdrSymBucketCount, kClasses, 0, a.st)) != hipSuccess) return e;
+    const int W = a.sym_window;
+    return with_acc(a, [&](auto acc) -> hipError_t {
+        const unsigned nb = blocks_for(L.NC, 256);
+        k_sym_count<<<nb, 256, 0, a.st>>>(acc, (int)L.NC, at<int>(a, L.nact), a.sym_blocks, W,
+                                          at<int>(a, L.sym_cnt), at<uint32_t>(a, L.sym_info), hdr,
+                                          L.magic());
+        hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess) return e2;
+        if ((e2 = scan_i32(at<int>(a, L.sym_cnt), at<int>(a, L.sym_base), kSymStride * L.NC,
+                           at<int>(a, L.scan_tmp), a.st)) != hipSuccess)
+            return e2;
+        k_sym_base<<<1, 64, 0, a.st>>>(hdr, L.magic(), (long long)L.sym_cap, 1);
+        k_sym_write<<<nb, 256, 0, a.st>>>(acc, (int)L.NC, at<int>(a, L.nact), a.sym_blocks,
+                                          at<uint32_t>(a, L.sym_info), hdr, at<int4>(a, L.sym_items));
         return hipGetLastError();
     });
 }
@@ -1550,8 +2303,8 @@ void launch_force(const DevArgs &a, Acc acc, float *acc_out)
 {
     const Layout &L = *a.L;
     k_force<Acc, kSoft, kOcc><<<persistent_grid(a), kWave, 0, a.st>>>(
-        acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), src_of(a),
-        at<int>(a, L.out_row), acc_out, a.n_rows, a.pull_limit);
+        acc, at<int4>(a, L.items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+        src_of(a), at<int>(a, L.out_row), acc_out, a.n_rows, a.pull_limit);
 }
 
 template <class Acc, bool kSoft, int kOcc>
@@ -1564,9 +2317,56 @@ void launch_vjp(const DevArgs &a, Acc acc, float *grad)
         grad, (int)L.N, a.pull_limit);
 }
 
+template <class Acc, bool kSoft>
+void launch_force_sym(const DevArgs &a, Acc acc)
+{
+    const Layout &L = *a.L;
+    unsigned grid = persistent_grid(a);
+    if ((int64_t)grid > L.sym_item_cap) grid = (unsigned)L.sym_item_cap;
+    if (a.sym_window >= 512)
+        k_force_sym<Acc, kSoft, 512><<<grid, kWave, 0, a.st>>>(
+            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+    else
+        k_force_sym<Acc, kSoft, 256><<<grid, kWave, 0, a.st>>>(
+            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+}
+
+template <class Acc, bool kSoft>
+void launch_vjp_sym(const DevArgs &a, Acc acc)
+{
+    const Layout &L = *a.L;
+    unsigned grid = persistent_grid(a);
+    if ((int64_t)grid > L.sym_item_cap) grid = (unsigned)L.sym_item_cap;
+    if (a.sym_window >= 512)
+        k_vjp_sym<Acc, kSoft, 512><<<grid, kWave, 0, a.st>>>(
+            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz),
+            at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+    else
+        k_vjp_sym<Acc, kSoft, 256><<<grid, kWave, 0, a.st>>>(
+            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz),
+            at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+}
+
+// Adds the symmetric partial sums to the rows the one-sided kernel wrote.
+hipError_t sym_gather(const DevArgs &a, const int *rows, float *out, int n_out)
+{
+    const Layout &L = *a.L;
+    k_sym_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
+        (int)L.N, L.key_bits, at<int>(a, L.sorted_keys()), at<int>(a, L.start), at<int>(a, L.nact),
+        at<int>(a, L.sym_cnt), at<int>(a, L.sym_base), at<float>(a, L.sym_pool), rows, at<float>(a, L.bm),
+        at<uint32_t>(a, L.hdr), out, n_out);
+    return hipGetLastError();
+}
+
 hipError_t dev_force(const DevArgs &a, float *acc_out)
 {
-    hipError_t e = build_items<true>(a, a.targets_per_lane >= 2 ? 1 : 0);
+    hipError_t e = build_sym(a);
+    if (e != hipSuccess) return e;
+    e = build_items<true>(a, a.targets_per_lane >= 2 ? 1 : 0);
     if (e != hipSuccess) return e;
     const bool soft = all_softened(a);
     return with_acc(a, [&](auto acc) -> hipError_t {
@@ -1582,7 +2382,14 @@ hipError_t dev_force(const DevArgs &a, float *acc_out)
             else if (a.occupancy >= 6) launch_force<A, false, 6>(a, acc, acc_out);
             else launch_force<A, false, 0>(a, acc, acc_out);
         }
-        const hipError_t le = hipGetLastError();
+        hipError_t le = hipGetLastError();
+        if (le == hipSuccess && a.sym_blocks > 0) {
+            // dense pairs once each; the device skips both when the tiles are off
+            if (soft) launch_force_sym<A, true>(a, acc);
+            else launch_force_sym<A, false>(a, acc);
+            if ((le = hipGetLastError()) == hipSuccess)
+                le = sym_gather(a, at<int>(a, a.L->out_row), acc_out, a.n_rows);
+        }
         timing_end(tok, a.st);
         return le;
     });
@@ -1596,6 +2403,7 @@ hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad)
                                                       at<float>(a, L.gz));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = build_sym(a)) != hipSuccess) return e;
     if ((e = build_items<false>(a, a.targets_per_lane >= 2 ? 1 : 0)) != hipSuccess) return e;
     const bool soft = all_softened(a);
     return with_acc(a, [&](auto acc) -> hipError_t {
@@ -1610,7 +2418,13 @@ hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad)
             if (a.occupancy >= 6) launch_vjp<A, false, 6>(a, acc, grad);
             else launch_vjp<A, false, 0>(a, acc, grad);
         }
-        const hipError_t le = hipGetLastError();
+        hipError_t le = hipGetLastError();
+        if (le == hipSuccess && a.sym_blocks > 0) {
+            if (soft) launch_vjp_sym<A, true>(a, acc);
+            else launch_vjp_sym<A, false>(a, acc);
+            if ((le = hipGetLastError()) == hipSuccess)
+                le = sym_gather(a, at<int>(a, a.L->perm()), grad, (int)a.L->N);
+        }
         timing_end(tok, a.st);
         return le;
     });
@@ -1624,7 +2438,12 @@ __global__ void k_copy_pairs(const uint32_t *hdr, int64_t *out)
 hipError_t dev_count_pairs(const DevArgs &a, bool adjoint, int64_t *pairs)
 {
     const Layout &L = *a.L;
-    hipError_t e = adjoint ? build_items<false>(a, 0) : build_items<true>(a, 0);
+    // every ordered pair from its target's end: no symmetric tiles here
+    DevArgs one = a;
+    one.sym_blocks = 0;
+    hipError_t e = build_sym(one);
+    if (e != hipSuccess) return e;
+    e = adjoint ? build_items<false>(a, 0) : build_items<true>(a, 0);
     if (e != hipSuccess) return e;
     if ((e = fill_u32(at<uint32_t>(a, L.hdr) + kHdrPairs, 2, 0, a.st)) != hipSuccess) return e;
     e = with_acc(a, [&](auto acc) -> hipError_t {

@@ -28,7 +28,7 @@ def test_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(_sr.EXPORTS)
-    assert L.sr_abi_version() == 4 == _sr.ABI_VERSION
+    assert L.sr_abi_version() == 5 == _sr.ABI_VERSION
     assert L.sr_status_str(0) == b"ok"
 
 
@@ -219,3 +219,21 @@ def test_static_forward_validation_before_the_device():
     assert L.sr_force_static(FAKE, FAKE, 100, 100, C.byref(p), None, None) == E_ARG
     assert L.sr_force_static(FAKE, FAKE, 100, 100, None, FAKE, None) == E_ARG
     assert L.sr_force_static(None, None, 0, 0, C.byref(p), None, None) == 0
+
+
+def test_tile_config_validation():
+    L = _sr.lib()
+    cur = (C.c_int * 2)()
+    saved = {k: _sr.tile_config(kernel=k) for k in ("force", "vjp")}
+    assert saved["force"] == (16, 512) and saved["vjp"] == (16, 256)
+    assert L.sr_tile_config(b"bogus", 4, 256, cur) == 1
+    assert L.sr_tile_config(None, 4, 256, cur) == 1
+    assert L.sr_tile_config(b"force", 257, -1, cur) == 1
+    assert L.sr_tile_config(b"force", -2, -1, cur) == 1
+    assert L.sr_tile_config(b"force", -1, 384, cur) == 1
+    assert _sr.tile_config(4, 256, kernel="force") == (4, 256)
+    assert _sr.tile_config(kernel="vjp") == saved["vjp"]  # the other kernel is untouched
+    assert _sr.tile_config(0, kernel="force") == (0, 256)  # 0 switches the tiles off
+    for k, v in saved.items():
+        _sr.tile_config(*v, kernel=k)
+    assert {k: _sr.tile_config(kernel=k) for k in ("force", "vjp")} == saved

@@ -240,6 +240,7 @@ std::atomic<int> g_occ_default[2] = {{6}, {0}};
 // item (0: off) and sources per window (256 or 512).
 std::atomic<int> g_sym_blocks[2] = {{16}, {16}};
 std::atomic<int> g_sym_window[2] = {{512}, {256}};
+std::atomic<int> g_sym_occ[2] = {{5}, {5}};
 
 // Launch defaults may be overridden for experiments (both kernels):
 // SR_WAVES_PER_CU, SR_TARGETS_PER_LANE, SR_OCCUPANCY.
@@ -266,6 +267,10 @@ struct EnvDefaults {
             if (const char *v = std::getenv("SR_SYM_WINDOW")) {
                 const int w = std::atoi(v);
                 if (w == 256 || w == 512) g_sym_window[k] = w;
+            }
+            if (const char *v = std::getenv("SR_SYM_OCC")) {
+                const int o = std::atoi(v);
+                if (o == 0 || o == 5 || o == 6) g_sym_occ[k] = o;
             }
         }
     }
@@ -315,6 +320,7 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.occupancy = g_occ_default[cfg].load();
     a.sym_blocks = g_sym_blocks[cfg].load();
     a.sym_window = g_sym_window[cfg].load();
+    a.sym_occupancy = g_sym_occ[cfg].load();
     a.pull_limit = pull_limit();
     return SR_OK;
 }

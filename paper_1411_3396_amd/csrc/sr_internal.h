@@ -132,6 +132,7 @@ struct DevArgs {
     int occupancy;         // register-allocation hint of the pair kernels: 0, 6 or 8 waves/SIMD
     int sym_blocks;        // symmetric tiles: blocks of 64 targets per item (0: symmetric tiles off)
     int sym_window;        // symmetric tiles: sources per item window (256 or 512)
+    int sym_occupancy;     // symmetric tiles: register-allocation hint, 0 or 5 waves/SIMD
     int64_t pull_limit;    // most items one wave of a persistent kernel may pull (test hook)
 };
 

@@ -1677,69 +1677,58 @@ struct SymRed {
 };
 
 // Stream the window's sources [vs, w1) through the culling test against the
-// block's box, collect survivors (with their window index) in `coll`, and run
-// `tile(my)` on every 64 of them: the tile reads tile0 (and tile1), filled
-// here with the 64 survivors stored twice, and my is this lane's survivor's
-// window index (-1 for padding).  Every lane must call this.
+// block's box and gather the survivors straight into the tile (tile0, and
+// tile1 for a second float4 per source; each entry stored twice, at e and
+// e + 64, so that step s of lane l reads entry l + s without a wrap) with
+// their window index in tix.  Whenever 64 are in, `tile(my)` runs (my: the
+// window index of this lane's entry, -1 for padding); survivors of the same
+// batch beyond the 64th start the next tile.  Every lane must call this.
 template <int kParts, class Fetch, class Tile>
 __device__ __forceinline__ void sym_stream(int vs, int w1, int w0, const Box &box, float cull2, int lane,
-                                           float4 *coll0, float4 *coll1, int *cix, float4 *tile0,
-                                           float4 *tile1, Fetch &&fetch, Tile &&tile)
+                                           float4 *tile0, float4 *tile1, int *tix, Fetch &&fetch,
+                                           Tile &&tile)
 {
+    if (vs >= w1) return;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     int fill = 0;
-    auto run = [&](int n) {
-        // n <= 64 collected; pad the rest of the tile
-        __syncthreads();
-        float4 a0 = coll0[lane], a1 = kParts == 2 ? coll1[lane] : a0;
-        int my = cix[lane];
-        if (lane >= n) {
-            a0 = make_float4(kFar, kFar, kFar, 0.f);
-            a1 = make_float4(0.f, 0.f, 0.f, 0.f);
-            my = -1;
-        }
-        tile0[lane] = a0;
-        tile0[lane + kWave] = a0;
+    auto put = [&](int at, const float4 &c0, const float4 &c1, int ix) {
+        tile0[at] = c0;
+        tile0[at + kWave] = c0;
         if (kParts == 2) {
-            tile1[lane] = a1;
-            tile1[lane + kWave] = a1;
+            tile1[at] = c1;
+            tile1[at + kWave] = c1;
         }
-        // the survivors beyond the first 64 move to the front
-        const int rest = fill - n;
-        float4 m0, m1;
-        int mi = -1;
-        if (lane < rest) {
-            m0 = coll0[kWave + lane];
-            if (kParts == 2) m1 = coll1[kWave + lane];
-            mi = cix[kWave + lane];
-        }
-        __syncthreads();
-        if (lane < rest) {
-            coll0[lane] = m0;
-            if (kParts == 2) coll1[lane] = m1;
-            cix[lane] = mi;
-        }
-        fill = rest;
-        __syncthreads();
-        tile(my);
+        tix[at] = ix;
     };
-    if (vs >= w1) return;
+    auto run = [&]() {
+        __syncthreads();
+        const int my = tix[lane];
+        tile(my);
+        __syncthreads();
+    };
     float4 c0, c1;
     fetch(vs + lane, c0, c1);
     for (int base = vs; base < w1; base += kWave) {
         const bool keep = (base + lane < w1) && may_reach(box, c0.x, c0.y, c0.z, cull2);
         const uint64_t m = __ballot(keep);
-        if (keep) {
-            const int at = fill + __popcll(m & below);
-            coll0[at] = c0;
-            if (kParts == 2) coll1[at] = c1;
-            cix[at] = base + lane - w0;
+        const int cnt = __popcll(m);
+        const int at = fill + __popcll(m & below);
+        const int ix = base + lane - w0;
+        if (keep && at < kWave) put(at, c0, c1, ix);
+        if (fill + cnt >= kWave) {
+            run();
+            if (keep && at >= kWave) put(at - kWave, c0, c1, ix);
+            fill += cnt - kWave;
+        } else {
+            fill += cnt;
         }
-        fill += __popcll(m);
         if (base + kWave < w1) fetch(base + kWave + lane, c0, c1);
-        if (fill >= kWave) run(kWave);
     }
-    if (fill > 0) run(fill);
+    if (fill > 0) {
+        if (lane >= fill)
+            put(lane, make_float4(kFar, kFar, kFar, 0.f), make_float4(0.f, 0.f, 0.f, 0.f), -1);
+        run();
+    }
 }
 
 // Forward symmetric items.
@@ -1748,9 +1737,8 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                                                 uint32_t *hdr, const int *__restrict__ start,
                                                 const int *__restrict__ nact,
                                                 const int *__restrict__ sym_base, const Src &src,
-                                                float *__restrict__ pool, int K, float4 *coll,
-                                                int *cix, float4 *tile, SymRed<kW> &red,
-                                                int64_t pull_limit)
+                                                float *__restrict__ pool, int K, float4 *tile,
+                                                int *tix, SymRed<kW> &red, int64_t pull_limit)
 {
     const int lane = threadIdx.x;
     const int64_t n_items = hdr[kHdrSymNItems];
@@ -1808,7 +1796,7 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                     red.z[r] += bz;
                 }
                 const int vs = max(w0, (p + 1) * kWave);
-                sym_stream<1>(vs, w1, w0, box, cull2, lane, coll, coll, cix, tile, tile, fetch_p, [&](int my) {
+                sym_stream<1>(vs, w1, w0, box, cull2, lane, tile, tile, tix, fetch_p, [&](int my) {
                     float bx = 0.f, by = 0.f, bz = 0.f;
                     const float4 *t = tile + lane;
                     for (int s = 0; s < kWave; s += 8) {
@@ -1851,23 +1839,22 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
     guard.report(hdr, lane);
 }
 
-template <class Acc, bool kSoft, int kW>
-__global__ __launch_bounds__(64) void k_force_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
+template <class Acc, bool kSoft, int kW, int kOcc>
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
                                                   const int *__restrict__ start,
                                                   const int *__restrict__ nact,
                                                   const int *__restrict__ sym_base, Src src,
                                                   float *__restrict__ pool, int K, int64_t pull_limit)
 {
-    __shared__ float4 coll[2 * kWave];
-    __shared__ int cix[2 * kWave];
     __shared__ float4 tile[2 * kWave];
+    __shared__ int tix[kWave];
     __shared__ SymRed<kW> red;
     if (hdr[kHdrMassInfo] == 0)
-        force_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, coll,
-                                              cix, tile, red, pull_limit);
+        force_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, tile,
+                                              tix, red, pull_limit);
     else
-        force_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, coll,
-                                               cix, tile, red, pull_limit);
+        force_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, tile,
+                                               tix, red, pull_limit);
 }
 
 // Adjoint symmetric items: as the forward, with the cotangent staged beside
@@ -1879,9 +1866,8 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
                                               const int *__restrict__ sym_base, const Src &src,
                                               const float *__restrict__ gx, const float *__restrict__ gy,
                                               const float *__restrict__ gz, float *__restrict__ pool,
-                                              int K, float4 *coll_p, float4 *coll_g, int *cix,
-                                              float4 *tile_p, float4 *tile_g, SymRed<kW> &red,
-                                              int64_t pull_limit)
+                                              int K, float4 *tile_p, float4 *tile_g, int *tix,
+                                              SymRed<kW> &red, int64_t pull_limit)
 {
     const int lane = threadIdx.x;
     const int64_t n_items = hdr[kHdrSymNItems];
@@ -1949,7 +1935,7 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
                     red.z[r] += bz;
                 }
                 const int vs = max(w0, (p + 1) * kWave);
-                sym_stream<2>(vs, w1, w0, box, cull2, lane, coll_p, coll_g, cix, tile_p, tile_g, fetch_pg,
+                sym_stream<2>(vs, w1, w0, box, cull2, lane, tile_p, tile_g, tix, fetch_pg,
                               [&](int my) {
                                   float bx = 0.f, by = 0.f, bz = 0.f;
                                   const float4 *tp = tile_p + lane;
@@ -1994,8 +1980,8 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
     guard.report(hdr, lane);
 }
 
-template <class Acc, bool kSoft, int kW>
-__global__ __launch_bounds__(64) void k_vjp_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
+template <class Acc, bool kSoft, int kW, int kOcc>
+__global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
                                                 const int *__restrict__ start,
                                                 const int *__restrict__ nact,
                                                 const int *__restrict__ sym_base, Src src,
@@ -2003,18 +1989,16 @@ __global__ __launch_bounds__(64) void k_vjp_sym(Acc acc, const int4 *__restrict_
                                                 const float *__restrict__ gz, float *__restrict__ pool, int K,
                                                 int64_t pull_limit)
 {
-    __shared__ float4 coll_p[2 * kWave];
-    __shared__ float4 coll_g[2 * kWave];
-    __shared__ int cix[2 * kWave];
     __shared__ float4 tile_p[2 * kWave];
     __shared__ float4 tile_g[2 * kWave];
+    __shared__ int tix[kWave];
     __shared__ SymRed<kW> red;
     if (hdr[kHdrMassInfo] == 0)
         vjp_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, src, gx, gy, gz, pool, K,
-                                            coll_p, coll_g, cix, tile_p, tile_g, red, pull_limit);
+                                            tile_p, tile_g, tix, red, pull_limit);
     else
         vjp_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, src, gx, gy, gz, pool, K,
-                                             coll_p, coll_g, cix, tile_p, tile_g, red, pull_limit);
+                                             tile_p, tile_g, tix, red, pull_limit);
 }
 
 // Adds the partial slots of every dense particle, in a fixed order (its target
@@ -2043,21 +2027,43 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
     if (r < 0 || r >= n_out) return;
     const int *cn = sym_cnt + (int64_t)kSymStride * c;
     const int *bs = sym_base + (int64_t)kSymStride * c;
-    float x = 0.f, y = 0.f, z = 0.f;
+    struct F3 {
+        float x, y, z;
+    };
+    const F3 *P = reinterpret_cast<const F3 *>(pool);
+    // four running sums over the slots of a row group (loads in flight
+    // together), combined in a fixed order at the end
+    float x[4] = {0.f, 0.f, 0.f, 0.f}, y[4] = {0.f, 0.f, 0.f, 0.f}, z[4] = {0.f, 0.f, 0.f, 0.f};
     for (int e = 0; e < kSymStride; ++e) {
         const int n = cn[e] / D;
         int64_t o = (int64_t)bs[e] + jl;
-        for (int t = 0; t < n; ++t, o += D) {
-            x += pool[3 * o];
-            y += pool[3 * o + 1];
-            z += pool[3 * o + 2];
+        int t = 0;
+        for (; t + 4 <= n; t += 4, o += 4 * (int64_t)D) {
+            F3 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = P[o + u * (int64_t)D];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x[u] += v[u].x;
+                y[u] += v[u].y;
+                z[u] += v[u].z;
+            }
+        }
+        for (; t < n; ++t, o += D) {
+            const F3 v = P[o];
+            x[0] += v.x;
+            y[0] += v.y;
+            z[0] += v.z;
         }
     }
+    const float sx = (x[0] + x[1]) + (x[2] + x[3]);
+    const float sy = (y[0] + y[1]) + (y[2] + y[3]);
+    const float sz = (z[0] + z[1]) + (z[2] + z[3]);
     const float m0 = hdr[kHdrMassInfo] == 0 ? mass[0] : 1.0f;
     const int64_t q = 3 * (int64_t)r;
-    out[q] += m0 * x;
-    out[q + 1] += m0 * y;
-    out[q + 2] += m0 * z;
+    out[q] += m0 * sx;
+    out[q + 1] += m0 * sy;
+    out[q + 2] += m0 * sz;
 }
 
 // --------------------------------------------------------------- A8: momentum
@@ -2317,38 +2323,53 @@ void launch_vjp(const DevArgs &a, Acc acc, float *grad)
         grad, (int)L.N, a.pull_limit);
 }
 
+template <class Acc, bool kSoft, int kW, int kOcc>
+void launch_force_sym_v(const DevArgs &a, Acc acc, unsigned grid)
+{
+    const Layout &L = *a.L;
+    k_force_sym<Acc, kSoft, kW, kOcc><<<grid, kWave, 0, a.st>>>(
+        acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+        at<int>(a, L.sym_base), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+}
+
 template <class Acc, bool kSoft>
 void launch_force_sym(const DevArgs &a, Acc acc)
 {
-    const Layout &L = *a.L;
     unsigned grid = persistent_grid(a);
-    if ((int64_t)grid > L.sym_item_cap) grid = (unsigned)L.sym_item_cap;
-    if (a.sym_window >= 512)
-        k_force_sym<Acc, kSoft, 512><<<grid, kWave, 0, a.st>>>(
-            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
-            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
-    else
-        k_force_sym<Acc, kSoft, 256><<<grid, kWave, 0, a.st>>>(
-            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
-            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+    if ((int64_t)grid > a.L->sym_item_cap) grid = (unsigned)a.L->sym_item_cap;
+    if (a.sym_window >= 512) {
+        if (a.sym_occupancy >= 6) launch_force_sym_v<Acc, kSoft, 512, 6>(a, acc, grid);
+        else if (a.sym_occupancy >= 5) launch_force_sym_v<Acc, kSoft, 512, 5>(a, acc, grid);
+        else launch_force_sym_v<Acc, kSoft, 512, 0>(a, acc, grid);
+    } else {
+        if (a.sym_occupancy >= 6) launch_force_sym_v<Acc, kSoft, 256, 6>(a, acc, grid);
+        else if (a.sym_occupancy >= 5) launch_force_sym_v<Acc, kSoft, 256, 5>(a, acc, grid);
+        else launch_force_sym_v<Acc, kSoft, 256, 0>(a, acc, grid);
+    }
+}
+
+template <class Acc, bool kSoft, int kW, int kOcc>
+void launch_vjp_sym_v(const DevArgs &a, Acc acc, unsigned grid)
+{
+    const Layout &L = *a.L;
+    k_vjp_sym<Acc, kSoft, kW, kOcc><<<grid, kWave, 0, a.st>>>(
+        acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
+        at<int>(a, L.sym_base), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz),
+        at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
 }
 
 template <class Acc, bool kSoft>
 void launch_vjp_sym(const DevArgs &a, Acc acc)
 {
-    const Layout &L = *a.L;
     unsigned grid = persistent_grid(a);
-    if ((int64_t)grid > L.sym_item_cap) grid = (unsigned)L.sym_item_cap;
-    if (a.sym_window >= 512)
-        k_vjp_sym<Acc, kSoft, 512><<<grid, kWave, 0, a.st>>>(
-            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
-            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz),
-            at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
-    else
-        k_vjp_sym<Acc, kSoft, 256><<<grid, kWave, 0, a.st>>>(
-            acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
-            at<int>(a, L.sym_base), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz),
-            at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+    if ((int64_t)grid > a.L->sym_item_cap) grid = (unsigned)a.L->sym_item_cap;
+    if (a.sym_window >= 512) {
+        if (a.sym_occupancy >= 5) launch_vjp_sym_v<Acc, kSoft, 512, 5>(a, acc, grid);
+        else launch_vjp_sym_v<Acc, kSoft, 512, 0>(a, acc, grid);
+    } else {
+        if (a.sym_occupancy >= 5) launch_vjp_sym_v<Acc, kSoft, 256, 5>(a, acc, grid);
+        else launch_vjp_sym_v<Acc, kSoft, 256, 0>(a, acc, grid);
+    }
 }
 
 // Adds the symmetric partial sums to the rows the one-sided kernel wrote.

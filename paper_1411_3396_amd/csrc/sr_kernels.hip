@@ -877,10 +877,12 @@ __device__ __forceinline__ void force_pair(const float4 s, float px, float py, f
     const float q2 = qi * qi;
     const float f = fmaf(q2, qi, -horner5(cq, tt));
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-    const float w = in ? (kUM ? f : s.w * f) : 0.f;
-    ax = fmaf(w, dx, ax);
-    ay = fmaf(w, dy, ay);
-    az = fmaf(w, dz, az);
+    if (in) {  // an exec mask rather than a select (f may be infinite for padding)
+        const float w = kUM ? f : s.w * f;
+        ax = fmaf(w, dx, ax);
+        ay = fmaf(w, dy, ay);
+        az = fmaf(w, dz, az);
+    }
 }
 
 // One adjoint pair term: r += f u + 2 f' (u.d) d, u = m_k g_j - m_j g_k.
@@ -903,15 +905,17 @@ __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float 
     const float q2 = qi * qi;
     const float q3 = q2 * qi;
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-    const float f = in ? q3 - horner5(cq, tt) : 0.f;
-    const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
+    const float f = q3 - horner5(cq, tt);
+    const float fp2 = fmaf(-3.0f, q3 * q2, -horner4(cd, tt));
     const float ux = kUM ? gj.x - gkx : mk * gj.x - s.w * gkx;
     const float uy = kUM ? gj.y - gky : mk * gj.y - s.w * gky;
     const float uz = kUM ? gj.z - gkz : mk * gj.z - s.w * gkz;
     const float c = fp2 * fmaf(ux, dx, fmaf(uy, dy, uz * dz));
-    rx = fmaf(c, dx, fmaf(f, ux, rx));
-    ry = fmaf(c, dy, fmaf(f, uy, ry));
-    rz = fmaf(c, dz, fmaf(f, uz, rz));
+    if (in) {  // an exec mask rather than selects (f, c may be infinite for padding)
+        rx = fmaf(c, dx, fmaf(f, ux, rx));
+        ry = fmaf(c, dy, fmaf(f, uy, ry));
+        rz = fmaf(c, dz, fmaf(f, uz, rz));
+    }
 }
 
 // ------------------------------------------------------------- source culling
@@ -1625,15 +1629,18 @@ __device__ __forceinline__ void sym_force_step(const float4 s, float px, float p
     const float q2 = qi * qi;
     const float f = fmaf(q2, qi, -horner5(cq, tt));
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-    const float fm = in ? f : 0.f;
-    const float wt = kUM ? fm : s.w * fm;
-    const float ws = kUM ? fm : mi * fm;
-    ax = fmaf(wt, dx, ax);
-    ay = fmaf(wt, dy, ay);
-    az = fmaf(wt, dz, az);
-    bx = fmaf(-ws, dx, bx);
-    by = fmaf(-ws, dy, by);
-    bz = fmaf(-ws, dz, bz);
+    // lanes out of reach skip the sums (an exec mask, not a select: one
+    // instruction fewer per step; their f may be infinite for padding)
+    if (in) {
+        const float wt = kUM ? f : s.w * f;
+        const float ws = kUM ? f : mi * f;
+        ax = fmaf(wt, dx, ax);
+        ay = fmaf(wt, dy, ay);
+        az = fmaf(wt, dz, az);
+        bx = fmaf(-ws, dx, bx);
+        by = fmaf(-ws, dy, by);
+        bz = fmaf(-ws, dz, bz);
+    }
 }
 
 // One adjoint step: the target gets T = f u + 2 f' (u.d) d, the source -T
@@ -1652,8 +1659,8 @@ __device__ __forceinline__ void sym_vjp_step(const float4 s, const float4 gj, fl
     const float q2 = qi * qi;
     const float q3 = q2 * qi;
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-    const float f = in ? q3 - horner5(cq, tt) : 0.f;
-    const float fp2 = in ? fmaf(-3.0f, q3 * q2, -horner4(cd, tt)) : 0.f;
+    const float f = q3 - horner5(cq, tt);
+    const float fp2 = fmaf(-3.0f, q3 * q2, -horner4(cd, tt));
     const float ux = kUM ? gj.x - gkx : mk * gj.x - s.w * gkx;
     const float uy = kUM ? gj.y - gky : mk * gj.y - s.w * gky;
     const float uz = kUM ? gj.z - gkz : mk * gj.z - s.w * gkz;
@@ -1661,12 +1668,14 @@ __device__ __forceinline__ void sym_vjp_step(const float4 s, const float4 gj, fl
     const float tx = fmaf(c, dx, f * ux);
     const float ty = fmaf(c, dy, f * uy);
     const float tz = fmaf(c, dz, f * uz);
-    rx += tx;
-    ry += ty;
-    rz += tz;
-    bx -= tx;
-    by -= ty;
-    bz -= tz;
+    if (in) {  // an exec mask: out-of-reach lanes (T possibly infinite for padding) add nothing
+        rx += tx;
+        ry += ty;
+        rz += tz;
+        bx -= tx;
+        by -= ty;
+        bz -= tz;
+    }
 }
 
 // Window partial sums of the sources (opposite terms), one float per source

@@ -253,7 +253,8 @@ sr_status sr_ws_flags(const void *ws, void *stream, uint32_t *flags /*host out*/
  *
  * sr_batch_plan_create (host) validates the batch, lays out the workspace
  * and reports its size in *ws_bytes.  tune_cache (host, nullable) names a
- * JSON file in which launch parameters measured on the first run are kept.
+ * JSON file in which the launch parameters and symmetric tiles measured on
+ * the first run are kept (the tiles change only the order of float32 sums).
  * The plan owns only host memory, one HIP stream and, after the first run
  * in graph mode, a captured HIP graph of the whole bin-then-force sequence
  * bound to the pointers (pos, mass, ws, acc, momentum) of that run.  A later
@@ -269,8 +270,9 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets /*host [B+1]*/,
  * sum over active rows of mass * acc per subvolume.  flags:
  * SR_BATCH_PER_SUBVOLUME (one sr_force per subvolume, the reference mode),
  * SR_BATCH_EAGER (batched kernels without a graph), 0 (graph replay; with
- * SR_BATCH_RECAPTURE, capture again for new pointers).  The first run that
- * is not per-subvolume tunes the launch parameters (it synchronises). */
+ * SR_BATCH_RECAPTURE, capture again for new pointers).  The first run, in
+ * any mode, tunes the launch parameters and the symmetric tiles by timing
+ * batched runs (it synchronises), so that every mode then uses the same. */
 sr_status sr_batch_force(sr_batch_plan *plan, const float *pos, const float *mass, void *ws,
                          size_t ws_bytes, float *acc, double *momentum, unsigned flags,
                          void *stream);

@@ -393,6 +393,8 @@ struct sr_batch_plan {
     int waves_per_cu = 0;               // 0: not tuned yet
     int targets_per_lane = 1;
     int occupancy = 0;
+    int sym_blocks = -1;                // symmetric tiles (-1: the forward kernel's current setting)
+    int sym_window = -1;
     std::string tune_cache;
     std::string tune_key;
     double tuned_ms = -1.0;
@@ -410,6 +412,8 @@ sr_status run_batched(sr_batch_plan *P, const float *pos, const float *mass, voi
     if (s != SR_OK) return s;
     a.targets_per_lane = P->targets_per_lane;
     a.occupancy = P->occupancy;
+    if (P->sym_blocks >= 0) a.sym_blocks = P->sym_blocks;
+    if (P->sym_window > 0) a.sym_window = P->sym_window;
     hipError_t e = hipMemcpyAsync(static_cast<char *>(ws) + P->L.seg, P->pinned,
                                   sizeof(SegParams) * P->B, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return SR_E_DEVICE;
@@ -432,6 +436,8 @@ sr_status run_per_subvolume(sr_batch_plan *P, const float *pos, const float *mas
         if (s != SR_OK) return s;
         a.targets_per_lane = P->targets_per_lane;
         a.occupancy = P->occupancy;
+        if (P->sym_blocks >= 0) a.sym_blocks = P->sym_blocks;
+        if (P->sym_window > 0) a.sym_window = P->sym_window;
         if (n > 0) {
             if (dev_bin(a, pos + 3 * off, mass + off) != hipSuccess) return SR_E_DEVICE;
             if (P->n_active[b] > 0 && dev_force(a, acc + 3 * out_off) != hipSuccess) return SR_E_DEVICE;
@@ -468,7 +474,8 @@ std::string arch_name()
 }
 
 // Minimal reader of the tune cache: one line per key, "key waves".
-bool cache_lookup(const std::string &path, const std::string &key, int &waves, int &tpl, int &occ)
+bool cache_lookup(const std::string &path, const std::string &key, int &waves, int &tpl, int &occ,
+                  int &sym_blocks, int &sym_window)
 {
     if (path.empty()) return false;
     std::ifstream in(path);
@@ -487,10 +494,17 @@ bool cache_lookup(const std::string &path, const std::string &key, int &waves, i
         const int tv = t == std::string::npos ? 1 : std::atoi(line.c_str() + t + 19);
         const size_t o = line.find("\"occupancy\":", q1);
         const int ov = o == std::string::npos ? 0 : std::atoi(line.c_str() + o + 12);
-        if (v >= 1 && v <= 64 && (tv == 1 || tv == 2) && (ov == 0 || ov == 6 || ov == 8)) {
+        const size_t sb = line.find("\"sym_blocks\":", q1);
+        const int sbv = sb == std::string::npos ? -1 : std::atoi(line.c_str() + sb + 13);
+        const size_t sw = line.find("\"sym_window\":", q1);
+        const int swv = sw == std::string::npos ? -1 : std::atoi(line.c_str() + sw + 13);
+        if (v >= 1 && v <= 64 && (tv == 1 || tv == 2) && (ov == 0 || ov == 6 || ov == 8) && sbv >= -1 &&
+            sbv <= 256 && (swv == -1 || swv == 256 || swv == 512)) {
             waves = v;
             tpl = tv;
             occ = ov;
+            sym_blocks = sbv;
+            sym_window = swv;
             return true;
         }
     }
@@ -498,7 +512,7 @@ bool cache_lookup(const std::string &path, const std::string &key, int &waves, i
 }
 
 void cache_store(const std::string &path, const std::string &key, int waves, int tpl, int occ,
-                 double ms)
+                 int sym_blocks, int sym_window, double ms)
 {
     if (path.empty()) return;
     std::vector<std::string> keep;
@@ -519,7 +533,8 @@ void cache_store(const std::string &path, const std::string &key, int waves, int
     }
     std::ostringstream e;
     e << "  \"" << key << "\": {\"waves_per_cu\": " << waves << ", \"targets_per_lane\": " << tpl
-      << ", \"occupancy\": " << occ << ", \"ms\": " << ms << "}";
+      << ", \"occupancy\": " << occ << ", \"sym_blocks\": " << sym_blocks << ", \"sym_window\": "
+      << sym_window << ", \"ms\": " << ms << "}";
     keep.push_back(e.str());
     const std::string tmp = path + ".tmp";
     {
@@ -534,31 +549,27 @@ void cache_store(const std::string &path, const std::string &key, int waves, int
 
 // Pick the launch parameters (persistent grid in waves per CU, targets per
 // lane of dense items, register-allocation variant) by timing the batched
-// sequence; results do not depend on them.
+// sequence, then the tiles of the symmetric kernel (blocks per item, window,
+// or off) with those parameters.  Launch parameters do not change results;
+// the tiles change only the order of the float32 sums (and so the last bits),
+// and are fixed once the plan is tuned.
 sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, float *acc,
                hipStream_t st)
 {
-    int waves = 0, tpl = 1, occ = 0;
-    if (cache_lookup(P->tune_cache, P->tune_key, waves, tpl, occ)) {
+    int waves = 0, tpl = 1, occ = 0, sb = -1, sw = -1;
+    if (cache_lookup(P->tune_cache, P->tune_key, waves, tpl, occ, sb, sw)) {
         P->waves_per_cu = waves;
         P->targets_per_lane = tpl;
         P->occupancy = occ;
+        P->sym_blocks = sb;
+        P->sym_window = sw;
         return SR_OK;
     }
-    struct Cand {
-        int w, t, o;
-    };
-    const Cand cand[] = {{16, 1, 0}, {32, 1, 0}, {16, 2, 0}, {32, 2, 0}, {24, 1, 6},
-                         {32, 1, 6}, {24, 2, 6}, {32, 2, 6}, {32, 1, 8}, {32, 2, 8}};
-    double best = 1e300;
-    Cand pick{g_waves_default[kCfgForce].load(), 1, 0};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SR_E_DEVICE;
-    for (const Cand &c : cand) {
-        P->waves_per_cu = c.w;
-        P->targets_per_lane = c.t;
-        P->occupancy = c.o;
-        sr_status s = run_batched(P, pos, mass, ws, acc, nullptr, st);  // warm
+    // two timed runs after a warm one
+    auto time_runs = [&](double &ms_out) -> sr_status {
+        sr_status s = run_batched(P, pos, mass, ws, acc, nullptr, st);
         if (s != SR_OK) return s;
         float ms = 0.f;
         (void)hipEventRecord(e0, st);
@@ -569,18 +580,56 @@ sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, 
         (void)hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess) return SR_E_DEVICE;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        ms_out = ms;
+        return SR_OK;
+    };
+    struct Cand {
+        int w, t, o;
+    };
+    const Cand cand[] = {{16, 1, 0}, {32, 1, 0}, {16, 2, 0}, {32, 2, 0}, {24, 1, 6},
+                         {32, 1, 6}, {24, 2, 6}, {32, 2, 6}, {32, 1, 8}, {32, 2, 8}};
+    double best = 1e300;
+    Cand pick{g_waves_default[kCfgForce].load(), 1, 0};
+    P->sym_blocks = -1;
+    P->sym_window = -1;
+    for (const Cand &c : cand) {
+        P->waves_per_cu = c.w;
+        P->targets_per_lane = c.t;
+        P->occupancy = c.o;
+        double ms = 0;
+        const sr_status s = time_runs(ms);
+        if (s != SR_OK) return s;
         if (ms < best) {
             best = ms;
             pick = c;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     P->waves_per_cu = pick.w;
     P->targets_per_lane = pick.t;
     P->occupancy = pick.o;
-    P->tuned_ms = best / 2.0;
-    cache_store(P->tune_cache, P->tune_key, pick.w, pick.t, pick.o, best / 2.0);
+    struct Tile {
+        int k, w;
+    };
+    const Tile tiles[] = {{16, 512}, {16, 256}, {64, 512}, {4, 512}, {0, 512}};
+    Tile tpick{-1, -1};
+    double best_t = 1e300;
+    for (const Tile &t : tiles) {
+        P->sym_blocks = t.k;
+        P->sym_window = t.w;
+        double ms = 0;
+        const sr_status s = time_runs(ms);
+        if (s != SR_OK) return s;
+        if (ms < best_t) {
+            best_t = ms;
+            tpick = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->sym_blocks = tpick.k;
+    P->sym_window = tpick.w;
+    P->tuned_ms = std::min(best, best_t) / 2.0;
+    cache_store(P->tune_cache, P->tune_key, pick.w, pick.t, pick.o, tpick.k, tpick.w, P->tuned_ms);
     return SR_OK;
 }
 
@@ -867,11 +916,12 @@ sr_status sr_batch_force(sr_batch_plan *P, const float *pos, const float *mass, 
     if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0 || ws_bytes < P->ws_bytes)
         return SR_E_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (flags & SR_BATCH_PER_SUBVOLUME) return run_per_subvolume(P, pos, mass, ws, acc, momentum, st);
+    // tuned before the first run of any mode, so that every mode uses the same tiles
     if (P->waves_per_cu == 0) {
         sr_status s = tune(P, pos, mass, ws, acc, st);
         if (s != SR_OK) return s;
     }
+    if (flags & SR_BATCH_PER_SUBVOLUME) return run_per_subvolume(P, pos, mass, ws, acc, momentum, st);
     if (flags & SR_BATCH_EAGER) return run_batched(P, pos, mass, ws, acc, momentum, st);
     const bool bound = P->exec && P->b_pos == pos && P->b_mass == mass && P->b_ws == ws &&
                        P->b_acc == acc && P->b_mom == momentum;
@@ -928,7 +978,8 @@ sr_status sr_batch_plan_info(const sr_batch_plan *P, char *buf, size_t buf_bytes
     o << "{\"B\": " << P->B << ", \"n\": " << P->offsets[P->B] << ", \"n_active\": "
       << P->total_active << ", \"cells\": " << P->L.NC << ", \"ws_bytes\": " << P->ws_bytes
       << ", \"waves_per_cu\": " << P->waves_per_cu << ", \"targets_per_lane\": "
-      << P->targets_per_lane << ", \"occupancy\": " << P->occupancy << ", \"tuned_ms\": "
+      << P->targets_per_lane << ", \"occupancy\": " << P->occupancy << ", \"sym_blocks\": "
+      << P->sym_blocks << ", \"sym_window\": " << P->sym_window << ", \"tuned_ms\": "
       << P->tuned_ms
       << ", \"tune_key\": \"" << P->tune_key << "\", \"graph\": " << (P->exec ? "true" : "false")
       << "}";

@@ -23,7 +23,7 @@
 namespace sr {
 namespace {
 
-constexpr int kBinBlocks = 512;  // workgroups of the binning pass
+constexpr int kBinBlocks = 1024;  // one-wave workgroups of the binning pass
 constexpr int kSumBlocks = 256;  // workgroups of the mass sum
 constexpr int kMaxBins = 2048;
 constexpr int kMaxGrid = 1024;  // ng^3 cell keys fit 30 bits
@@ -185,36 +185,71 @@ __global__ __launch_bounds__(256) void k_mass_final(const double *__restrict__ p
     if (threadIdx.x == 0) total[0] = s;
 }
 
-// Modes of the half spectrum (iz in [0, ng/2]) in x-major order, grid-stride.
+// Modes of the half spectrum (iz in [0, ng/2]), one wave per workgroup, each
+// taking whole rows (ix, iy) in a fixed order.  Along a row |n| grows with iz,
+// so the bins of 64 consecutive modes form runs: a segmented scan sums each
+// run in a fixed tree order and the run's last lane adds it to the
+// workgroup's bins in LDS (within a chunk every run has its own bin, so no two
+// lanes touch one bin at once, and chunks go in order).  The sums therefore
+// do not depend on scheduling: the spectrum is bitwise reproducible.
 // sinc2[i] = sinc^2(pi n_i / ng) for the mode index n_i of array index i.
-__global__ __launch_bounds__(256) void k_pk_bins(const float2 *__restrict__ c, int ng, int n_bins,
-                                                 double inv_dn, const double *__restrict__ sinc2,
-                                                 double *__restrict__ part)
+__global__ __launch_bounds__(64) void k_pk_bins(const float2 *__restrict__ c, int ng, int n_bins,
+                                                double inv_dn, const double *__restrict__ sinc2,
+                                                double *__restrict__ part)
 {
     extern __shared__ double bins[];  // [3][n_bins]: sum of w P', sum of w |n|, sum of w
-    for (int b = threadIdx.x; b < 3 * n_bins; b += 256) bins[b] = 0.0;
+    const int lane = threadIdx.x;
+    for (int b = lane; b < 3 * n_bins; b += kWave) bins[b] = 0.0;
     __syncthreads();
     const int nzh = ng / 2 + 1;
-    const int64_t total = (int64_t)ng * ng * nzh;
-    for (int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x; m < total; m += (int64_t)gridDim.x * 256) {
-        const int iz = (int)(m % nzh);
-        const int64_t r = m / nzh;
+    const int64_t rows = (int64_t)ng * ng;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
         const int iy = (int)(r % ng), ix = (int)(r / ng);
         const int nx = ix <= ng / 2 ? ix : ix - ng;
         const int ny = iy <= ng / 2 ? iy : iy - ng;
-        const double mag = sqrt((double)nx * nx + (double)ny * ny + (double)iz * iz);
-        const int b = (int)floor(mag * inv_dn);
-        if (mag == 0.0 || b >= n_bins) continue;
-        const float2 v = c[m];
-        const double w = (iz == 0 || 2 * iz == ng) ? 1.0 : 2.0;
-        const double win = sinc2[ix] * sinc2[iy] * sinc2[iz];
-        const double p = ((double)v.x * v.x + (double)v.y * v.y) / (win * win);
-        atomicAdd(&bins[b], w * p);
-        atomicAdd(&bins[n_bins + b], w * mag);
-        atomicAdd(&bins[2 * n_bins + b], w);
+        const double sxy = sinc2[ix] * sinc2[iy];
+        for (int z0 = 0; z0 < nzh; z0 += kWave) {
+            const int iz = z0 + lane;
+            double p = 0.0, km = 0.0, wt = 0.0;
+            int key = -1;  // outside every bin: k = 0, beyond the last bin, past the row
+            if (iz < nzh) {
+                const double mag = sqrt((double)nx * nx + (double)ny * ny + (double)iz * iz);
+                const int b = (int)floor(mag * inv_dn);
+                if (mag != 0.0 && b < n_bins) {
+                    const float2 v = c[r * nzh + iz];
+                    const double w = (iz == 0 || 2 * iz == ng) ? 1.0 : 2.0;
+                    const double win = sxy * sinc2[iz];
+                    p = w * (((double)v.x * v.x + (double)v.y * v.y) / (win * win));
+                    km = w * mag;
+                    wt = w;
+                    key = b;
+                } else if (mag != 0.0) {
+                    key = n_bins;
+                }
+            }
+            const int prev = __shfl_up(key, 1);
+            const uint64_t heads = __ballot(lane == 0 || prev != key);
+            const uint64_t upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1));
+            const int first = 63 - __clzll(upto);  // first lane of this lane's run
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const double yp = __shfl_up(p, o), yk = __shfl_up(km, o), yw = __shfl_up(wt, o);
+                if (lane - o >= first) {
+                    p += yp;
+                    km += yk;
+                    wt += yw;
+                }
+            }
+            const int next = __shfl_down(key, 1);
+            if ((lane == 63 || next != key) && key >= 0 && key < n_bins) {
+                bins[key] += p;
+                bins[n_bins + key] += km;
+                bins[2 * n_bins + key] += wt;
+            }
+        }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < 3 * n_bins; b += 256) part[(int64_t)blockIdx.x * 3 * n_bins + b] = bins[b];
+    for (int b = lane; b < 3 * n_bins; b += kWave) part[(int64_t)blockIdx.x * 3 * n_bins + b] = bins[b];
 }
 
 // P(bin) = box^3 / M^2 * sum(w P') / sum(w), k = 2 pi / box * sum(w |n|) / sum(w).
@@ -473,7 +508,7 @@ sr_status sr_power_spectrum(sr_pk_plan *P, const float *pos, const float *mass, 
     (void)rocfft_execution_info_destroy(info);
     if (!ok) return SR_E_DEVICE;
     double *part = reinterpret_cast<double *>(w + P->part_off);
-    k_pk_bins<<<kBinBlocks, 256, sizeof(double) * 3 * P->n_bins, s>>>(
+    k_pk_bins<<<kBinBlocks, kWave, sizeof(double) * 3 * P->n_bins, s>>>(
         reinterpret_cast<const float2 *>(w + P->grid_off), P->ng, P->n_bins, 1.0 / P->dn,
         reinterpret_cast<const double *>(w + P->sinc_off), part);
     k_pk_final<<<(unsigned)((P->n_bins + 255) / 256), 256, 0, s>>>(

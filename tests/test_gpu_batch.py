@@ -141,6 +141,10 @@ def test_tune_cache_roundtrip(tmp_path):
     p2 = sr.BatchPlan(b.offsets, b.n_active, b.problems, tune_cache=path)
     a2, _ = run(p2, b, "graph", momentum=False)
     assert p2.info()["waves_per_cu"] == w1
+    # the tuner also picks the symmetric tiles (blocks per item, window; 0 blocks = off)
+    t1 = (p1.info()["sym_blocks"], p1.info()["sym_window"])
+    assert t1 in {(16, 512), (16, 256), (64, 512), (4, 512), (0, 512)}
+    assert (p2.info()["sym_blocks"], p2.info()["sym_window"]) == t1
     assert np.array_equal(a1.view(np.uint32), a2.view(np.uint32))
     import json
     assert p1.info()["tune_key"] in json.load(open(path))
@@ -155,4 +159,36 @@ def test_batch_force_rejects_unknown_flags():
     fake = C.c_void_p(0x10000)
     assert L.sr_batch_force(plan._plan, fake, fake, fake, plan.ws_bytes, fake, None, 8, None) == 1
     assert L.sr_batch_force(plan._plan, fake, fake, None, plan.ws_bytes, fake, None, 4, None) == 2
+    plan.close()
+
+
+def test_dense_batch_symmetric_tiles_agree_bitwise():
+    # subvolumes with dense cells: the symmetric tiles run in the batched launch
+    # (the workspace header records it) and give the same bits as one launch
+    # sequence per subvolume; each subvolume matches the oracle
+    parts = [synth.clustered_box(65536, 40.0, 61, 0),
+             synth.clustered_box(150000, 40.0, 80, 5, halo_frac=0.5, mass_range=(1e2, 1e4))]
+    pos = np.concatenate([p.pos for p in parts]).astype(np.float32)
+    mass = np.concatenate([p.mass for p in parts]).astype(np.float32)
+    offsets = np.concatenate([[0], np.cumsum([p.n for p in parts])]).astype(np.int64)
+    n_act = np.array([p.n_active for p in parts], np.int64)
+    b = synth.Batch("dense", pos, mass, offsets, n_act, [p.problem for p in parts])
+    plan = sr.BatchPlan(b.offsets, b.n_active, b.problems)
+    announce(f"dense batch n={b.pos.shape[0]}")
+    ws = sr.new_workspace(plan.ws_bytes, DEV)
+    out = {}
+    for mode in ("per_subvolume", "graph"):
+        acc = torch.full((plan.total_active, 3), float("nan"), device=DEV)
+        plan.run(to_dev(b.pos), to_dev(b.mass), ws, acc, None, mode)
+        torch.cuda.synchronize()
+        out[mode] = acc.cpu().numpy()
+        if mode == "graph":
+            assert int(ws[4 * 518:4 * 519].view(torch.int32).item()) == 1  # symmetric tiles ran
+    assert np.array_equal(out["per_subvolume"].view(np.uint32), out["graph"].view(np.uint32))
+    row = 0
+    for k in range(b.size):
+        part = b.part(k)
+        ref, _ = oracle.force(part.pos, part.mass, part.n_active, part.problem)
+        assert_force_close(out["graph"][row: row + part.n_active], ref, what=f"dense subvolume {k}")
+        row += part.n_active
     plan.close()

@@ -64,10 +64,15 @@ def test_power_spectrum_matches_oracle(name, ng, dn):
     print(f"  max rel {rel.max():.3e} median {np.median(rel):.3e}", flush=True)
     assert rel.max() <= PK_RTOL
     assert np.all(p[~ok] == 0)
-    # a second run on the same plan and workspace: the deposit and the FFT repeat
-    # bit for bit; the float64 mode sums may add in another order inside a workgroup
-    p2 = plan.run(to_dev(pos), to_dev(mass), ws)[0].cpu().numpy()
-    np.testing.assert_allclose(p2, p, rtol=1e-12)
+    # runs on the same plan and on a fresh workspace repeat bit for bit: the
+    # deposit, the FFT and the mode sums all add in a fixed order
+    p2, k2, m2 = (t.cpu().numpy() for t in plan.run(to_dev(pos), to_dev(mass), ws))
+    ws3 = sr.new_workspace(plan.ws_bytes, DEV)
+    p3 = plan.run(to_dev(pos), to_dev(mass), ws3)[0].cpu().numpy()
+    assert np.array_equal(p2.view(np.uint64), p.view(np.uint64))
+    assert np.array_equal(k2.view(np.uint64), k.view(np.uint64))
+    assert np.array_equal(m2, modes)
+    assert np.array_equal(p3.view(np.uint64), p.view(np.uint64))
     plan.close()
 
 

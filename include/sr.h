@@ -458,7 +458,7 @@ sr_status sr_launch_config_kernel(const char *kernel /*host*/, int waves_per_cu,
  * (1..256; 0 switches the symmetric tiles off; -1 keeps the value); window:
  * sources per work item, 256 or 512 (-1 keeps).  Larger tiles need fewer
  * partial slots but make longer items.  The partial slots (12 bytes each)
- * fill the tail of the workspace: sr_workspace_bytes reserves about 11 per
+ * fill the tail of the workspace: sr_workspace_bytes reserves about 15 per
  * particle, and a larger workspace passed to sr_force / sr_force_vjp lends
  * its whole tail to them.  A problem that needs more (very large cells) runs
  * without symmetric tiles.  Results differ from the one-sided sums only in rounding

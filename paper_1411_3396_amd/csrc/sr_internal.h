@@ -80,8 +80,12 @@ enum HdrWord : int {
 // pair of two dense particles is evaluated once, its two opposite terms kept
 // as partial sums in fixed slots and added up in a fixed order afterwards.
 constexpr int kSymDirs = 14;        // the cell itself and the 13 directions of the upper half stencil
-constexpr int kSymStride = 15;      // per cell: target slots, then source slots of the 14 directions
-constexpr int kSymSlotsPerParticle = 12;  // partial-slot pool: this many 12-byte slots per particle
+constexpr int kSymNdDirs = 27;      // all 27 directions: non-dense sources of a dense block
+constexpr int kSymSegs = kSymDirs + kSymNdDirs;  // source segments of a symmetric item
+// per cell: target slots, then source slots of its dense particles for the 14
+// directions, then source slots of its non-dense particles for the 27
+constexpr int kSymStride = 1 + kSymDirs + kSymNdDirs;
+constexpr int kSymSlotsPerParticle = 16;  // partial-slot pool: this many 12-byte slots per particle
 
 // Byte offsets of every buffer inside a workspace.
 struct Layout {

@@ -517,10 +517,10 @@ __device__ __forceinline__ int cell_items(int nt, bool two)
 // Work item: x = home cell, y = first target slot, z = targets,
 // w = lk | two << 3 | psrc << 4 | nd << 5 | seg << 6 (lk: log2 lanes per
 // target; two: two targets per lane; psrc: the targets are passive and their
-// sources are the active particles of the 27 cells only; nd: the targets are
-// dense and their sources here are only the non-dense particles of the 27
-// cells, the dense ones being summed by the symmetric tiles; seg: the problem
-// of a batch).
+// sources are the active particles of the 27 cells only; nd: symmetric tiles
+// run, the targets are non-dense and their sources here are only the
+// non-dense particles of the 27 cells, the pairs with a dense particle being
+// summed by the symmetric tiles; seg: the problem of a batch).
 __device__ __forceinline__ int item_word(int lk, int two, int psrc, int seg, int nd = 0)
 {
     return lk | (two << 3) | (psrc << 4) | (nd << 5) | (seg << 6);
@@ -546,7 +546,7 @@ __device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, 
     if (nt < kTargetsPerItem) {
         for (int t = 0; t < nt; t += kSparseGroup, ++k) {
             const int cn = min(kSparseGroup, nt - t);
-            items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg));
+            items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg, nd));
         }
         return k;
     }
@@ -558,7 +558,7 @@ __device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, 
     }
     for (int t = dense_end; t < nt; t += kSparseGroup, ++k) {
         const int cn = min(kSparseGroup, nt - t);
-        items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg));
+        items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg, nd));
     }
     return k;
 }
@@ -600,7 +600,7 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
     const SegParams &S = acc.get(acc.seg_of_cell(c));
     int ix, iy, iz;
     decode_cell(S, c, ix, iy, iz);
-    int64_t src = 0, src_act = 0, src_nd = 0;
+    int64_t src = 0, src_act = 0, src_nd = 0, src_act_nd = 0;
     for (int dx = -1; dx <= 1; ++dx) {
         int jx = ix + dx;
         if (jx < 0 || jx >= S.nc[0]) {
@@ -622,17 +622,21 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
                 const int cc = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
                 src += start[cc + 1] - start[cc];
                 if (np > 0) src_act += nact[cc];
-                if (sym) src_nd += start[cc + 1] - start[cc] - dense_count(nact[cc]);
+                if (sym) {
+                    src_nd += start[cc + 1] - start[cc] - dense_count(nact[cc]);
+                    src_act_nd += nact[cc] - dense_count(nact[cc]);
+                }
             }
         }
     }
-    // cost class from the cell's widest item: a group of min(nt, kSparseGroup) targets when sparse
-    const int n_items = cell_items(na, two) + cell_items(np, two);
-    // with symmetric tiles a dense block's own item sees only the non-dense sources
+    // cost class from the cell's widest item: a group of min(nt, kSparseGroup) targets when sparse.
+    // With symmetric tiles the dense blocks have no item here, and the other
+    // targets take only the non-dense sources (the symmetric tiles give them
+    // the terms of the dense ones)
     const int dn = sym ? dense_count(na) : 0;
-    int64_t cost = dn > 0 ? max(run_cost(dn, src_nd, two), run_cost(na - dn, src, two))
-                          : run_cost(na, src, two);
-    cost = max(cost, run_cost(np, src_act, two));
+    const int n_items = cell_items(na - dn, two) + cell_items(np, two);
+    int64_t cost = sym ? max(run_cost(na - dn, src_nd, two), run_cost(np, src_act_nd, two))
+                       : max(run_cost(na, src, two), run_cost(np, src_act, two));
     if (cost < 1) cost = 1;
     int cls = 63 - __clzll((unsigned long long)cost);
     cls = cls > 31 ? 31 : cls;
@@ -703,9 +707,12 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
     const int seg = acc.seg_of_cell(c);
     const uint32_t at = base[cls] + local;
     const int s0 = start[c];
-    // active targets (all sources), then for the adjoint the passive ones (active sources)
-    const int k = write_run(items, at, c, s0, na, two, seg, 0, hdr[kHdrSymOk] != 0 && dense_count(na) > 0);
-    if (!kActiveOnly) write_run(items, at + k, c, s0 + na, nt - na, two, seg, 1);
+    // active targets (all sources), then for the adjoint the passive ones (active sources);
+    // with symmetric tiles only the non-dense targets, against the non-dense sources
+    const int sym = hdr[kHdrSymOk] != 0 ? 1 : 0;
+    const int dn = sym ? dense_count(na) : 0;
+    const int k = write_run(items, at, c, s0 + dn, na - dn, two, seg, 0, sym);
+    if (!kActiveOnly) write_run(items, at + k, c, s0 + na, nt - na, two, seg, 1, sym);
 }
 
 // --------------------------------------------------------------- pair kernels
@@ -721,7 +728,8 @@ struct Stencil {
 // With act_only each cell contributes only its active particles (they lead
 // the cell): the sources of an item of passive targets.
 // With nd each cell contributes only its non-dense particles (those after its
-// dense blocks): the one-sided sources of a dense block.
+// dense blocks; with act_only its active ones): when symmetric tiles run, the
+// pairs with a dense source are theirs.
 __device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
                                               const int *__restrict__ start,
                                               const int *__restrict__ nact, bool act_only, int lane,
@@ -742,8 +750,9 @@ __device__ __forceinline__ void stencil_setup(const SegParams &S, int cell,
             const int c = S.cell_off + (jx * S.nc[1] + jy) * S.nc[2] + jz;
             st.nstart = start[c];
             if (nd) {
-                st.nstart += dense_count(nact[c]);
-                cnt = start[c + 1] - st.nstart;
+                const int d = dense_count(nact[c]);
+                st.nstart += d;
+                cnt = act_only ? nact[c] - d : start[c + 1] - st.nstart;
             } else {
                 cnt = act_only ? nact[c] : start[c + 1] - st.nstart;
             }
@@ -1418,16 +1427,27 @@ __device__ __forceinline__ bool cell_at(const SegParams &S, int ix, int iy, int 
     return true;
 }
 
-// Per cell c: partial-slot counts in cnt[15 c .. 15 c + 14] (target slots:
-// windows of c times its dense particles; source slots of direction e: runs
-// of the cell c - dir_e times the dense particles of c), its items as a home
-// cell (runs times windows) and their cost class in info[c], and the slot
+// Direction f of the full stencil (0..26): offsets (f / 9 - 1, (f / 3) % 3 - 1, f % 3 - 1).
+__device__ __forceinline__ void full_dir(int f, int &dx, int &dy, int &dz)
+{
+    dx = f / 9 - 1;
+    dy = (f / 3) % 3 - 1;
+    dz = f % 3 - 1;
+}
+
+// Per cell c, its row of kSymStride partial-slot counts in cnt: [0] target
+// slots (windows of c times its dense particles); [1 + e] source slots of
+// its dense particles for direction e of the half stencil (runs of the cell
+// c - dir_e times the dense particles); [15 + f] source slots of its
+// non-dense particles for direction f of the full stencil (runs of the cell
+// c - dir_f times the non-dense particles).  Also the item count and cost
+// class of c as a home cell (runs times windows) in info[c], and the slot
 // total of all cells (int64, header).
 template <class Acc>
-__global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *__restrict__ nact,
-                                                   int K, int W, int *__restrict__ cnt,
-                                                   uint32_t *__restrict__ info, uint32_t *hdr,
-                                                   uint32_t magic)
+__global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *__restrict__ start,
+                                                   const int *__restrict__ nact, int K, int W,
+                                                   int *__restrict__ cnt, uint32_t *__restrict__ info,
+                                                   uint32_t *hdr, uint32_t magic)
 {
     __shared__ uint32_t blk[kClasses];
     __shared__ unsigned long long tot;
@@ -1437,47 +1457,59 @@ __global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *_
     const bool ok = hdr[kHdrMagic] == magic;
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < NC) {
-        const int D = ok ? dense_count(nact[c]) : 0;
         int *row = cnt + (int64_t)kSymStride * c;
         uint32_t inf = 0;
         unsigned long long slots = 0;
-        if (D > 0) {
+        if (ok) {
+            const int D = dense_count(nact[c]);
+            const int ND = start[c + 1] - start[c] - D;
             const SegParams &S = acc.get(acc.seg_of_cell(c));
             int ix, iy, iz;
             decode_cell(S, c, ix, iy, iz);
             int64_t sv = 0;
+            auto runs_of = [&](int a) { return (dense_count(nact[a]) / kWave + K - 1) / K; };
             for (int e = 0; e < kSymDirs; ++e) {
                 int dx, dy, dz, b;
                 float sx, sy, sz;
                 half_dir(e, dx, dy, dz);
-                if (cell_at(S, ix, iy, iz, dx, dy, dz, b, sx, sy, sz)) sv += dense_count(nact[b]);
+                if (D > 0 && cell_at(S, ix, iy, iz, dx, dy, dz, b, sx, sy, sz)) sv += dense_count(nact[b]);
                 int64_t sc = 0;
-                if (cell_at(S, ix, iy, iz, -dx, -dy, -dz, b, sx, sy, sz)) {
-                    const int nba = dense_count(nact[b]) / kWave;
-                    sc = (int64_t)((nba + K - 1) / K) * D;
-                }
+                if (D > 0 && cell_at(S, ix, iy, iz, -dx, -dy, -dz, b, sx, sy, sz)) sc = (int64_t)runs_of(b) * D;
                 row[1 + e] = (int)min(sc, (int64_t)INT32_MAX);
                 slots += (unsigned long long)sc;
             }
-            const int nb = D / kWave;
-            const int64_t C = (sv + W - 1) / W;
-            const int64_t G = (nb + K - 1) / K;
-            row[0] = (int)min(C * D, (int64_t)INT32_MAX);
-            slots += (unsigned long long)(C * D);
-            const int64_t n_items = G * C;
-            // tile steps of the widest item: its blocks times its window
-            int64_t cost = (int64_t)min(nb, K) * min((int64_t)W, sv);
-            if (cost < 1) cost = 1;
-            int cls = 63 - __clzll((unsigned long long)cost);
-            cls = cls > 31 ? 31 : cls;
-            if (n_items < (int64_t(1) << 27)) {
-                inf = ((uint32_t)n_items << 5) | (uint32_t)cls;
-                atomicAdd(&blk[cls], (uint32_t)n_items);
-            } else {
-                slots = ~0ull >> 2;  // beyond any pool: the symmetric tiles stay off
+            for (int f = 0; f < kSymNdDirs; ++f) {
+                int dx, dy, dz, b;
+                float sx, sy, sz;
+                full_dir(f, dx, dy, dz);
+                if (D > 0 && cell_at(S, ix, iy, iz, dx, dy, dz, b, sx, sy, sz))
+                    sv += start[b + 1] - start[b] - dense_count(nact[b]);
+                int64_t sc = 0;
+                if (ND > 0 && cell_at(S, ix, iy, iz, -dx, -dy, -dz, b, sx, sy, sz)) sc = (int64_t)runs_of(b) * ND;
+                row[1 + kSymDirs + f] = (int)min(sc, (int64_t)INT32_MAX);
+                slots += (unsigned long long)sc;
+            }
+            row[0] = 0;
+            if (D > 0) {
+                const int nb = D / kWave;
+                const int64_t C = (sv + W - 1) / W;
+                const int64_t G = (nb + K - 1) / K;
+                row[0] = (int)min(C * D, (int64_t)INT32_MAX);
+                slots += (unsigned long long)(C * D);
+                const int64_t n_items = G * C;
+                // tile steps of the widest item: its blocks times its window
+                int64_t cost = (int64_t)min(nb, K) * min((int64_t)W, sv);
+                if (cost < 1) cost = 1;
+                int cls = 63 - __clzll((unsigned long long)cost);
+                cls = cls > 31 ? 31 : cls;
+                if (n_items < (int64_t(1) << 27)) {
+                    inf = ((uint32_t)n_items << 5) | (uint32_t)cls;
+                    atomicAdd(&blk[cls], (uint32_t)n_items);
+                } else {
+                    slots = ~0ull >> 2;  // beyond any pool: the symmetric tiles stay off
+                }
             }
         } else {
-#pragma unroll
             for (int e = 0; e < kSymStride; ++e) row[e] = 0;
         }
         info[c] = inf;
@@ -1540,9 +1572,13 @@ __global__ __launch_bounds__(256) void k_sym_write(Acc acc, int NC, const int *_
         for (int k = 0; k < C; ++k) items[at + (uint32_t)(g * C + k)] = make_int4(c, g, k, seg);
 }
 
-// The 14 source segments of a symmetric item, one per lane (lanes 0..13):
-// first binned slot and dense count of the cell in direction e, prefix of the
-// counts, centre shift, and the base of its source slots for direction e.
+// The source segments of a symmetric item, one per lane: lanes 0..13 the
+// dense particles of the cell itself and of its 13 upper-half neighbours
+// (each such pair once), lanes 14..40 the non-dense particles of all 27
+// cells of its stencil (none of them is ever a symmetric target, so each of
+// those pairs is met once too).  Per segment: first binned slot, count,
+// prefix of the counts, centre shift, and the base of the source slots its
+// particles receive from this cell.
 struct SymStencil {
     int nstart, cnt, excl, sbase;
     float sx, sy, sz;
@@ -1561,23 +1597,27 @@ __device__ __forceinline__ void sym_stencil_setup(const SegParams &S, int cell,
     st.cnt = 0;
     st.sbase = 0;
     st.sx = st.sy = st.sz = 0.f;
-    if (lane < kSymDirs) {
+    if (lane < kSymSegs) {
         int dx, dy, dz, b;
-        half_dir(lane, dx, dy, dz);
+        if (lane < kSymDirs)
+            half_dir(lane, dx, dy, dz);
+        else
+            full_dir(lane - kSymDirs, dx, dy, dz);
         if (cell_at(S, ix, iy, iz, dx, dy, dz, b, st.sx, st.sy, st.sz)) {
-            st.nstart = start[b];
-            st.cnt = dense_count(nact[b]);
+            const int d = dense_count(nact[b]);
+            st.nstart = start[b] + (lane < kSymDirs ? 0 : d);
+            st.cnt = lane < kSymDirs ? d : start[b + 1] - start[b] - d;
             st.sbase = sym_base[(int64_t)kSymStride * b + 1 + lane];
         }
     }
     int incl = st.cnt;
 #pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
+    for (int d = 1; d < kWave; d <<= 1) {
         const int y = __shfl_up(incl, d);
         if (lane >= d) incl += y;
     }
     st.excl = incl - st.cnt;
-    st.total = __builtin_amdgcn_readfirstlane(__shfl(incl, kSymDirs - 1));
+    st.total = __builtin_amdgcn_readfirstlane(__shfl(incl, kSymSegs - 1));
 }
 
 // Segment of virtual source v (clamped to the list); every lane must call it.
@@ -1586,10 +1626,10 @@ __device__ __forceinline__ int sym_locate(const SymStencil &st, int v)
     const int vv = min(v, st.total - 1);
     int q = 0;
 #pragma unroll
-    for (int step = 8; step >= 1; step >>= 1) {
+    for (int step = 32; step >= 1; step >>= 1) {
         const int cand = q + step;
-        const int e = __shfl(st.excl, min(cand, kSymDirs - 1));
-        if (cand < kSymDirs && e <= vv) q = cand;
+        const int e = __shfl(st.excl, min(cand, kSymSegs - 1));
+        if (cand < kSymSegs && e <= vv) q = cand;
     }
     return q;
 }
@@ -2010,11 +2050,14 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, co
                                              tile_p, tile_g, tix, red, pull_limit);
 }
 
-// Adds the partial slots of every dense particle, in a fixed order (its target
-// slots over the windows, then its source slots over the directions and
-// runs), to the row its one-sided item wrote: out[row] += m0 * sum (m0 the
-// common mass when every mass is equal, else 1).  rows: out_row (forward,
-// n_out = rows of acc) or perm (adjoint, n_out = N).
+// Adds up the partial slots of every particle, in a fixed order.  A dense
+// particle: its target slots over the windows, then its source slots over
+// the 14 directions and runs; it has no one-sided item, so the sum is its
+// row (out[row] = m0 * sum).  A non-dense particle: its source slots over the
+// 27 directions and runs, added to the row its one-sided item wrote
+// (out[row] += m0 * sum).  m0 is the common mass when every mass is equal,
+// else 1.  rows: out_row (forward, n_out = rows of acc; passive particles
+// have none) or perm (adjoint, n_out = N).
 __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const int *__restrict__ key,
                                                     const int *__restrict__ start,
                                                     const int *__restrict__ nact,
@@ -2028,12 +2071,15 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= N || hdr[kHdrSymOk] == 0) return;
+    const int r = rows[b];
+    if (r < 0 || r >= n_out) return;
     const int c = key[b] >> key_bits;
     const int jl = b - start[c];
     const int D = dense_count(nact[c]);
-    if (jl >= D) return;
-    const int r = rows[b];
-    if (r < 0 || r >= n_out) return;
+    const bool dense = jl < D;
+    const int per = dense ? D : start[c + 1] - start[c] - D;  // particles of a slot row
+    const int j = dense ? jl : jl - D;
+    const int e0 = dense ? 0 : 1 + kSymDirs, e1 = dense ? 1 + kSymDirs : kSymStride;
     const int *cn = sym_cnt + (int64_t)kSymStride * c;
     const int *bs = sym_base + (int64_t)kSymStride * c;
     struct F3 {
@@ -2043,14 +2089,14 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
     // four running sums over the slots of a row group (loads in flight
     // together), combined in a fixed order at the end
     float x[4] = {0.f, 0.f, 0.f, 0.f}, y[4] = {0.f, 0.f, 0.f, 0.f}, z[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int e = 0; e < kSymStride; ++e) {
-        const int n = cn[e] / D;
-        int64_t o = (int64_t)bs[e] + jl;
+    for (int e = e0; e < e1; ++e) {
+        const int n = cn[e] / per;
+        int64_t o = (int64_t)bs[e] + j;
         int t = 0;
-        for (; t + 4 <= n; t += 4, o += 4 * (int64_t)D) {
+        for (; t + 4 <= n; t += 4, o += 4 * (int64_t)per) {
             F3 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = P[o + u * (int64_t)D];
+            for (int u = 0; u < 4; ++u) v[u] = P[o + u * (int64_t)per];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 x[u] += v[u].x;
@@ -2058,7 +2104,7 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
                 z[u] += v[u].z;
             }
         }
-        for (; t < n; ++t, o += D) {
+        for (; t < n; ++t, o += per) {
             const F3 v = P[o];
             x[0] += v.x;
             y[0] += v.y;
@@ -2070,9 +2116,15 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
     const float sz = (z[0] + z[1]) + (z[2] + z[3]);
     const float m0 = hdr[kHdrMassInfo] == 0 ? mass[0] : 1.0f;
     const int64_t q = 3 * (int64_t)r;
-    out[q] += m0 * sx;
-    out[q + 1] += m0 * sy;
-    out[q + 2] += m0 * sz;
+    if (dense) {
+        out[q] = m0 * sx;
+        out[q + 1] = m0 * sy;
+        out[q + 2] = m0 * sz;
+    } else {
+        out[q] += m0 * sx;
+        out[q + 1] += m0 * sy;
+        out[q + 2] += m0 * sz;
+    }
 }
 
 // --------------------------------------------------------------- A8: momentum
@@ -2194,7 +2246,8 @@ hipError_t build_sym(const DevArgs &a)
     const int W = a.sym_window;
     return with_acc(a, [&](auto acc) -> hipError_t {
         const unsigned nb = blocks_for(L.NC, 256);
-        k_sym_count<<<nb, 256, 0, a.st>>>(acc, (int)L.NC, at<int>(a, L.nact), a.sym_blocks, W,
+        k_sym_count<<<nb, 256, 0, a.st>>>(acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact),
+                                          a.sym_blocks, W,
                                           at<int>(a, L.sym_cnt), at<uint32_t>(a, L.sym_info), hdr,
                                           L.magic());
         hipError_t e2 = hipGetLastError();

@@ -121,7 +121,7 @@ def test_symmetric_tiles_random_filter_dense():
 
 def test_partial_slots_beyond_the_pool_fall_back():
     # 27 cells of about 2000 particles need ~83 partial slots per particle:
-    # with the workspace sr_workspace_bytes gives (about 11 per particle) the
+    # with the workspace sr_workspace_bytes gives (about 15 per particle) the
     # tiles stay off and the one-sided kernels sum every pair; a larger
     # workspace lends its tail to the slots and the tiles run
     w = synth.uniform_box(27 * 2000, 9.3, 11)

@@ -4,13 +4,18 @@
 //
 // Device passes: the deposit into the FFT's padded in-place layout, a
 // float64 mass sum in a fixed order, the FFT (rocFFT, in place), and the
-// binning.  The deposit is atomic-free: particles are sorted by the cell of
-// their lower corner point (the binning's radix sort), a segmented scan sums
-// each cell's corner contributions per wave, and every grid point adds the
+// binning.  Two deposits, both reproducible bit for bit.  For ng a multiple of
+// 8, particles are sorted by brick of 8^3 cells and each run of a brick's
+// particles sums its weights exactly, in fixed point, into a tile of grid
+// points in LDS (below).  Otherwise particles are sorted by the cell of their
+// lower corner point (the binning's radix sort), a segmented scan sums each
+// cell's corner contributions per wave, and every grid point adds the
 // partials of its 8 cells in float64, in a fixed order.  Binning: every mode of
 // the half spectrum adds w |rho_k|^2 / W(k)^2 (w = 2 for modes whose mirror
-// is not stored) into per-workgroup float64 bins in LDS; a last pass adds
-// the workgroups' bins in workgroup order.
+// is not stored) into per-wave float64 bins in LDS by segmented sums along
+// rows; a workgroup adds its waves' bins in wave order, and a last pass adds
+// the workgroups' partials with a fixed tree.  The spectrum is reproducible
+// bit for bit too.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -23,7 +28,7 @@
 namespace sr {
 namespace {
 
-constexpr int kBinBlocks = 1024;  // one-wave workgroups of the binning pass
+constexpr int kBinBlocks = 1024;  // workgroups of the binning pass
 constexpr int kSumBlocks = 256;  // workgroups of the mass sum
 constexpr int kMaxBins = 2048;
 constexpr int kMaxGrid = 1024;  // ng^3 cell keys fit 30 bits
@@ -43,15 +48,19 @@ __global__ __launch_bounds__(256) void k_cic_key(const float *__restrict__ pos,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         float u = pos[3 * (int64_t)i + d] * inv_h;
-        u = u - floorf(u / fng) * fng;
-        int k = (int)floorf(u);
-        float fr = u - (float)k;
-        if (k >= ng) {
-            k = 0;
+        // for 0 <= u < ng, u / ng rounds below 1, so the wrap is the identity
+        if (!(u >= 0.f && u < fng)) u = u - floorf(u / fng) * fng;
+        float fk = floorf(u);
+        float fr = u - fk;
+        // u rounded up to ng wraps to 0; a NaN (from a non-finite position)
+        // takes cell 0 and keeps its NaN weights
+        if (fk >= fng || fk < 0.f) {
+            fk = 0.f;
             fr = 0.f;
+        } else if (fk != fk) {
+            fk = 0.f;
         }
-        if (k < 0) k = 0;
-        i0[d] = k;
+        i0[d] = (int)fk;
         f[d] = fr;
     }
     key[i] = (i0[0] * ng + i0[1]) * ng + i0[2];
@@ -152,6 +161,402 @@ __global__ __launch_bounds__(256) void k_cic_points(const int *__restrict__ csta
     grid[((int64_t)ix * ng + iy) * pad + iz] = (float)sum;
 }
 
+// ------------------------------------------------------------ brick deposit
+//
+// For grids whose side is a multiple of 8 the deposit works per brick of 8^3
+// cells.  Particles are sorted by brick only (a key of 3 log2(ng / 8) bits, so
+// fewer radix passes than a sort by cell), and the passes move each particle's
+// 16-byte payload along with its key, so no gather follows the sort.  Each
+// workgroup then adds the 8 corner weights of up to kChunk consecutive
+// particles of one brick into a 9^3 tile of grid points in LDS, and a last pass
+// adds, for every grid point, the tiles that cover it.
+//
+// Tile sums are exact integers: a weight c = m w_x w_y w_z (float32 products,
+// as in the cell deposit) is scaled by S = 2^(62 - e), where e bounds
+// kChunk max|m| < 2^e, and split into x = c S = hi + lo 2^-32 with hi =
+// floor(x) and lo = round((x - hi) 2^32).  |x| < 2^51, so hi sums over a
+// chunk stay below 2^62 in magnitude and lo sums below 2^43, and integer sums do not depend on their order,
+// so every tile is the same whatever order the LDS atomics land in.  x is exact
+// in float64 (c has 24 significant bits, S is a power of two), so only weights
+// below 2^(e - 71) lose bits, by at most 2^(e - 95).  A tile point holds
+// hi / S + lo / (2^32 S), computed in float64 and rounded to float32; chunk boundaries are fixed by
+// the stable sort, and the last pass adds the tiles in a fixed order in float64.
+// A non-finite weight makes its whole tile NaN, so it still reaches the
+// spectrum.
+
+constexpr int kBrick = 8;                                   // cells per brick side
+constexpr int kTile = kBrick + 1;                           // grid points per tile side
+constexpr int kTilePts = kTile * kTile * kTile;             // 729
+constexpr int kChunk = 2048;                                // most particles per workgroup
+constexpr int kSortThreads = 256;                           // four waves per sort tile
+constexpr int kSortSteps = kRadixTile / kSortThreads;
+constexpr double kMagic52 = 6755399441055744.0;             // 1.5 * 2^52
+
+// Brick of particle i (the sort key) and its payload (lu_x, lu_y, lu_z, m), lu
+// the coordinate in grid units from the brick's lower corner.  u wraps by the
+// cell deposit's rule; lu = u - 8 b is exact (Sterbenz), so floor(lu) and
+// lu - floor(lu) are the cell deposit's cell offset and fraction bit for bit.
+__device__ __forceinline__ void brick_of(const float *__restrict__ pos, const float *__restrict__ mass,
+                                         int64_t i, int ng, float inv_h, int &key, float4 &v)
+{
+    const float fng = (float)ng;
+    const int nb = ng / kBrick;
+    int b[3];
+    float lu[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float u = pos[3 * i + d] * inv_h;
+        // for 0 <= u < ng, u / ng rounds below 1, so the wrap is the identity
+        if (!(u >= 0.f && u < fng)) u = u - floorf(u / fng) * fng;
+        float fk = floorf(u);
+        // u rounded up to ng wraps to 0; a NaN (from a non-finite position)
+        // takes brick 0 and keeps its NaN payload
+        if (fk >= fng || fk < 0.f) {
+            fk = 0.f;
+            u = 0.f;
+        } else if (fk != fk) {
+            fk = 0.f;
+        }
+        const int k = (int)fk;
+        b[d] = k / kBrick;
+        lu[d] = u - (float)(b[d] * kBrick);
+    }
+    key = (b[0] * nb + b[1]) * nb + b[2];
+    v = make_float4(lu[0], lu[1], lu[2], mass[i]);
+}
+
+// Keys and payloads of one tile of kRadixTile particles, the first sort
+// pass's digit counts of the tile (table[d * ntiles + tile]), and the tile's
+// float64 mass sum (a fixed order per thread, then a fixed tree) and largest
+// |m|.
+__global__ __launch_bounds__(kSortThreads) void k_brick_hist0(const float *__restrict__ pos,
+                                                              const float *__restrict__ mass, int n,
+                                                              int ng, float inv_h, int bits,
+                                                              int *__restrict__ table, int ntiles,
+                                                              int *__restrict__ keys,
+                                                              float4 *__restrict__ vals,
+                                                              double *__restrict__ msum,
+                                                              float *__restrict__ mmax)
+{
+    __shared__ int h[256];
+    __shared__ double ls[kSortThreads];
+    __shared__ float lm[kSortThreads];
+    const int tid = threadIdx.x;
+    const int R = 1 << bits;
+    if (tid < R) h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    double s = 0.0;
+    float mx = 0.f;
+    for (int r = 0; r < kSortSteps; ++r) {
+        const int64_t i = base + r * kSortThreads + tid;
+        if (i < n) {
+            int key;
+            float4 v;
+            brick_of(pos, mass, i, ng, inv_h, key, v);
+            keys[i] = key;
+            vals[i] = v;
+            atomicAdd(&h[key & (R - 1)], 1);
+            s += (double)v.w;
+            mx = fmaxf(mx, fabsf(v.w));
+        }
+    }
+    ls[tid] = s;
+    lm[tid] = mx;
+    __syncthreads();
+    for (int o = kSortThreads / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            ls[tid] += ls[tid + o];
+            lm[tid] = fmaxf(lm[tid], lm[tid + o]);
+        }
+        __syncthreads();
+    }
+    if (tid < R) table[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+    if (tid == 0) {
+        msum[blockIdx.x] = ls[0];
+        mmax[blockIdx.x] = lm[0];
+    }
+}
+
+// Later sort passes, histogram side: digit counts of one tile of keys.
+__global__ __launch_bounds__(kSortThreads) void k_brick_hist(const int *__restrict__ keys, int n, int shift,
+                                                             int bits, int *__restrict__ table, int ntiles)
+{
+    __shared__ int h[256];
+    const int R = 1 << bits;
+    if ((int)threadIdx.x < R) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int r = 0; r < kSortSteps; ++r) {
+        const int64_t i = base + r * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (R - 1)], 1);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < R) table[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile: each wave ranks 64 particles at a time within
+// their digit (one ballot per digit bit, per-wave digit counters), the tile is
+// reordered by digit in LDS keeping input order inside a digit, and each
+// digit's run is written to consecutive addresses from the scanned table.
+__global__ __launch_bounds__(kSortThreads) void k_brick_scatter(
+    const int *__restrict__ keys_in, const float4 *__restrict__ v_in, int n, int shift, int bits,
+    const int *__restrict__ table_x, int ntiles, int *__restrict__ keys_out, float4 *__restrict__ v_out)
+{
+    constexpr int kWaves = kSortThreads / kWave;
+    constexpr int kPerWave = kRadixTile / kWaves;
+    __shared__ int cnt[kWaves][256];
+    __shared__ int lstart[256];
+    __shared__ int gstart[256];
+    __shared__ int wsum[kWaves];
+    __shared__ int lkey[kRadixTile];
+    __shared__ float4 lv[kRadixTile];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int R = 1 << bits;
+    const int tile = blockIdx.x;
+    gstart[tid] = tid < R ? table_x[(int64_t)tid * ntiles + tile] : 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t tile0 = (int64_t)tile * kRadixTile;
+    const int64_t base = tile0 + (int64_t)wv * kPerWave;
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int key[kSortSteps], rk[kSortSteps];
+    float4 v[kSortSteps];
+#pragma unroll
+    for (int r = 0; r < kSortSteps; ++r) {
+        const int64_t e = base + r * kWave + lane;
+        const bool valid = e < n;
+        key[r] = 0;
+        v[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (valid) {
+            key[r] = keys_in[e];
+            v[r] = v_in[e];
+        }
+        const int d = (key[r] >> shift) & (R - 1);
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & below);
+        const int before = cnt[wv][d];
+        rk[r] = valid ? before + rank : -1;
+        __syncthreads();
+        if (valid && rank == 0) cnt[wv][d] = before + __popcll(peers);
+        __syncthreads();
+    }
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int c = cnt[w][tid];
+        cnt[w][tid] = tot;
+        tot += c;
+    }
+    int incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    int prior = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) prior += w < wv ? wsum[w] : 0;
+    lstart[tid] = prior + incl - tot;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortSteps; ++r) {
+        if (rk[r] >= 0) {
+            const int d = (key[r] >> shift) & (R - 1);
+            const int at = lstart[d] + cnt[wv][d] + rk[r];
+            lkey[at] = key[r];
+            lv[at] = v[r];
+        }
+    }
+    __syncthreads();
+    const int n_tile = (int)min((int64_t)kRadixTile, (int64_t)n - tile0);
+    for (int i = tid; i < n_tile; i += kSortThreads) {
+        const int k = lkey[i];
+        const int d = (k >> shift) & (R - 1);
+        const int dest = gstart[d] + (i - lstart[d]);
+        keys_out[dest] = k;
+        v_out[dest] = lv[i];
+    }
+}
+
+// Total mass (the tiles' sums in tile order, then a fixed tree) into out[0]
+// and the largest |m| into out[1].
+__global__ __launch_bounds__(256) void k_brick_mass(const double *__restrict__ msum,
+                                                    const float *__restrict__ mmax, int tiles,
+                                                    double *__restrict__ out)
+{
+    __shared__ double ls[256];
+    __shared__ float lm[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    float mx = 0.f;
+    for (int t = tid; t < tiles; t += 256) {
+        s += msum[t];
+        mx = fmaxf(mx, mmax[t]);
+    }
+    ls[tid] = s;
+    lm[tid] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            ls[tid] += ls[tid + o];
+            lm[tid] = fmaxf(lm[tid], lm[tid + o]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[0] = ls[0];
+        out[1] = (double)lm[0];
+    }
+}
+
+// Workgroups of each brick: ceil(particles / kChunk), none for an empty brick.
+__global__ __launch_bounds__(256) void k_brick_chunks(const int *__restrict__ bstart, int nbricks,
+                                                      int *__restrict__ chunks)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nbricks) return;
+    const int np = bstart[b + 1] - bstart[b];
+    chunks[b] = (np + kChunk - 1) / kChunk;
+}
+
+// Every chunk's record: its brick and its range of sorted particles.
+__global__ __launch_bounds__(256) void k_brick_owner(const int *__restrict__ bstart,
+                                                     const int *__restrict__ cbase, int nbricks,
+                                                     int4 *__restrict__ rec)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nbricks) return;
+    const int s0 = bstart[b], s1 = bstart[b + 1];
+    for (int w = cbase[b], p = s0; w < cbase[b + 1]; ++w, p += kChunk)
+        rec[w] = make_int4(b, p, min(p + kChunk, s1), 0);
+}
+
+// One chunk of one brick: exact integer corner sums in a 9^3 LDS tile, then
+// the tile as float32 into chunk slot w of ctile.  Launched with at least as
+// many workgroups as chunks; the others leave at once.
+__global__ __launch_bounds__(256) void k_brick_tile(const int *__restrict__ cbase, int nbricks,
+                                                    const int4 *__restrict__ rec,
+                                                    const float4 *__restrict__ v_sorted,
+                                                    const double *__restrict__ mstat,
+                                                    float *__restrict__ ctile)
+{
+    __shared__ unsigned long long thi[kTilePts];
+    __shared__ unsigned long long tlo[kTilePts];
+    __shared__ int bad;  // a non-finite weight: the whole tile becomes NaN
+    const int w = blockIdx.x;
+    // independent loads: the chunk count, this chunk's record, the mass bound
+    const int nchunks = cbase[nbricks];
+    const int4 r = rec[min(w, nchunks > 0 ? nchunks - 1 : 0)];
+    const double mmax = mstat[1];
+    if (w >= nchunks) return;  // uniform over the workgroup
+    for (int t = threadIdx.x; t < kTilePts; t += 256) {
+        thi[t] = 0ull;
+        tlo[t] = 0ull;
+    }
+    if (threadIdx.x == 0) bad = 0;
+    int e = 0;
+    const double bound = (double)kChunk * mmax;
+    if (bound > 0.0) (void)frexp(bound, &e);  // bound < 2^e
+    const double S = ldexp(1.0, 62 - e);
+    __syncthreads();
+    for (int p = r.y + (int)threadIdx.x; p < r.z; p += 256) {
+        const float4 v = v_sorted[p];
+        // offsets in [0, 7] for any payload (fmaxf drops a NaN; its weights stay NaN)
+        const float lx = fminf(fmaxf(floorf(v.x), 0.f), 7.f);
+        const float ly = fminf(fmaxf(floorf(v.y), 0.f), 7.f);
+        const float lz = fminf(fmaxf(floorf(v.z), 0.f), 7.f);
+        const float fx = v.x - lx, fy = v.y - ly, fz = v.z - lz;
+        const int base = ((int)lx * kTile + (int)ly) * kTile + (int)lz;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float wx = (k & 4) ? fx : 1.f - fx;
+            const float wy = (k & 2) ? fy : 1.f - fy;
+            const float wz = (k & 1) ? fz : 1.f - fz;
+            const double x = (double)(v.w * wx * wy * wz) * S;
+            if (!(fabs(x) < 2251799813685248.0)) {  // NaN, or not below 2^51
+                bad = 1;
+                continue;
+            }
+            // integer-valued doubles of magnitude below 2^51 to int64: added to
+            // 1.5 * 2^52 they land in [2^52, 2^53), where the low bits of the
+            // representation are the integer (exact); for r 2^32 the same add
+            // rounds to the nearest integer, as rint would
+            const double xh = floor(x);
+            const double r = x - xh;
+            const int at = base + (k >> 2) * kTile * kTile + ((k >> 1) & 1) * kTile + (k & 1);
+            const long long hi = __double_as_longlong(xh + kMagic52) - __double_as_longlong(kMagic52);
+            const long long lo = __double_as_longlong(fma(r, 4294967296.0, kMagic52)) -
+                                 __double_as_longlong(kMagic52);
+            if (hi != 0) atomicAdd(&thi[at], (unsigned long long)hi);
+            if (lo != 0) atomicAdd(&tlo[at], (unsigned long long)lo);
+        }
+    }
+    __syncthreads();
+    float *out = ctile + (int64_t)w * kTilePts;
+    const double inv_s = 1.0 / S, inv_s32 = inv_s / 4294967296.0;
+    const float nan = __int_as_float(0x7fc00000);
+    for (int t = threadIdx.x; t < kTilePts; t += 256)
+        out[t] = bad ? nan : (float)((double)(long long)thi[t] * inv_s + (double)tlo[t] * inv_s32);
+}
+
+// Grid point (ix, iy, iz): per axis, its own brick at offset i mod 8 and, for
+// i mod 8 == 0, also the brick below at tile index 8; the chunk tiles of those
+// (up to 8) bricks are added in a fixed order in float64.  One thread takes
+// the 8 points of a brick row along z (grid: x covers the z bricks, y is iy,
+// z is ix, so no index is divided): one lookup of a brick's chunks serves 8
+// independent loads, and a wave stores 64 x 32 contiguous bytes.
+__global__ __launch_bounds__(256) void k_brick_combine(const int *__restrict__ cbase, int ng,
+                                                       const float *__restrict__ ctile, int pad,
+                                                       float *__restrict__ grid)
+{
+    const int nb = ng / kBrick;
+    const int bz = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bz >= nb) return;
+    const int iy = blockIdx.y, ix = blockIdx.z;
+    const int bx = ix >> 3, by = iy >> 3;
+    const int tx = ix & 7, ty = iy & 7;
+    const int bzm = bz == 0 ? nb - 1 : bz - 1;
+    double sum[kBrick];
+#pragma unroll
+    for (int k = 0; k < kBrick; ++k) sum[k] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (a == 1 && tx != 0) break;
+        const int px = a ? (bx == 0 ? nb - 1 : bx - 1) : bx, sx = a ? kBrick : tx;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c == 1 && ty != 0) break;
+            const int py = c ? (by == 0 ? nb - 1 : by - 1) : by, sy = c ? kBrick : ty;
+            const int row = (sx * kTile + sy) * kTile;  // tile index of z offset 0
+            const int own = (px * nb + py) * nb + bz, below = (px * nb + py) * nb + bzm;
+            const int w0 = cbase[own], w1 = cbase[own + 1];
+            const int v0 = cbase[below], v1 = cbase[below + 1];
+            for (int w = w0; w < w1; ++w) {
+                const float *t = ctile + (int64_t)w * kTilePts + row;
+                float v[kBrick];
+#pragma unroll
+                for (int k = 0; k < kBrick; ++k) v[k] = t[k];
+#pragma unroll
+                for (int k = 0; k < kBrick; ++k) sum[k] += v[k];
+            }
+            // the brick below in z reaches only offset 0, from its tile index 8
+            for (int w = v0; w < v1; ++w) sum[0] += ctile[(int64_t)w * kTilePts + row + kBrick];
+        }
+    }
+    float *g = grid + ((int64_t)ix * ng + iy) * pad + bz * kBrick;
+#pragma unroll
+    for (int k = 0; k < kBrick; ++k) g[k] = (float)sum[k];
+}
+
 // Float64 sum of the masses: strided partial sums per thread, a fixed tree
 // per workgroup, then one workgroup over the partials.
 __device__ __forceinline__ double block_sum(double v, double *lds)
@@ -185,41 +590,47 @@ __global__ __launch_bounds__(256) void k_mass_final(const double *__restrict__ p
     if (threadIdx.x == 0) total[0] = s;
 }
 
-// Modes of the half spectrum (iz in [0, ng/2]), one wave per workgroup, each
-// taking whole rows (ix, iy) in a fixed order.  Along a row |n| grows with iz,
-// so the bins of 64 consecutive modes form runs: a segmented scan sums each
-// run in a fixed tree order and the run's last lane adds it to the
-// workgroup's bins in LDS (within a chunk every run has its own bin, so no two
-// lanes touch one bin at once, and chunks go in order).  The sums therefore
-// do not depend on scheduling: the spectrum is bitwise reproducible.
-// sinc2[i] = sinc^2(pi n_i / ng) for the mode index n_i of array index i.
-__global__ __launch_bounds__(64) void k_pk_bins(const float2 *__restrict__ c, int ng, int n_bins,
-                                                double inv_dn, const double *__restrict__ sinc2,
-                                                double *__restrict__ part)
+// Modes of the half spectrum (iz in [0, ng/2]).  Each wave of a workgroup
+// takes whole rows (ix, iy) in a fixed order and keeps its own bins in LDS.
+// Along a row |n| grows with iz, so the bins of 64 consecutive modes form
+// runs: a segmented scan sums each run in a fixed tree order and the run's last
+// lane adds it to the wave's bins (within a chunk every run has its own bin,
+// so no two lanes touch one bin at once, and chunks go in order).  The waves'
+// bins are then added in wave order and written transposed,
+// part[(3 b + j) blocks + workgroup], for the last pass.  The sums therefore do
+// not depend on scheduling: the spectrum is bitwise reproducible.
+// iw[i] = 1 / sinc^4(pi n_i / ng) for the mode index n_i of array index i.
+__global__ __launch_bounds__(256) void k_pk_bins(const float2 *__restrict__ c, int ng, int n_bins,
+                                                 double inv_dn, const double *__restrict__ iw,
+                                                 double *__restrict__ part)
 {
-    extern __shared__ double bins[];  // [3][n_bins]: sum of w P', sum of w |n|, sum of w
-    const int lane = threadIdx.x;
-    for (int b = lane; b < 3 * n_bins; b += kWave) bins[b] = 0.0;
+    extern __shared__ double bins[];  // per wave [3][n_bins]: sum of w P', sum of w |n|, sum of w
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    const int nb3 = 3 * n_bins;
+    double *wb = bins + (int64_t)wv * nb3;
+    for (int b = threadIdx.x; b < nw * nb3; b += blockDim.x) bins[b] = 0.0;
     __syncthreads();
     const int nzh = ng / 2 + 1;
     const int64_t rows = (int64_t)ng * ng;
-    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * nw;
+    for (int64_t r = (int64_t)blockIdx.x * nw + wv; r < rows; r += stride) {
         const int iy = (int)(r % ng), ix = (int)(r / ng);
         const int nx = ix <= ng / 2 ? ix : ix - ng;
         const int ny = iy <= ng / 2 ? iy : iy - ng;
-        const double sxy = sinc2[ix] * sinc2[iy];
+        const double wxy = iw[ix] * iw[iy];
+        const double r2 = (double)nx * nx + (double)ny * ny;
         for (int z0 = 0; z0 < nzh; z0 += kWave) {
             const int iz = z0 + lane;
             double p = 0.0, km = 0.0, wt = 0.0;
             int key = -1;  // outside every bin: k = 0, beyond the last bin, past the row
             if (iz < nzh) {
-                const double mag = sqrt((double)nx * nx + (double)ny * ny + (double)iz * iz);
+                const double mag = sqrt(r2 + (double)iz * iz);
                 const int b = (int)floor(mag * inv_dn);
                 if (mag != 0.0 && b < n_bins) {
                     const float2 v = c[r * nzh + iz];
                     const double w = (iz == 0 || 2 * iz == ng) ? 1.0 : 2.0;
-                    const double win = sxy * sinc2[iz];
-                    p = w * (((double)v.x * v.x + (double)v.y * v.y) / (win * win));
+                    p = w * (((double)v.x * v.x + (double)v.y * v.y) * (wxy * iw[iz]));
                     km = w * mag;
                     wt = w;
                     key = b;
@@ -242,16 +653,22 @@ __global__ __launch_bounds__(64) void k_pk_bins(const float2 *__restrict__ c, in
             }
             const int next = __shfl_down(key, 1);
             if ((lane == 63 || next != key) && key >= 0 && key < n_bins) {
-                bins[key] += p;
-                bins[n_bins + key] += km;
-                bins[2 * n_bins + key] += wt;
+                wb[key] += p;
+                wb[n_bins + key] += km;
+                wb[2 * n_bins + key] += wt;
             }
         }
     }
     __syncthreads();
-    for (int b = lane; b < 3 * n_bins; b += kWave) part[(int64_t)blockIdx.x * 3 * n_bins + b] = bins[b];
+    for (int b = threadIdx.x; b < nb3; b += blockDim.x) {
+        double t = bins[b];
+        for (int w = 1; w < nw; ++w) t += bins[(int64_t)w * nb3 + b];
+        part[(int64_t)b * gridDim.x + blockIdx.x] = t;
+    }
 }
 
+// One workgroup per bin: the workgroups' partials of each sum added with a
+// fixed stride per thread and a fixed tree.
 // P(bin) = box^3 / M^2 * sum(w P') / sum(w), k = 2 pi / box * sum(w |n|) / sum(w).
 __global__ __launch_bounds__(256) void k_pk_final(const double *__restrict__ part, int blocks,
                                                   int n_bins, const double *__restrict__ mtot,
@@ -259,15 +676,25 @@ __global__ __launch_bounds__(256) void k_pk_final(const double *__restrict__ par
                                                   double *__restrict__ kmean,
                                                   int64_t *__restrict__ modes)
 {
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= n_bins) return;
-    double sp = 0.0, sk = 0.0, sw = 0.0;
-    for (int g = 0; g < blocks; ++g) {
-        const double *q = part + (int64_t)g * 3 * n_bins;
-        sp += q[b];
-        sk += q[n_bins + b];
-        sw += q[2 * n_bins + b];
+    __shared__ double red[3][256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double *q = part + (int64_t)(j * n_bins + b) * blocks;
+        for (int g = t; g < blocks; g += 256) acc[j] += q[g];
+        red[j][t] = acc[j];
     }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + o];
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const double sp = red[0][0], sk = red[1][0], sw = red[2][0];
     const double M = mtot[0];
     const double two_pi = 6.283185307179586476925;
     pk[b] = sw > 0.0 ? sp / sw * box * box * box / (M * M) : 0.0;
@@ -275,16 +702,20 @@ __global__ __launch_bounds__(256) void k_pk_final(const double *__restrict__ par
     if (modes) modes[b] = (int64_t)(sw + 0.5);
 }
 
-// sinc2[i] = sinc^2(pi n / ng) for the mode index n of array index i.
-__global__ __launch_bounds__(256) void k_pk_sinc(int ng, double *__restrict__ sinc2)
+// iw[i] = 1 / sinc^4(pi n / ng) for the mode index n of array index i.
+__global__ __launch_bounds__(256) void k_pk_sinc(int ng, double *__restrict__ iw)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= ng) return;
     const int nm = i <= ng / 2 ? i : i - ng;
     const double x = 3.14159265358979323846 * nm / ng;
     const double s = nm == 0 ? 1.0 : sin(x) / x;
-    sinc2[i] = s * s;
+    const double s2 = s * s;
+    iw[i] = 1.0 / (s2 * s2);
 }
+
+// Waves per workgroup of the binning: up to 4, as many as their bins fit 64 KiB of LDS.
+int bin_waves(int n_bins) { return std::max(1, std::min(4, 65536 / (24 * n_bins))); }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -301,9 +732,12 @@ struct sr_pk_plan {
     int64_t n_max = 0;
     int passes = 1, digit_bits = 1;
     int64_t tiles = 1;
+    bool brick = false;      // brick deposit (ng a multiple of 8), else the cell deposit
+    int64_t nbricks = 0, max_chunks = 0;
     size_t grid_off = 0, grid_bytes = 0, sinc_off = 0, mass_off = 0, part_off = 0, work_off = 0,
            key_off[2] = {0, 0}, val_off[2] = {0, 0}, pf_off = 0, spf_off = 0, seg_off = 0, cstart_off = 0,
-           tab_off = 0, tabx_off = 0, scan_off = 0, ws_bytes = 0;
+           tab_off = 0, tabx_off = 0, scan_off = 0, chunks_off = 0, cbase_off = 0, owner_off = 0,
+           ctile_off = 0, msum_off = 0, mmax_off = 0, ws_bytes = 0;
     rocfft_plan fft = nullptr;
     size_t work_bytes = 0;
     bool fft_failed = false;
@@ -343,8 +777,76 @@ sr_status check_pk_ws(const sr_pk_plan *P, const void *ws, size_t ws_bytes)
     return SR_OK;
 }
 
+sr_status deposit_bricks(sr_pk_plan *P, const float *pos, const float *mass, int64_t n, char *w,
+                         hipStream_t s)
+{
+    float *grid = reinterpret_cast<float *>(w + P->grid_off);
+    const int pad = 2 * (P->ng / 2 + 1);
+    const float inv_h = (float)(P->ng / P->box);
+    auto I = [&](size_t off) { return reinterpret_cast<int *>(w + off); };
+    auto V = [&](size_t off) { return reinterpret_cast<float4 *>(w + off); };
+    double *mstat = reinterpret_cast<double *>(w + P->mass_off) + kSumBlocks;  // total, max |m|
+    const int nbricks = (int)P->nbricks;
+    int *bstart = I(P->cstart_off), *cbase = I(P->cbase_off);
+    float *ctile = reinterpret_cast<float *>(w + P->ctile_off);
+    if (n > 0) {
+        const int tiles = (int)((n + kRadixTile - 1) / kRadixTile);
+        const int R = 1 << P->digit_bits;
+        double *msum = reinterpret_cast<double *>(w + P->msum_off);
+        float *mmax = reinterpret_cast<float *>(w + P->mmax_off);
+        // keys and payloads (with the first pass's digit counts) into buffer
+        // passes & 1, then a stable radix sort by brick moving the payloads
+        // with the keys; pass p reads buffer (passes + p) & 1 and writes the
+        // other, so the last lands in buffer 0
+        auto K = [&](int q) { return I(P->key_off[q]); };
+        auto Vb = [&](int q) { return V(q ? P->spf_off : P->pf_off); };
+        const int first = P->passes & 1;
+        for (int p = 0; p < P->passes; ++p) {
+            const int shift = p * P->digit_bits;
+            const int in = (first + p) & 1, out = in ^ 1;
+            if (p == 0)
+                k_brick_hist0<<<tiles, kSortThreads, 0, s>>>(pos, mass, (int)n, P->ng, inv_h, P->digit_bits,
+                                                             I(P->tab_off), tiles, K(in), Vb(in), msum, mmax);
+            else
+                k_brick_hist<<<tiles, kSortThreads, 0, s>>>(K(in), (int)n, shift, P->digit_bits, I(P->tab_off),
+                                                            tiles);
+            if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+            if (dev_scan(I(P->tab_off), I(P->tabx_off), (int64_t)R * tiles, I(P->scan_off), s) != hipSuccess)
+                return SR_E_DEVICE;
+            k_brick_scatter<<<tiles, kSortThreads, 0, s>>>(K(in), Vb(in), (int)n, shift, P->digit_bits,
+                                                           I(P->tabx_off), tiles, K(out), Vb(out));
+            if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+        }
+        k_brick_mass<<<1, 256, 0, s>>>(msum, mmax, tiles, mstat);
+        if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+        if (dev_bounds(K(0), n, nbricks, 0, bstart, s) != hipSuccess) return SR_E_DEVICE;
+        const unsigned bb = (unsigned)((nbricks + 255) / 256);
+        k_brick_chunks<<<bb, 256, 0, s>>>(bstart, nbricks, I(P->chunks_off));
+        if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+        if (dev_scan(I(P->chunks_off), cbase, nbricks, I(P->scan_off), s) != hipSuccess) return SR_E_DEVICE;
+        int4 *rec = reinterpret_cast<int4 *>(w + P->owner_off);
+        k_brick_owner<<<bb, 256, 0, s>>>(bstart, cbase, nbricks, rec);
+        if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+        // workgroups: an upper bound on the chunks, sum over bricks of ceil(np / kChunk)
+        const int64_t bound = n / kChunk + std::min<int64_t>(nbricks, n);
+        k_brick_tile<<<(unsigned)bound, 256, 0, s>>>(cbase, nbricks, rec, Vb(0), mstat, ctile);
+        if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+    } else {
+        // no chunks, and a zero mass
+        if (dev_zero(cbase, nbricks + 1, s) != hipSuccess) return SR_E_DEVICE;
+        k_brick_mass<<<1, 256, 0, s>>>(nullptr, nullptr, 0, mstat);
+        if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
+    }
+    const int nbz = P->ng / kBrick;
+    const int tz = std::min(256, (nbz + 63) / 64 * 64);
+    const dim3 cg((unsigned)((nbz + tz - 1) / tz), (unsigned)P->ng, (unsigned)P->ng);
+    k_brick_combine<<<cg, tz, 0, s>>>(cbase, P->ng, ctile, pad, grid);
+    return hipGetLastError() == hipSuccess ? SR_OK : SR_E_DEVICE;
+}
+
 sr_status deposit(sr_pk_plan *P, const float *pos, const float *mass, int64_t n, char *w, hipStream_t s)
 {
+    if (P->brick) return deposit_bricks(P, pos, mass, n, w, s);
     float *grid = reinterpret_cast<float *>(w + P->grid_off);
     const int pad = 2 * (P->ng / 2 + 1);
     const float inv_h = (float)(P->ng / P->box);
@@ -411,7 +913,7 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
     P->sinc_off = o;
     o = align256(o + sizeof(double) * ng);
     P->mass_off = o;
-    o = align256(o + sizeof(double) * (kSumBlocks + 1));
+    o = align256(o + sizeof(double) * (kSumBlocks + 2));
     P->part_off = o;
     o = align256(o + sizeof(double) * 3 * n_bins * kBinBlocks);
     P->work_off = o;
@@ -419,7 +921,47 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
     // conservative bound (one complex grid), checked again at the first run
     P->work_bytes = (size_t)ng * ng * nzh * 2 * sizeof(float);
     o = align256(o + P->work_bytes);
-    {
+    P->brick = ng % kBrick == 0;
+    if (P->brick) {
+        const int64_t nb = ng / kBrick;
+        P->nbricks = nb * nb * nb;  // brick keys fit 21 bits
+        int bits = 1;
+        while ((int64_t(1) << bits) < P->nbricks) ++bits;
+        P->passes = (bits + 7) / 8;
+        P->digit_bits = (bits + P->passes - 1) / P->passes;
+        const int64_t m = std::max<int64_t>(1, n_max);
+        P->tiles = std::max<int64_t>(1, (m + kRadixTile - 1) / kRadixTile);
+        const int64_t table = (int64_t(1) << P->digit_bits) * P->tiles;
+        P->max_chunks = m / kChunk + std::min<int64_t>(P->nbricks, m);
+        for (int k = 0; k < 2; ++k) {
+            P->key_off[k] = o;
+            o = align256(o + sizeof(int) * m);
+        }
+        P->pf_off = o;  // payloads of sort buffer 0; buffer 1 at spf_off
+        o = align256(o + sizeof(float4) * m);
+        P->spf_off = o;
+        o = align256(o + sizeof(float4) * m);
+        P->cstart_off = o;  // first sorted slot of each brick
+        o = align256(o + sizeof(int) * (P->nbricks + 1));
+        P->chunks_off = o;
+        o = align256(o + sizeof(int) * P->nbricks);
+        P->cbase_off = o;
+        o = align256(o + sizeof(int) * (P->nbricks + 1));
+        P->owner_off = o;  // chunk records (brick, first, end)
+        o = align256(o + sizeof(int4) * P->max_chunks);
+        P->ctile_off = o;
+        o = align256(o + sizeof(float) * kTilePts * P->max_chunks);
+        P->msum_off = o;
+        o = align256(o + sizeof(double) * P->tiles);
+        P->mmax_off = o;
+        o = align256(o + sizeof(float) * P->tiles);
+        P->tab_off = o;
+        o = align256(o + sizeof(int) * table);
+        P->tabx_off = o;
+        o = align256(o + sizeof(int) * (table + 1));
+        P->scan_off = o;
+        o = align256(o + sizeof(int) * scan_scratch_elems(std::max<int64_t>(table, P->nbricks)));
+    } else {
         const int64_t cells = (int64_t)ng * ng * ng;  // cell keys fit 30 bits
         int bits = 1;
         while ((int64_t(1) << bits) < cells) ++bits;
@@ -508,10 +1050,11 @@ sr_status sr_power_spectrum(sr_pk_plan *P, const float *pos, const float *mass, 
     (void)rocfft_execution_info_destroy(info);
     if (!ok) return SR_E_DEVICE;
     double *part = reinterpret_cast<double *>(w + P->part_off);
-    k_pk_bins<<<kBinBlocks, kWave, sizeof(double) * 3 * P->n_bins, s>>>(
+    const int nw = bin_waves(P->n_bins);
+    k_pk_bins<<<kBinBlocks, nw * kWave, sizeof(double) * 3 * nw * P->n_bins, s>>>(
         reinterpret_cast<const float2 *>(w + P->grid_off), P->ng, P->n_bins, 1.0 / P->dn,
         reinterpret_cast<const double *>(w + P->sinc_off), part);
-    k_pk_final<<<(unsigned)((P->n_bins + 255) / 256), 256, 0, s>>>(
+    k_pk_final<<<(unsigned)P->n_bins, 256, 0, s>>>(
         part, kBinBlocks, P->n_bins, reinterpret_cast<const double *>(w + P->mass_off) + kSumBlocks, P->box,
         pk, k, modes);
     return hipGetLastError() == hipSuccess ? SR_OK : SR_E_DEVICE;

@@ -1,5 +1,7 @@
 """Power spectrum on the GPU (paper Sec. 4.1) against the float64 oracle:
-the CIC grid point by point, the mode counts exactly, and P(k) per bin."""
+the CIC grid point by point, the mode counts exactly, and P(k) per bin.
+Grids whose side is a multiple of 8 take the brick deposit, the others the
+cell deposit; both are covered."""
 import numpy as np
 import pytest
 import torch
@@ -11,8 +13,21 @@ from gpu_helpers import DEV, announce, to_dev
 
 pytestmark = pytest.mark.gpu
 
-GRID_RTOL = 1e-6   # float32 terms summed in float64, stored as float32
+# float32 weights; the brick deposit sums them exactly per tile and adds a
+# point's float32 tile values in float64, the cell deposit sums them in float64
+GRID_RTOL = 1e-6
 PK_RTOL = 1e-4     # float32 grid and FFT; measured float32-vs-float64 bin error <= 5e-6
+
+
+def exact_scale(pos, box, ng):
+    """(pos, box) with ng / box a power of two, so that u = x ng / box is exact
+    in float32 on both sides: otherwise the positions are rescaled to box = ng
+    (as float32) first.  The deposit defines u in float32; this keeps that
+    rounding, which the float64 oracle does not make, out of the comparison."""
+    r = ng / box
+    if np.log2(r) == np.round(np.log2(r)):
+        return pos, box
+    return (pos.astype(np.float64) * r).astype(np.float32), float(ng)
 
 
 def case(name):
@@ -28,9 +43,11 @@ def case(name):
 
 
 @pytest.mark.parametrize("name,ng", [("uniform_32k", 32), ("uniform_32k", 64), ("clustered_64", 64),
-                                     ("clustered_64", 32)])
+                                     ("clustered_64", 32), ("uniform_32k", 36), ("clustered_64", 30),
+                                     ("clustered_64", 8)])
 def test_deposit_matches_oracle(name, ng):
     pos, mass, box = case(name)
+    pos, box = exact_scale(pos, box, ng)
     announce(f"cic deposit {name} ng={ng}")
     plan = sr.PkPlan(ng, box, 8, n_max=pos.shape[0])
     ws = sr.new_workspace(plan.ws_bytes, DEV)
@@ -76,12 +93,16 @@ def test_power_spectrum_matches_oracle(name, ng, dn):
     plan.close()
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 128, 129, 5000])
-def test_deposit_crowded_cells_and_wrap(n):
-    # n particles in one cell and n // 2 in its neighbour: the sorted slots of a
-    # crowded cell are cut into 64-slot runs whose partials the grid points add
-    # back; plus particles on grid points and across the periodic faces
-    ng, box = 16, 16.0
+@pytest.mark.parametrize("n,ng", [(1, 16), (63, 16), (64, 16), (65, 16), (128, 16), (129, 16), (5000, 16),
+                                  (2731, 16), (20000, 16), (129, 12), (5000, 12)])
+def test_deposit_crowded_cells_and_wrap(n, ng):
+    # n particles in one cell and n // 2 in its neighbour, plus particles on
+    # grid points and across the periodic faces.  Cell deposit (ng = 12): the
+    # sorted slots of a crowded cell are cut into 64-slot runs whose partials
+    # the grid points add back.  Brick deposit (ng = 16): both cells sit in one
+    # brick, cut into chunks of 2048 particles (2731 + 1365 = 4096 exactly two,
+    # more with the particles spread over the box) whose tiles the points add
+    box = 16.0
     rng = np.random.default_rng(n)
     crowd = np.array([5.0, 7.0, 9.0]) + rng.random((n, 3)) * 0.999
     nbr = np.array([6.0, 7.0, 9.0]) + rng.random((n // 2, 3)) * 0.999
@@ -89,6 +110,7 @@ def test_deposit_crowded_cells_and_wrap(n):
                       [-0.5, 3.25, 15.75], [4, 4, 4]])
     pos = np.concatenate([crowd, nbr, faces, rng.random((300, 3)) * 16]).astype(np.float32)
     pos = pos[rng.permutation(len(pos))]
+    pos, box = exact_scale(pos, box, ng)
     mass = rng.uniform(0.5, 2.0, len(pos)).astype(np.float32)
     announce(f"cic deposit crowded cell n={n}")
     plan = sr.PkPlan(ng, box, 8, n_max=len(pos))
@@ -99,4 +121,32 @@ def test_deposit_crowded_cells_and_wrap(n):
     np.testing.assert_allclose(got.astype(np.float64), ref, rtol=GRID_RTOL, atol=1e-30)
     again, _ = plan.deposit(to_dev(pos), to_dev(mass), ws)
     assert np.array_equal(again.cpu().numpy().view(np.uint32), got.view(np.uint32))
+    plan.close()
+
+
+@pytest.mark.parametrize("ng", [16, 12])
+def test_non_finite_position_reaches_the_spectrum(ng):
+    # a NaN or infinite coordinate gives NaN weights: the grid points they reach
+    # and then every P(k) bin with modes are NaN (never a finite wrong value)
+    rng = np.random.default_rng(ng)
+    box = float(ng)
+    pos = (rng.random((2000, 3)) * box).astype(np.float32)
+    mass = rng.uniform(0.5, 2.0, 2000).astype(np.float32)
+    pos[7, 1] = np.nan
+    pos[11, 2] = np.inf
+    announce(f"cic deposit non-finite positions ng={ng}")
+    plan = sr.PkPlan(ng, box, 8, n_max=len(pos))
+    ws = sr.new_workspace(plan.ws_bytes, DEV)
+    grid, _ = plan.deposit(to_dev(pos), to_dev(mass), ws)
+    g = grid.cpu().numpy()
+    assert np.isnan(g).any()
+    ok = np.delete(np.arange(len(pos)), [7, 11])
+    ref = opk.cic_deposit(pos[ok], mass[ok], ng, box)
+    # the points no NaN reached (all but the 8 corners of a NaN particle's cell,
+    # or the 9^3 tile of its brick) hold the deposit of the finite particles
+    fin = np.isfinite(g)
+    assert fin.sum() >= g.size - 2 * (8 if ng % 8 else 729)
+    np.testing.assert_allclose(g[fin].astype(np.float64), ref[fin], rtol=GRID_RTOL, atol=1e-30)
+    p, _, modes = (t.cpu().numpy() for t in plan.run(to_dev(pos), to_dev(mass), ws))
+    assert np.all(np.isnan(p[modes > 0]))
     plan.close()

@@ -21,9 +21,11 @@ def test_plan_validation_and_sizes():
         assert _create(**bad)[0] == 1, bad
     sizes = [_create(ng)[2] for ng in (16, 64, 256)]
     assert sizes == sorted(sizes) and all(s % 256 == 0 for s in sizes)
-    # the grid alone: ng * ng * 2 (ng/2 + 1) floats; the sorted deposit adds
-    # per-particle buffers and a cell-start table
-    assert sizes[2] >= 256 * 256 * 258 * 4 + 256 ** 3 * 4
+    # the grid, ng * ng * 2 (ng/2 + 1) floats, and the FFT's work buffer of
+    # about the same size; the deposits add per-particle sort buffers
+    assert sizes[2] >= 2 * 256 * 256 * 258 * 4
+    # the cell deposit (ng not a multiple of 8) keeps a cell-start table of ng^3 + 1
+    assert _create(250)[2] >= 2 * 250 * 250 * 252 * 4 + 250 ** 3 * 4
     assert _create(64, n_max=100000)[2] > _create(64, n_max=1000)[2]
 
 

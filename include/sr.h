@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SR_ABI_VERSION 5
+#define SR_ABI_VERSION 6
 
 typedef enum sr_status {
     SR_OK = 0,
@@ -389,10 +389,15 @@ sr_status sr_centres(sr_centres_plan *plan, const float *pos, const float *mass,
  * left out), with delta = rho / mean(rho) - 1.  Deposit: a particle at
  * u = x / h, wrapped into [0, ng), gives m (1 - f) to grid point floor(u) and
  * m f to floor(u) + 1 per axis (f = u - floor(u)), the product over axes to
- * each of 8 points; grid points sit at multiples of h.  The particles are
+ * each of 8 points; grid points sit at multiples of h.  For ng a multiple
+ * of 8 the particles are sorted (stably) by brick of 8^3 cells, each run of up
+ * to 2048 particles of a brick sums its weights exactly as 2^-(94 - e) fixed
+ * point (2^e > 2048 max|m|; weights below 2^(e - 71) are rounded by at most
+ * 2^(e - 95)) into a 9^3 tile stored as float32, and every grid point adds
+ * the tiles covering it in float64 in a fixed order.  For other ng they are
  * sorted by cell, each cell's contributions are summed in float64 per
- * 64-particle run, and every grid point adds its 8 cells' partials in a
- * fixed order (the grid is reproducible bit for bit).  The FFT is rocFFT's
+ * 64-particle run, and every grid point adds its 8 cells' partials in a fixed
+ * order.  Either way the grid is reproducible bit for bit.  The FFT is rocFFT's
  * single-precision real-to-complex transform, in place in the workspace;
  * mode sums are float64.  Non-finite positions make the spectrum
  * non-finite. */
@@ -466,6 +471,17 @@ sr_status sr_launch_config_kernel(const char *kernel /*host*/, int waves_per_cu,
  * receives {blocks_per_item, window}. */
 sr_status sr_tile_config(const char *kernel /*host*/, int blocks_per_item, int window,
                          int *cur /*host out*/);
+
+/* Host only.  When the symmetric tiles pay: they run only if their work (tile
+ * steps of all items) spread over the persistent grid's waves is at least
+ * min_ratio times the longest item, so that a few long items cannot leave
+ * most waves idle; the decision is taken on the device after binning, like
+ * the pool check.  min_ratio >= 0 (0: whenever the partial slots fit; -1
+ * keeps the value); initial value 1, or SR_SYM_BALANCE.  Batch plans do not
+ * apply it: their tuner times the tiles against none, and every mode of a
+ * plan takes the same decision.  Results of either path agree to rounding
+ * order; cur (nullable) receives the value in effect. */
+sr_status sr_tile_balance(double min_ratio, double *cur /*host out*/);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
  * launch of the pair kernels ("force", "vjp").  sr_timing_enable(1) clears

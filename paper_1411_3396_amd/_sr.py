@@ -36,7 +36,8 @@ EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "
            "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
            "sr_blocks_reconcile_grad", "sr_centres_plan_create", "sr_centres_plan_destroy",
            "sr_centres", "sr_pk_plan_create", "sr_pk_plan_destroy", "sr_pk_deposit", "sr_pk_grid",
-           "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_tile_config", "sr_timing_enable",
+           "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_tile_config", "sr_tile_balance",
+           "sr_timing_enable",
            "sr_timing_read")
 
 
@@ -76,7 +77,7 @@ class BinLayout(C.Structure):
 
 
 # sr_problem layout and entry points of include/sr.h (SR_ABI_VERSION)
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 _lib = None
 
@@ -124,6 +125,7 @@ def lib():
         L.sr_launch_config.argtypes = [C.c_int, C.c_int, C.c_int, p]
         L.sr_launch_config_kernel.argtypes = [C.c_char_p, C.c_int, C.c_int, C.c_int, p]
         L.sr_tile_config.argtypes = [C.c_char_p, C.c_int, C.c_int, p]
+        L.sr_tile_balance.argtypes = [C.c_double, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
         for name in EXPORTS:
@@ -666,6 +668,15 @@ def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: i
         _check(lib().sr_launch_config_kernel(kernel.encode(), int(waves_per_cu), int(targets_per_lane),
                                              int(occupancy), cur), "sr_launch_config_kernel")
     return int(cur[0]), int(cur[1]), int(cur[2])
+
+
+def tile_balance(min_ratio: float = -1.0) -> float:
+    """Set and return the balance rule of the symmetric tiles: they run only if their work per
+    wave of the persistent grid is at least min_ratio longest items (0: whenever the partial
+    slots fit; -1 keeps the value)."""
+    cur = C.c_double()
+    _check(lib().sr_tile_balance(float(min_ratio), C.byref(cur)), "sr_tile_balance")
+    return float(cur.value)
 
 
 def tile_config(blocks_per_item: int = -1, window: int = -1, kernel: str = "force"):

@@ -169,7 +169,7 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.tabx = take((size_t)(L.table + 1) * 4);
     L.nact = take((size_t)NC * 4);
     L.start = take((size_t)(NC + 1) * 4);
-    L.scan_tmp = take((size_t)std::max(scan_scratch_elems(L.table), scan_scratch_elems(kSymStride * NC)) * 4);
+    L.scan_tmp = take((size_t)std::max(scan_scratch_elems(L.table), scan_scratch_elems(NC)) * 4);
     L.bx = take(n4);
     L.by = take(n4);
     L.bz = take(n4);
@@ -181,11 +181,13 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.items = take((size_t)L.item_cap * 16);
     L.info = take((size_t)NC * 4);
     L.mom = take((size_t)(3 * mom_tiles + 3) * 8);
-    // symmetric tiles: per cell and direction the partial-slot counts and their
-    // exclusive scan, per cell the item count and cost class, the items, and
-    // the pool of 12-byte partial slots (at most 2^31 - 1 of them)
-    L.sym_cnt = take((size_t)kSymStride * NC * 4);
-    L.sym_base = take(((size_t)kSymStride * NC + 1) * 4);
+    // symmetric tiles: per cell and slot group the prefix of the partial-slot
+    // counts, per cell their total and its exclusive scan, per cell the item
+    // count and cost class, the items, and the pool of 12-byte partial slots
+    // (at most 2^31 - 1 of them)
+    L.sym_pref = take((size_t)kSymStride * NC * 4);
+    L.sym_tot = take((size_t)NC * 4);
+    L.sym_base = take(((size_t)NC + 1) * 4);
     L.sym_info = take((size_t)NC * 4);
     // the tail: symmetric items and the pool, sized for the default number of
     // slots per particle; a larger workspace lends the tail more (sym_tail)
@@ -241,6 +243,7 @@ std::atomic<int> g_occ_default[2] = {{6}, {0}};
 std::atomic<int> g_sym_blocks[2] = {{16}, {16}};
 std::atomic<int> g_sym_window[2] = {{512}, {256}};
 std::atomic<int> g_sym_occ[2] = {{5}, {5}};
+std::atomic<double> g_sym_balance{1.0};
 
 // Launch defaults may be overridden for experiments (both kernels):
 // SR_WAVES_PER_CU, SR_TARGETS_PER_LANE, SR_OCCUPANCY.
@@ -272,6 +275,10 @@ struct EnvDefaults {
                 const int o = std::atoi(v);
                 if (o == 0 || o == 5 || o == 6) g_sym_occ[k] = o;
             }
+        }
+        if (const char *v = std::getenv("SR_SYM_BALANCE")) {
+            const double b = std::atof(v);
+            if (b >= 0.0 && std::isfinite(b)) g_sym_balance = b;
         }
     }
 } g_env_defaults;
@@ -321,6 +328,7 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.sym_blocks = g_sym_blocks[cfg].load();
     a.sym_window = g_sym_window[cfg].load();
     a.sym_occupancy = g_sym_occ[cfg].load();
+    a.sym_balance = g_sym_balance.load();
     a.pull_limit = pull_limit();
     return SR_OK;
 }
@@ -414,6 +422,9 @@ sr_status run_batched(sr_batch_plan *P, const float *pos, const float *mass, voi
     a.occupancy = P->occupancy;
     if (P->sym_blocks >= 0) a.sym_blocks = P->sym_blocks;
     if (P->sym_window > 0) a.sym_window = P->sym_window;
+    // the plan's tuner already timed the tiles against none, and the same
+    // decision must hold in every mode (bitwise agreement): no balance rule
+    a.sym_balance = 0.0;
     hipError_t e = hipMemcpyAsync(static_cast<char *>(ws) + P->L.seg, P->pinned,
                                   sizeof(SegParams) * P->B, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return SR_E_DEVICE;
@@ -438,6 +449,7 @@ sr_status run_per_subvolume(sr_batch_plan *P, const float *pos, const float *mas
         a.occupancy = P->occupancy;
         if (P->sym_blocks >= 0) a.sym_blocks = P->sym_blocks;
         if (P->sym_window > 0) a.sym_window = P->sym_window;
+        a.sym_balance = 0.0;
         if (n > 0) {
             if (dev_bin(a, pos + 3 * off, mass + off) != hipSuccess) return SR_E_DEVICE;
             if (P->n_active[b] > 0 && dev_force(a, acc + 3 * out_off) != hipSuccess) return SR_E_DEVICE;
@@ -1037,6 +1049,14 @@ sr_status sr_tile_config(const char *kernel, int blocks_per_item, int window, in
         cur[0] = g_sym_blocks[k].load();
         cur[1] = g_sym_window[k].load();
     }
+    return SR_OK;
+}
+
+sr_status sr_tile_balance(double min_ratio, double *cur)
+{
+    if (!(min_ratio >= 0.0 || min_ratio == -1.0) || !std::isfinite(min_ratio)) return SR_E_ARG;
+    if (min_ratio >= 0.0) g_sym_balance = min_ratio;
+    if (cur) *cur = g_sym_balance.load();
     return SR_OK;
 }
 

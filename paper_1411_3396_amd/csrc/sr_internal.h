@@ -14,7 +14,8 @@ namespace sr {
 constexpr int kWave = 64;
 constexpr int kTargetsPerItem = 64;  // one target per lane in a dense cell
 constexpr int kSparseGroup = 16;     // most targets per item of a cell with fewer than 64
-constexpr int kQueues = 8;           // one work queue per XCD
+constexpr int kXcds = 8;             // XCDs of an MI355X; workgroups are dealt to them in turn
+constexpr int kQueues = kXcds;       // one work queue per XCD
 constexpr int kQueueBlock = 32;      // consecutive items a queue takes from the list
 constexpr int kClasses = 32;         // cost classes (floor log2 of the per-lane pair count)
 constexpr int kRadixTile = 2048;     // elements per radix-sort tile
@@ -69,6 +70,8 @@ enum HdrWord : int {
     kHdrSymTotal = 516,     // int64 partial slots the symmetric tiles need (2 words)
     kHdrSymOk = 518,        // 1: symmetric tiles run (their partial slots fit the pool)
     kHdrSymNItems = 519,    // symmetric work items
+    kHdrSymWork = 520,      // int64 tile steps of all symmetric items (2 words)
+    kHdrSymMaxItem = 522,   // tile steps of the longest symmetric item
     kHdrSymBucketCount = 544,   // [32]
     kHdrSymBucketBase = 576,    // [33]
     kHdrSymBucketCursor = 640,  // [32]
@@ -105,7 +108,7 @@ struct Layout {
     size_t items = 0, info = 0, mom = 0;
     int64_t sym_cap = 0;    // partial slots of the pool
     int64_t sym_item_cap = 0;
-    size_t sym_cnt = 0, sym_base = 0, sym_info = 0, sym_items = 0, sym_pool = 0;
+    size_t sym_pref = 0, sym_tot = 0, sym_base = 0, sym_info = 0, sym_items = 0, sym_pool = 0;
     size_t total = 0;
     size_t perm() const { return vals[(passes - 1) & 1]; }
     size_t sorted_keys() const { return keys[(passes - 1) & 1]; }
@@ -137,6 +140,7 @@ struct DevArgs {
     int sym_blocks;        // symmetric tiles: blocks of 64 targets per item (0: symmetric tiles off)
     int sym_window;        // symmetric tiles: sources per item window (256 or 512)
     int sym_occupancy;     // symmetric tiles: register-allocation hint, 0 or 5 waves/SIMD
+    double sym_balance;    // symmetric tiles run only if their steps per wave reach this many longest items
     int64_t pull_limit;    // most items one wave of a persistent kernel may pull (test hook)
 };
 

@@ -1435,29 +1435,40 @@ __device__ __forceinline__ void full_dir(int f, int &dx, int &dy, int &dz)
     dz = f % 3 - 1;
 }
 
-// Per cell c, its row of kSymStride partial-slot counts in cnt: [0] target
-// slots (windows of c times its dense particles); [1 + e] source slots of
-// its dense particles for direction e of the half stencil (runs of the cell
-// c - dir_e times the dense particles); [15 + f] source slots of its
+// Per cell c, the partial-slot counts of its row of kSymStride groups: [0]
+// target slots (windows of c times its dense particles); [1 + e] source slots
+// of its dense particles for direction e of the half stencil (runs of the
+// cell c - dir_e times the dense particles); [15 + f] source slots of its
 // non-dense particles for direction f of the full stencil (runs of the cell
-// c - dir_f times the non-dense particles).  Also the item count and cost
-// class of c as a home cell (runs times windows) in info[c], and the slot
-// total of all cells (int64, header).
+// c - dir_f times the non-dense particles).  Stored as the row's exclusive
+// prefix sums in pref and the row total in tot[c]; a scan of tot gives each
+// cell's first slot, so group e of cell c starts at base[c] + pref[c][e].
+// Also the item count and cost class of c as a home cell (runs times
+// windows) in info[c], and the slot total of all cells (int64, header).  The
+// workgroup's rows are assembled in LDS and stored as one contiguous run.
 template <class Acc>
 __global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *__restrict__ start,
                                                    const int *__restrict__ nact, int K, int W,
-                                                   int *__restrict__ cnt, uint32_t *__restrict__ info,
-                                                   uint32_t *hdr, uint32_t magic)
+                                                   int *__restrict__ pref, int *__restrict__ tot_out,
+                                                   uint32_t *__restrict__ info, uint32_t *hdr,
+                                                   uint32_t magic)
 {
     __shared__ uint32_t blk[kClasses];
-    __shared__ unsigned long long tot;
+    __shared__ unsigned long long tot, work;
+    __shared__ uint32_t longest;
+    __shared__ int rows[256 * kSymStride];
     if (threadIdx.x < kClasses) blk[threadIdx.x] = 0;
-    if (threadIdx.x == 0) tot = 0;
+    if (threadIdx.x == 0) {
+        tot = 0;
+        work = 0;
+        longest = 0;
+    }
     __syncthreads();
     const bool ok = hdr[kHdrMagic] == magic;
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int c0 = blockIdx.x * 256;
+    const int c = c0 + threadIdx.x;
     if (c < NC) {
-        int *row = cnt + (int64_t)kSymStride * c;
+        int *row = rows + kSymStride * threadIdx.x;
         uint32_t inf = 0;
         unsigned long long slots = 0;
         if (ok) {
@@ -1505,6 +1516,9 @@ __global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *_
                 if (n_items < (int64_t(1) << 27)) {
                     inf = ((uint32_t)n_items << 5) | (uint32_t)cls;
                     atomicAdd(&blk[cls], (uint32_t)n_items);
+                    // every block of the cell meets every source of its list once
+                    atomicAdd(&work, (unsigned long long)nb * (unsigned long long)sv);
+                    atomicMax(&longest, (uint32_t)min(cost, (int64_t)UINT32_MAX));
                 } else {
                     slots = ~0ull >> 2;  // beyond any pool: the symmetric tiles stay off
                 }
@@ -1512,18 +1526,39 @@ __global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *_
         } else {
             for (int e = 0; e < kSymStride; ++e) row[e] = 0;
         }
+        // counts to exclusive prefixes; a total past 2^31 - 1 exceeds every pool
+        // (the header's int64 total turns the tiles off), so clamping is harmless
+        int64_t run = 0;
+        for (int e = 0; e < kSymStride; ++e) {
+            const int v = row[e];
+            row[e] = (int)min(run, (int64_t)INT32_MAX);
+            run += v;
+        }
+        tot_out[c] = (int)min(run, (int64_t)INT32_MAX);
         info[c] = inf;
         if (slots) atomicAdd(&tot, slots);
     }
     __syncthreads();
+    const int nrow = min(256, NC - c0);
+    int *out = pref + (int64_t)kSymStride * c0;
+    for (int i = threadIdx.x; i < nrow * kSymStride; i += 256) out[i] = rows[i];
     if (threadIdx.x < kClasses && blk[threadIdx.x])
         atomicAdd(&hdr[kHdrSymBucketCount + threadIdx.x], blk[threadIdx.x]);
-    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&hdr[kHdrSymTotal], tot);
+    if (threadIdx.x == 0) {
+        if (tot) atomicAdd((unsigned long long *)&hdr[kHdrSymTotal], tot);
+        if (work) atomicAdd((unsigned long long *)&hdr[kHdrSymWork], work);
+        if (longest) atomicMax(&hdr[kHdrSymMaxItem], longest);
+    }
 }
 
 // Class bases of the symmetric items, heaviest first; the tiles run only when
-// enabled, on bins of these sizes, and when every partial slot fits the pool.
-__global__ void k_sym_base(uint32_t *hdr, uint32_t magic, long long cap, int enabled)
+// enabled, on bins of these sizes, when every partial slot fits the pool, and
+// when their work spread over the persistent grid (waves) is at least
+// balance times the longest item: otherwise a few long items would leave most
+// waves idle, and the one-sided kernels, with items of at most 64 targets,
+// finish sooner.
+__global__ void k_sym_base(uint32_t *hdr, uint32_t magic, long long cap, int enabled, int waves,
+                           double balance)
 {
     if (threadIdx.x == 0) {
         uint32_t run = 0;
@@ -1532,7 +1567,10 @@ __global__ void k_sym_base(uint32_t *hdr, uint32_t magic, long long cap, int ena
             run += hdr[kHdrSymBucketCount + cls];
         }
         const unsigned long long tot = *(const unsigned long long *)&hdr[kHdrSymTotal];
-        const bool ok = enabled && hdr[kHdrMagic] == magic && run > 0 && tot <= (unsigned long long)cap;
+        const double work = (double)*(const unsigned long long *)&hdr[kHdrSymWork];
+        const bool spread = work >= balance * (double)waves * (double)hdr[kHdrSymMaxItem];
+        const bool ok = enabled && hdr[kHdrMagic] == magic && run > 0 && tot <= (unsigned long long)cap &&
+                        spread;
         hdr[kHdrSymOk] = ok ? 1u : 0u;
         hdr[kHdrSymNItems] = ok ? run : 0u;
     }
@@ -1588,7 +1626,8 @@ struct SymStencil {
 __device__ __forceinline__ void sym_stencil_setup(const SegParams &S, int cell,
                                                   const int *__restrict__ start,
                                                   const int *__restrict__ nact,
-                                                  const int *__restrict__ sym_base, int lane,
+                                                  const int *__restrict__ sym_base,
+                                                  const int *__restrict__ sym_pref, int lane,
                                                   SymStencil &st)
 {
     int ix, iy, iz;
@@ -1607,7 +1646,7 @@ __device__ __forceinline__ void sym_stencil_setup(const SegParams &S, int cell,
             const int d = dense_count(nact[b]);
             st.nstart = start[b] + (lane < kSymDirs ? 0 : d);
             st.cnt = lane < kSymDirs ? d : start[b + 1] - start[b] - d;
-            st.sbase = sym_base[(int64_t)kSymStride * b + 1 + lane];
+            st.sbase = sym_base[b] + sym_pref[(int64_t)kSymStride * b + 1 + lane];
         }
     }
     int incl = st.cnt;
@@ -1785,12 +1824,16 @@ template <class Acc, bool kSoft, bool kUM, int kW>
 __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__restrict__ items,
                                                 uint32_t *hdr, const int *__restrict__ start,
                                                 const int *__restrict__ nact,
-                                                const int *__restrict__ sym_base, const Src &src,
+                                                const int *__restrict__ sym_base,
+                                                const int *__restrict__ sym_pref, const Src &src,
                                                 float *__restrict__ pool, int K, float4 *tile,
                                                 int *tix, SymRed<kW> &red, int64_t pull_limit)
 {
     const int lane = threadIdx.x;
     const int64_t n_items = hdr[kHdrSymNItems];
+    // tiles off (or nothing to do): leave before touching the queues, which
+    // thousands of idle waves would otherwise all hit once per queue
+    if (n_items == 0) return;
     const int q0 = blockIdx.x & (kQueues - 1);
     PullGuard guard(min(n_items, pull_limit));
     for (int qq = 0; qq < kQueues && !guard.bad; ++qq) {
@@ -1807,11 +1850,11 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
 #pragma unroll
             for (int i = 0; i < 6; ++i) cq[i] = S.pc.q[i];
             SymStencil st;
-            sym_stencil_setup(S, c, start, nact, sym_base, lane, st);
+            sym_stencil_setup(S, c, start, nact, sym_base, sym_pref, lane, st);
             const int D = __shfl(st.cnt, 0);  // segment 0 is the cell itself
             const int c0s = start[c];
             const int w0 = k * kW, w1 = min(w0 + kW, st.total);
-            const int tbase = sym_base[(int64_t)kSymStride * c] + k * D;
+            const int tbase = sym_base[c] + k * D;  // group 0: the target slots
             for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
             const int p0 = g * K, p1 = min(p0 + K, D / kWave);
             auto fetch_p = [&](int v, float4 &a, float4 &) {
@@ -1892,17 +1935,18 @@ template <class Acc, bool kSoft, int kW, int kOcc>
 __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
                                                   const int *__restrict__ start,
                                                   const int *__restrict__ nact,
-                                                  const int *__restrict__ sym_base, Src src,
+                                                  const int *__restrict__ sym_base,
+                                                  const int *__restrict__ sym_pref, Src src,
                                                   float *__restrict__ pool, int K, int64_t pull_limit)
 {
     __shared__ float4 tile[2 * kWave];
     __shared__ int tix[kWave];
     __shared__ SymRed<kW> red;
     if (hdr[kHdrMassInfo] == 0)
-        force_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, tile,
+        force_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, pool, K, tile,
                                               tix, red, pull_limit);
     else
-        force_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, src, pool, K, tile,
+        force_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, pool, K, tile,
                                                tix, red, pull_limit);
 }
 
@@ -1912,7 +1956,8 @@ template <class Acc, bool kSoft, bool kUM, int kW>
 __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__restrict__ items,
                                               uint32_t *hdr, const int *__restrict__ start,
                                               const int *__restrict__ nact,
-                                              const int *__restrict__ sym_base, const Src &src,
+                                              const int *__restrict__ sym_base,
+                                              const int *__restrict__ sym_pref, const Src &src,
                                               const float *__restrict__ gx, const float *__restrict__ gy,
                                               const float *__restrict__ gz, float *__restrict__ pool,
                                               int K, float4 *tile_p, float4 *tile_g, int *tix,
@@ -1920,6 +1965,9 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
 {
     const int lane = threadIdx.x;
     const int64_t n_items = hdr[kHdrSymNItems];
+    // tiles off (or nothing to do): leave before touching the queues, which
+    // thousands of idle waves would otherwise all hit once per queue
+    if (n_items == 0) return;
     const int q0 = blockIdx.x & (kQueues - 1);
     PullGuard guard(min(n_items, pull_limit));
     for (int qq = 0; qq < kQueues && !guard.bad; ++qq) {
@@ -1938,11 +1986,11 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
 #pragma unroll
             for (int i = 0; i < 5; ++i) cd[i] = S.pc.dq[i];
             SymStencil st;
-            sym_stencil_setup(S, c, start, nact, sym_base, lane, st);
+            sym_stencil_setup(S, c, start, nact, sym_base, sym_pref, lane, st);
             const int D = __shfl(st.cnt, 0);
             const int c0s = start[c];
             const int w0 = k * kW, w1 = min(w0 + kW, st.total);
-            const int tbase = sym_base[(int64_t)kSymStride * c] + k * D;
+            const int tbase = sym_base[c] + k * D;  // group 0: the target slots
             for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
             const int p0 = g * K, p1 = min(p0 + K, D / kWave);
             auto fetch_pg = [&](int v, float4 &a, float4 &gv) {
@@ -2033,7 +2081,8 @@ template <class Acc, bool kSoft, int kW, int kOcc>
 __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, const int4 *__restrict__ items, uint32_t *hdr,
                                                 const int *__restrict__ start,
                                                 const int *__restrict__ nact,
-                                                const int *__restrict__ sym_base, Src src,
+                                                const int *__restrict__ sym_base,
+                                                const int *__restrict__ sym_pref, Src src,
                                                 const float *__restrict__ gx, const float *__restrict__ gy,
                                                 const float *__restrict__ gz, float *__restrict__ pool, int K,
                                                 int64_t pull_limit)
@@ -2043,10 +2092,10 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, co
     __shared__ int tix[kWave];
     __shared__ SymRed<kW> red;
     if (hdr[kHdrMassInfo] == 0)
-        vjp_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, src, gx, gy, gz, pool, K,
+        vjp_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, gx, gy, gz, pool, K,
                                             tile_p, tile_g, tix, red, pull_limit);
     else
-        vjp_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, src, gx, gy, gz, pool, K,
+        vjp_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, gx, gy, gz, pool, K,
                                              tile_p, tile_g, tix, red, pull_limit);
 }
 
@@ -2061,7 +2110,7 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, co
 __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const int *__restrict__ key,
                                                     const int *__restrict__ start,
                                                     const int *__restrict__ nact,
-                                                    const int *__restrict__ sym_cnt,
+                                                    const int *__restrict__ sym_pref,
                                                     const int *__restrict__ sym_base,
                                                     const float *__restrict__ pool,
                                                     const int *__restrict__ rows,
@@ -2080,8 +2129,8 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
     const int per = dense ? D : start[c + 1] - start[c] - D;  // particles of a slot row
     const int j = dense ? jl : jl - D;
     const int e0 = dense ? 0 : 1 + kSymDirs, e1 = dense ? 1 + kSymDirs : kSymStride;
-    const int *cn = sym_cnt + (int64_t)kSymStride * c;
-    const int *bs = sym_base + (int64_t)kSymStride * c;
+    const int *pf = sym_pref + (int64_t)kSymStride * c;
+    const int cb = sym_base[c], ctot = sym_base[c + 1] - cb;
     struct F3 {
         float x, y, z;
     };
@@ -2090,8 +2139,8 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
     // together), combined in a fixed order at the end
     float x[4] = {0.f, 0.f, 0.f, 0.f}, y[4] = {0.f, 0.f, 0.f, 0.f}, z[4] = {0.f, 0.f, 0.f, 0.f};
     for (int e = e0; e < e1; ++e) {
-        const int n = cn[e] / per;
-        int64_t o = (int64_t)bs[e] + j;
+        const int n = ((e + 1 < kSymStride ? pf[e + 1] : ctot) - pf[e]) / per;
+        int64_t o = (int64_t)cb + pf[e] + j;
         int t = 0;
         for (; t + 4 <= n; t += 4, o += 4 * (int64_t)per) {
             F3 v[4];
@@ -2232,15 +2281,17 @@ hipError_t build_items(const DevArgs &a, int two)
     });
 }
 
-// Symmetric tiles: partial-slot counts and their scan, the go/no-go decision
+// Symmetric tiles: partial-slot counts and the scan of their cell totals, the go/no-go decision
 // (hdr[kHdrSymOk]) and the items.  Must precede build_items, whose dense
 // items then take only the non-dense sources.  With the tiles switched off
 // the decision is no.
+unsigned persistent_grid(const DevArgs &a);
+
 hipError_t build_sym(const DevArgs &a)
 {
     const Layout &L = *a.L;
     uint32_t *hdr = at<uint32_t>(a, L.hdr);
-    hipError_t e = fill_u32(hdr + kHdrSymTotal, 4, 0, a.st);  // total, ok, n_items
+    hipError_t e = fill_u32(hdr + kHdrSymTotal, 7, 0, a.st);  // total, ok, n_items, work, longest
     if (e != hipSuccess || a.sym_blocks <= 0) return e;
     if ((e = fill_u32(hdr + kHdrSymBucketCount, kClasses, 0, a.st)) != hipSuccess) return e;
     const int W = a.sym_window;
@@ -2248,14 +2299,16 @@ hipError_t build_sym(const DevArgs &a)
         const unsigned nb = blocks_for(L.NC, 256);
         k_sym_count<<<nb, 256, 0, a.st>>>(acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact),
                                           a.sym_blocks, W,
-                                          at<int>(a, L.sym_cnt), at<uint32_t>(a, L.sym_info), hdr,
-                                          L.magic());
+                                          at<int>(a, L.sym_pref), at<int>(a, L.sym_tot),
+                                          at<uint32_t>(a, L.sym_info), hdr, L.magic());
         hipError_t e2 = hipGetLastError();
         if (e2 != hipSuccess) return e2;
-        if ((e2 = scan_i32(at<int>(a, L.sym_cnt), at<int>(a, L.sym_base), kSymStride * L.NC,
-                           at<int>(a, L.scan_tmp), a.st)) != hipSuccess)
+        if ((e2 = scan_i32(at<int>(a, L.sym_tot), at<int>(a, L.sym_base), L.NC, at<int>(a, L.scan_tmp),
+                           a.st)) != hipSuccess)
             return e2;
-        k_sym_base<<<1, 64, 0, a.st>>>(hdr, L.magic(), (long long)L.sym_cap, 1);
+        int64_t waves = persistent_grid(a);
+        if (waves > L.sym_item_cap) waves = L.sym_item_cap;
+        k_sym_base<<<1, 64, 0, a.st>>>(hdr, L.magic(), (long long)L.sym_cap, 1, (int)waves, a.sym_balance);
         k_sym_write<<<nb, 256, 0, a.st>>>(acc, (int)L.NC, at<int>(a, L.nact), a.sym_blocks,
                                           at<uint32_t>(a, L.sym_info), hdr, at<int4>(a, L.sym_items));
         return hipGetLastError();
@@ -2391,7 +2444,8 @@ void launch_force_sym_v(const DevArgs &a, Acc acc, unsigned grid)
     const Layout &L = *a.L;
     k_force_sym<Acc, kSoft, kW, kOcc><<<grid, kWave, 0, a.st>>>(
         acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
-        at<int>(a, L.sym_base), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+        at<int>(a, L.sym_base), at<int>(a, L.sym_pref), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks,
+        a.pull_limit);
 }
 
 template <class Acc, bool kSoft>
@@ -2416,8 +2470,8 @@ void launch_vjp_sym_v(const DevArgs &a, Acc acc, unsigned grid)
     const Layout &L = *a.L;
     k_vjp_sym<Acc, kSoft, kW, kOcc><<<grid, kWave, 0, a.st>>>(
         acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
-        at<int>(a, L.sym_base), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy), at<float>(a, L.gz),
-        at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+        at<int>(a, L.sym_base), at<int>(a, L.sym_pref), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy),
+        at<float>(a, L.gz), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
 }
 
 template <class Acc, bool kSoft>
@@ -2440,7 +2494,7 @@ hipError_t sym_gather(const DevArgs &a, const int *rows, float *out, int n_out)
     const Layout &L = *a.L;
     k_sym_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
         (int)L.N, L.key_bits, at<int>(a, L.sorted_keys()), at<int>(a, L.start), at<int>(a, L.nact),
-        at<int>(a, L.sym_cnt), at<int>(a, L.sym_base), at<float>(a, L.sym_pool), rows, at<float>(a, L.bm),
+        at<int>(a, L.sym_pref), at<int>(a, L.sym_base), at<float>(a, L.sym_pool), rows, at<float>(a, L.bm),
         at<uint32_t>(a, L.hdr), out, n_out);
     return hipGetLastError();
 }

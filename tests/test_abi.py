@@ -28,7 +28,7 @@ def test_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(_sr.EXPORTS)
-    assert L.sr_abi_version() == 5 == _sr.ABI_VERSION
+    assert L.sr_abi_version() == 6 == _sr.ABI_VERSION
     assert L.sr_status_str(0) == b"ok"
 
 
@@ -237,3 +237,18 @@ def test_tile_config_validation():
     for k, v in saved.items():
         _sr.tile_config(*v, kernel=k)
     assert {k: _sr.tile_config(kernel=k) for k in ("force", "vjp")} == saved
+
+
+def test_tile_balance_validation():
+    L = _sr.lib()
+    cur = C.c_double()
+    saved = _sr.tile_balance()
+    assert saved == 1.0
+    for bad in (-2.0, -0.5, float("nan"), float("inf")):
+        assert L.sr_tile_balance(bad, C.byref(cur)) == 1, bad
+    assert _sr.tile_balance() == saved  # rejected values change nothing
+    assert _sr.tile_balance(0.0) == 0.0
+    assert _sr.tile_balance(2.5) == 2.5
+    assert L.sr_tile_balance(-1.0, None) == 0
+    _sr.tile_balance(saved)
+    assert _sr.tile_balance() == saved

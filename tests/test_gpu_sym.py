@@ -2,8 +2,11 @@
 pair of dense particles evaluated once, both opposite terms kept in partial
 slots and gathered in a fixed order.  Checked against the float64 oracle at
 several tile sizes, against the one-sided kernels (tiles off), run to run
-bitwise, and on a problem whose partial slots do not fit the pool (the tiles
-then stay off and the one-sided kernels do all the work)."""
+bitwise, on a problem whose partial slots do not fit the pool (the tiles
+then stay off and the one-sided kernels do all the work), and under the
+balance rule that keeps them off when a few long items would dominate.
+These test problems are small, so the balance rule is switched off (0)
+wherever the tiles are meant to run."""
 import numpy as np
 import pytest
 import torch
@@ -18,11 +21,13 @@ pytestmark = pytest.mark.gpu
 HDR_SYM_OK = 518  # header word: the symmetric tiles ran
 
 
-def run(w, g, kernel_tiles=None, extra_slots=80):
+def run(w, g, kernel_tiles=None, extra_slots=80, balance=0.0):
     """Forward and adjoint on a fresh workspace with room for extra_slots more partial slots
     per particle than sr_workspace_bytes reserves; returns (acc, grad, sym_ok_fwd, sym_ok_vjp)."""
     saved = {k: sr.tile_config(kernel=k) for k in ("force", "vjp")}
+    saved_balance = sr.tile_balance()
     try:
+        sr.tile_balance(balance)
         if kernel_tiles is not None:
             for k in ("force", "vjp"):
                 sr.tile_config(*kernel_tiles, kernel=k)
@@ -40,6 +45,7 @@ def run(w, g, kernel_tiles=None, extra_slots=80):
     finally:
         for k, v in saved.items():
             sr.tile_config(*v, kernel=k)
+        sr.tile_balance(saved_balance)
 
 
 def dense_cases():
@@ -136,3 +142,22 @@ def test_partial_slots_beyond_the_pool_fall_back():
         assert ok_f == want and ok_v == want
         assert_force_close(a[idx], acc_ref, what=f"extra {extra}")
         assert oracle.rms_rel(gr[idx], gref) <= VJP_TOL
+
+
+def test_balance_rule_keeps_long_items_off():
+    # 27 cells of 300 particles: at 256 blocks per item each cell is one item,
+    # far longer than the work per wave of the persistent grid, so the default
+    # balance rule keeps the tiles off; with the rule at 0 they run.  Either
+    # way the forces match the oracle and each other to rounding order.
+    w = dense_cases()["small_periodic"]()
+    g = synth.cotangent(w.n_active, 5)
+    ref = oracle_force(w)
+    announce(f"balance rule n={w.n}")
+    a1, g1, f1, v1 = run(w, g, (256, 256), balance=1.0)
+    assert f1 == 0 and v1 == 0
+    a0, g0, f0, v0 = run(w, g, (256, 256), balance=0.0)
+    assert f0 == 1 and v0 == 1
+    for a in (a0, a1):
+        assert_force_close(a, ref, what="balance rule")
+    assert oracle.rms_rel(a0, a1) <= 2e-6
+    assert oracle.rms_rel(g0, g1) <= 2e-5

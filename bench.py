@@ -148,7 +148,7 @@ def batch_comparison(reps: int = 5):
             "ms_graph": round(out["graph"], 3), "ms_per_subvolume": round(out["per_subvolume"], 3),
             "speedup": round(out["per_subvolume"] / out["graph"], 3),
             "waves_per_cu": info["waves_per_cu"], "sym_blocks": info["sym_blocks"],
-            "sym_window": info["sym_window"]}
+            "sym_window": info["sym_window"], "sparse_group": info["sparse_group"]}
 
 
 def block_comparison(w, pos, mass, acc_mono, reps: int = 3):

@@ -253,8 +253,9 @@ sr_status sr_ws_flags(const void *ws, void *stream, uint32_t *flags /*host out*/
  *
  * sr_batch_plan_create (host) validates the batch, lays out the workspace
  * and reports its size in *ws_bytes.  tune_cache (host, nullable) names a
- * JSON file in which the launch parameters and symmetric tiles measured on
- * the first run are kept (the tiles change only the order of float32 sums).
+ * JSON file in which the launch parameters, symmetric tiles and sparse-cell
+ * item size measured on the first run are kept (the last two change only the
+ * order of float32 sums).
  * The plan owns only host memory, one HIP stream and, after the first run
  * in graph mode, a captured HIP graph of the whole bin-then-force sequence
  * bound to the pointers (pos, mass, ws, acc, momentum) of that run.  A later
@@ -271,7 +272,8 @@ sr_status sr_batch_plan_create(int32_t B, const int64_t *offsets /*host [B+1]*/,
  * SR_BATCH_PER_SUBVOLUME (one sr_force per subvolume, the reference mode),
  * SR_BATCH_EAGER (batched kernels without a graph), 0 (graph replay; with
  * SR_BATCH_RECAPTURE, capture again for new pointers).  The first run, in
- * any mode, tunes the launch parameters and the symmetric tiles by timing
+ * any mode, tunes the launch parameters, the symmetric tiles and the targets
+ * per item of cells with fewer than 64 targets (16, 32 or 8) by timing
  * batched runs (it synchronises), so that every mode then uses the same. */
 sr_status sr_batch_force(sr_batch_plan *plan, const float *pos, const float *mass, void *ws,
                          size_t ws_bytes, float *acc, double *momentum, unsigned flags,
@@ -445,7 +447,10 @@ sr_status sr_power_spectrum(sr_pk_plan *plan, const float *pos, const float *mas
  * writes the forward kernel's values in effect to cur (host, nullable,
  * int[3]).  The initial values differ per kernel (forward: 32, 1, 6; adjoint:
  * 24, 2, 0, the fastest measured); SR_WAVES_PER_CU / SR_TARGETS_PER_LANE /
- * SR_OCCUPANCY override them for both. */
+ * SR_OCCUPANCY override them for both.  SR_SPARSE_GROUP (8, 16, 32 or 64;
+ * default 16) sets the most targets per item of a cell, or the remainder of
+ * a cell, with fewer than 64 targets; it changes the order of float32 sums
+ * only. */
 sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy,
                            int *cur /*host out*/);
 

@@ -147,7 +147,7 @@ Layout make_layout(int64_t N, int64_t NC, int B, int64_t mom_tiles, bool any_pas
     L.table = (int64_t(1) << L.digit_bits) * L.ntiles;
     // a run of n targets makes at most ceil(n / kSparseGroup) items, and a
     // cell has up to two runs (active targets; passive ones in the adjoint)
-    L.item_cap = 2 * NC + (N + kSparseGroup - 1) / kSparseGroup + 1;
+    L.item_cap = 2 * NC + (N + kMinSparseGroup - 1) / kMinSparseGroup + 1;
     L.mom_tiles = mom_tiles;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -244,6 +244,7 @@ std::atomic<int> g_sym_blocks[2] = {{16}, {16}};
 std::atomic<int> g_sym_window[2] = {{512}, {256}};
 std::atomic<int> g_sym_occ[2] = {{5}, {5}};
 std::atomic<double> g_sym_balance{1.0};
+std::atomic<int> g_sparse_group{kSparseGroup};
 
 // Launch defaults may be overridden for experiments (both kernels):
 // SR_WAVES_PER_CU, SR_TARGETS_PER_LANE, SR_OCCUPANCY.
@@ -275,6 +276,10 @@ struct EnvDefaults {
                 const int o = std::atoi(v);
                 if (o == 0 || o == 5 || o == 6) g_sym_occ[k] = o;
             }
+        }
+        if (const char *v = std::getenv("SR_SPARSE_GROUP")) {
+            const int gsz = std::atoi(v);
+            if (gsz == 8 || gsz == 16 || gsz == 32 || gsz == 64) g_sparse_group = gsz;
         }
         if (const char *v = std::getenv("SR_SYM_BALANCE")) {
             const double b = std::atof(v);
@@ -329,6 +334,7 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.sym_window = g_sym_window[cfg].load();
     a.sym_occupancy = g_sym_occ[cfg].load();
     a.sym_balance = g_sym_balance.load();
+    a.sparse_group = g_sparse_group.load();
     a.pull_limit = pull_limit();
     return SR_OK;
 }
@@ -403,6 +409,7 @@ struct sr_batch_plan {
     int occupancy = 0;
     int sym_blocks = -1;                // symmetric tiles (-1: the forward kernel's current setting)
     int sym_window = -1;
+    int sparse_group = -1;              // targets per item of sparse cells (-1: the process-wide value)
     std::string tune_cache;
     std::string tune_key;
     double tuned_ms = -1.0;
@@ -422,6 +429,7 @@ sr_status run_batched(sr_batch_plan *P, const float *pos, const float *mass, voi
     a.occupancy = P->occupancy;
     if (P->sym_blocks >= 0) a.sym_blocks = P->sym_blocks;
     if (P->sym_window > 0) a.sym_window = P->sym_window;
+    if (P->sparse_group > 0) a.sparse_group = P->sparse_group;
     // the plan's tuner already timed the tiles against none, and the same
     // decision must hold in every mode (bitwise agreement): no balance rule
     a.sym_balance = 0.0;
@@ -449,6 +457,7 @@ sr_status run_per_subvolume(sr_batch_plan *P, const float *pos, const float *mas
         a.occupancy = P->occupancy;
         if (P->sym_blocks >= 0) a.sym_blocks = P->sym_blocks;
         if (P->sym_window > 0) a.sym_window = P->sym_window;
+        if (P->sparse_group > 0) a.sparse_group = P->sparse_group;
         a.sym_balance = 0.0;
         if (n > 0) {
             if (dev_bin(a, pos + 3 * off, mass + off) != hipSuccess) return SR_E_DEVICE;
@@ -487,7 +496,7 @@ std::string arch_name()
 
 // Minimal reader of the tune cache: one line per key, "key waves".
 bool cache_lookup(const std::string &path, const std::string &key, int &waves, int &tpl, int &occ,
-                  int &sym_blocks, int &sym_window)
+                  int &sym_blocks, int &sym_window, int &group)
 {
     if (path.empty()) return false;
     std::ifstream in(path);
@@ -510,13 +519,17 @@ bool cache_lookup(const std::string &path, const std::string &key, int &waves, i
         const int sbv = sb == std::string::npos ? -1 : std::atoi(line.c_str() + sb + 13);
         const size_t sw = line.find("\"sym_window\":", q1);
         const int swv = sw == std::string::npos ? -1 : std::atoi(line.c_str() + sw + 13);
+        const size_t sg = line.find("\"sparse_group\":", q1);
+        const int sgv = sg == std::string::npos ? -1 : std::atoi(line.c_str() + sg + 15);
         if (v >= 1 && v <= 64 && (tv == 1 || tv == 2) && (ov == 0 || ov == 6 || ov == 8) && sbv >= -1 &&
-            sbv <= 256 && (swv == -1 || swv == 256 || swv == 512)) {
+            sbv <= 256 && (swv == -1 || swv == 256 || swv == 512) &&
+            (sgv == -1 || sgv == 8 || sgv == 16 || sgv == 32 || sgv == 64)) {
             waves = v;
             tpl = tv;
             occ = ov;
             sym_blocks = sbv;
             sym_window = swv;
+            group = sgv;
             return true;
         }
     }
@@ -524,7 +537,7 @@ bool cache_lookup(const std::string &path, const std::string &key, int &waves, i
 }
 
 void cache_store(const std::string &path, const std::string &key, int waves, int tpl, int occ,
-                 int sym_blocks, int sym_window, double ms)
+                 int sym_blocks, int sym_window, int group, double ms)
 {
     if (path.empty()) return;
     std::vector<std::string> keep;
@@ -546,7 +559,7 @@ void cache_store(const std::string &path, const std::string &key, int waves, int
     std::ostringstream e;
     e << "  \"" << key << "\": {\"waves_per_cu\": " << waves << ", \"targets_per_lane\": " << tpl
       << ", \"occupancy\": " << occ << ", \"sym_blocks\": " << sym_blocks << ", \"sym_window\": "
-      << sym_window << ", \"ms\": " << ms << "}";
+      << sym_window << ", \"sparse_group\": " << group << ", \"ms\": " << ms << "}";
     keep.push_back(e.str());
     const std::string tmp = path + ".tmp";
     {
@@ -562,19 +575,21 @@ void cache_store(const std::string &path, const std::string &key, int waves, int
 // Pick the launch parameters (persistent grid in waves per CU, targets per
 // lane of dense items, register-allocation variant) by timing the batched
 // sequence, then the tiles of the symmetric kernel (blocks per item, window,
-// or off) with those parameters.  Launch parameters do not change results;
-// the tiles change only the order of the float32 sums (and so the last bits),
-// and are fixed once the plan is tuned.
+// or off), then the targets per item of sparse cells, each stage with the
+// choices before it.  Launch parameters do not change results; the tiles and
+// the sparse groups change only the order of the float32 sums (and so the
+// last bits), and are fixed once the plan is tuned.
 sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, float *acc,
                hipStream_t st)
 {
-    int waves = 0, tpl = 1, occ = 0, sb = -1, sw = -1;
-    if (cache_lookup(P->tune_cache, P->tune_key, waves, tpl, occ, sb, sw)) {
+    int waves = 0, tpl = 1, occ = 0, sb = -1, sw = -1, sg = -1;
+    if (cache_lookup(P->tune_cache, P->tune_key, waves, tpl, occ, sb, sw, sg)) {
         P->waves_per_cu = waves;
         P->targets_per_lane = tpl;
         P->occupancy = occ;
         P->sym_blocks = sb;
         P->sym_window = sw;
+        P->sparse_group = sg;
         return SR_OK;
     }
     hipEvent_t e0, e1;
@@ -604,6 +619,7 @@ sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, 
     Cand pick{g_waves_default[kCfgForce].load(), 1, 0};
     P->sym_blocks = -1;
     P->sym_window = -1;
+    P->sparse_group = -1;
     for (const Cand &c : cand) {
         P->waves_per_cu = c.w;
         P->targets_per_lane = c.t;
@@ -636,12 +652,26 @@ sr_status tune(sr_batch_plan *P, const float *pos, const float *mass, void *ws, 
             tpick = t;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     P->sym_blocks = tpick.k;
     P->sym_window = tpick.w;
-    P->tuned_ms = std::min(best, best_t) / 2.0;
-    cache_store(P->tune_cache, P->tune_key, pick.w, pick.t, pick.o, tpick.k, tpick.w, P->tuned_ms);
+    const int groups[] = {16, 32, 8};
+    int gpick = kSparseGroup;
+    double best_g = 1e300;
+    for (const int gsz : groups) {
+        P->sparse_group = gsz;
+        double ms = 0;
+        const sr_status s = time_runs(ms);
+        if (s != SR_OK) return s;
+        if (ms < best_g) {
+            best_g = ms;
+            gpick = gsz;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->sparse_group = gpick;
+    P->tuned_ms = std::min(best, std::min(best_t, best_g)) / 2.0;
+    cache_store(P->tune_cache, P->tune_key, pick.w, pick.t, pick.o, tpick.k, tpick.w, gpick, P->tuned_ms);
     return SR_OK;
 }
 
@@ -991,7 +1021,8 @@ sr_status sr_batch_plan_info(const sr_batch_plan *P, char *buf, size_t buf_bytes
       << P->total_active << ", \"cells\": " << P->L.NC << ", \"ws_bytes\": " << P->ws_bytes
       << ", \"waves_per_cu\": " << P->waves_per_cu << ", \"targets_per_lane\": "
       << P->targets_per_lane << ", \"occupancy\": " << P->occupancy << ", \"sym_blocks\": "
-      << P->sym_blocks << ", \"sym_window\": " << P->sym_window << ", \"tuned_ms\": "
+      << P->sym_blocks << ", \"sym_window\": " << P->sym_window << ", \"sparse_group\": "
+      << P->sparse_group << ", \"tuned_ms\": "
       << P->tuned_ms
       << ", \"tune_key\": \"" << P->tune_key << "\", \"graph\": " << (P->exec ? "true" : "false")
       << "}";

@@ -13,7 +13,8 @@ namespace sr {
 
 constexpr int kWave = 64;
 constexpr int kTargetsPerItem = 64;  // one target per lane in a dense cell
-constexpr int kSparseGroup = 16;     // most targets per item of a cell with fewer than 64
+constexpr int kSparseGroup = 16;     // default: most targets per item of a cell with fewer than 64
+constexpr int kMinSparseGroup = 8;   // the smallest group size (sizes the item list)
 constexpr int kXcds = 8;             // XCDs of an MI355X; workgroups are dealt to them in turn
 constexpr int kQueues = kXcds;       // one work queue per XCD
 constexpr int kQueueBlock = 32;      // consecutive items a queue takes from the list
@@ -141,6 +142,7 @@ struct DevArgs {
     int sym_window;        // symmetric tiles: sources per item window (256 or 512)
     int sym_occupancy;     // symmetric tiles: register-allocation hint, 0 or 5 waves/SIMD
     double sym_balance;    // symmetric tiles run only if their steps per wave reach this many longest items
+    int sparse_group;      // most targets per item of a cell (or remainder) with fewer than 64: 8, 16, 32 or 64
     int64_t pull_limit;    // most items one wave of a persistent kernel may pull (test hook)
 };
 

@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_gather_g(int N, int n_rows,
 // --------------------------------------------------------------- work items
 
 // Items of a home cell with nt targets.  A cell of fewer than 64 targets is cut
-// into items of at most kSparseGroup consecutive targets (leaf order), each with
+// into items of at most `group` consecutive targets (leaf order), each with
 // 2^lk lanes per target: a smaller group has a tighter box, so fewer of the
 // sources it stages lie out of reach of its targets.  A larger cell is cut into
 // items of 64 targets (128, two per lane, with `two`; then a last 64 when an
@@ -506,12 +506,12 @@ __device__ __forceinline__ int lanes_log2(int n)
     return n >= kTargetsPerItem ? 0 : (31 - __clz(kTargetsPerItem / n));
 }
 
-__device__ __forceinline__ int cell_items(int nt, bool two)
+__device__ __forceinline__ int cell_items(int nt, bool two, int group)
 {
-    if (nt < kTargetsPerItem) return (nt + kSparseGroup - 1) / kSparseGroup;
+    if (nt < kTargetsPerItem) return (nt + group - 1) / group;
     const int r = nt % kTargetsPerItem, groups = nt / kTargetsPerItem;
     const int dense = two ? (groups + 1) / 2 : groups;
-    return dense + (r + kSparseGroup - 1) / kSparseGroup;
+    return dense + (r + group - 1) / group;
 }
 
 // Work item: x = home cell, y = first target slot, z = targets,
@@ -537,15 +537,16 @@ __device__ __forceinline__ int item_seg(int w) { return w >> 6; }
 __device__ __forceinline__ int dense_count(int na) { return na >= kWave ? (na & ~(kWave - 1)) : 0; }
 
 // Items of a run of nt consecutive targets from slot s0 (the cut described
-// above); returns the number written, cell_items(nt, two).
+// above, groups of at most `group` targets); returns the number written,
+// cell_items(nt, two, group).
 __device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, int c, int s0, int nt,
-                                         bool two, int seg, int psrc, int nd = 0)
+                                         bool two, int seg, int psrc, int nd, int group)
 {
     if (nt <= 0) return 0;
     int k = 0;
     if (nt < kTargetsPerItem) {
-        for (int t = 0; t < nt; t += kSparseGroup, ++k) {
-            const int cn = min(kSparseGroup, nt - t);
+        for (int t = 0; t < nt; t += group, ++k) {
+            const int cn = min(group, nt - t);
             items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg, nd));
         }
         return k;
@@ -556,8 +557,8 @@ __device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, 
         items[at + k] = make_int4(c, s0 + t0, cn, item_word(0, cn > kTargetsPerItem ? 1 : 0, psrc, seg, nd));
         t0 += cn;
     }
-    for (int t = dense_end; t < nt; t += kSparseGroup, ++k) {
-        const int cn = min(kSparseGroup, nt - t);
+    for (int t = dense_end; t < nt; t += group, ++k) {
+        const int cn = min(group, nt - t);
         items[at + k] = make_int4(c, s0 + t, cn, item_word(lanes_log2(cn), 0, psrc, seg, nd));
     }
     return k;
@@ -565,10 +566,10 @@ __device__ __forceinline__ int write_run(int4 *__restrict__ items, uint32_t at, 
 
 // Cost of the widest item of a run of nt targets that sees src sources:
 // pairs one lane evaluates.
-__device__ __forceinline__ int64_t run_cost(int nt, int64_t src, bool two)
+__device__ __forceinline__ int64_t run_cost(int nt, int64_t src, bool two, int group)
 {
     if (nt <= 0) return 0;
-    const int lk = nt >= kTargetsPerItem ? 0 : lanes_log2(min(nt, kSparseGroup));
+    const int lk = nt >= kTargetsPerItem ? 0 : lanes_log2(min(nt, group));
     const int chunk = (two && nt > kTargetsPerItem) ? 2 * kTargetsPerItem : kTargetsPerItem;
     return ((src + (1 << lk) - 1) >> lk) * (chunk / kTargetsPerItem);
 }
@@ -584,7 +585,7 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
                                                  const int *__restrict__ start,
                                                  const int *__restrict__ nact,
                                                  uint32_t *__restrict__ info, uint32_t *blk,
-                                                 bool ok, int N, bool two, bool sym)
+                                                 bool ok, int N, bool two, bool sym, int group)
 {
     if (c >= NC) return;
     if (!ok) {
@@ -629,14 +630,14 @@ __device__ __forceinline__ void items_count_cell(const Acc &acc, int c, int NC,
             }
         }
     }
-    // cost class from the cell's widest item: a group of min(nt, kSparseGroup) targets when sparse.
+    // cost class from the cell's widest item: a group of min(nt, group) targets when sparse.
     // With symmetric tiles the dense blocks have no item here, and the other
     // targets take only the non-dense sources (the symmetric tiles give them
     // the terms of the dense ones)
     const int dn = sym ? dense_count(na) : 0;
-    const int n_items = cell_items(na - dn, two) + cell_items(np, two);
-    int64_t cost = sym ? max(run_cost(na - dn, src_nd, two), run_cost(np, src_act_nd, two))
-                       : max(run_cost(na, src, two), run_cost(np, src_act, two));
+    const int n_items = cell_items(na - dn, two, group) + cell_items(np, two, group);
+    int64_t cost = sym ? max(run_cost(na - dn, src_nd, two, group), run_cost(np, src_act_nd, two, group))
+                       : max(run_cost(na, src, two, group), run_cost(np, src_act, two, group));
     if (cost < 1) cost = 1;
     int cls = 63 - __clzll((unsigned long long)cost);
     cls = cls > 31 ? 31 : cls;
@@ -649,7 +650,7 @@ template <class Acc, bool kActiveOnly>
 __global__ __launch_bounds__(256) void k_items_count(Acc acc, int NC, const int *__restrict__ start,
                                                      const int *__restrict__ nact,
                                                      uint32_t *__restrict__ info, uint32_t *hdr,
-                                                     uint32_t magic, int N, int two)
+                                                     uint32_t magic, int N, int two, int group)
 {
     __shared__ uint32_t blk[kClasses];
     if (threadIdx.x < kClasses) blk[threadIdx.x] = 0;
@@ -658,7 +659,7 @@ __global__ __launch_bounds__(256) void k_items_count(Acc acc, int NC, const int 
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (!ok && c == 0) atomicOr(&hdr[kHdrFlags], (uint32_t)SR_FLAG_NOT_BINNED);
     items_count_cell<Acc, kActiveOnly>(acc, c, NC, start, nact, info, blk, ok, N, two != 0,
-                                       hdr[kHdrSymOk] != 0);
+                                       hdr[kHdrSymOk] != 0, group);
     __syncthreads();
     if (threadIdx.x < kClasses && blk[threadIdx.x])
         atomicAdd(&hdr[kHdrBucketCount + threadIdx.x], blk[threadIdx.x]);
@@ -684,7 +685,7 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
                                                      const int *__restrict__ nact,
                                                      const uint32_t *__restrict__ info,
                                                      uint32_t *hdr, int4 *__restrict__ items,
-                                                     int two)
+                                                     int two, int group)
 {
     __shared__ uint32_t cnt[kClasses];
     __shared__ uint32_t base[kClasses];
@@ -711,8 +712,8 @@ __global__ __launch_bounds__(256) void k_items_write(Acc acc, int NC, const int 
     // with symmetric tiles only the non-dense targets, against the non-dense sources
     const int sym = hdr[kHdrSymOk] != 0 ? 1 : 0;
     const int dn = sym ? dense_count(na) : 0;
-    const int k = write_run(items, at, c, s0 + dn, na - dn, two, seg, 0, sym);
-    if (!kActiveOnly) write_run(items, at + k, c, s0 + na, nt - na, two, seg, 1, sym);
+    const int k = write_run(items, at, c, s0 + dn, na - dn, two, seg, 0, sym, group);
+    if (!kActiveOnly) write_run(items, at + k, c, s0 + na, nt - na, two, seg, 1, sym, group);
 }
 
 // --------------------------------------------------------------- pair kernels
@@ -2272,11 +2273,11 @@ hipError_t build_items(const DevArgs &a, int two)
         const unsigned nb = blocks_for(L.NC, 256);
         k_items_count<decltype(acc), kActiveOnly><<<nb, 256, 0, a.st>>>(
             acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact), at<uint32_t>(a, L.info), hdr,
-            L.magic(), (int)L.N, two);
+            L.magic(), (int)L.N, two, a.sparse_group);
         k_items_base<<<1, 64, 0, a.st>>>(hdr, L.magic());
         k_items_write<decltype(acc), kActiveOnly><<<nb, 256, 0, a.st>>>(
             acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact), at<uint32_t>(a, L.info), hdr,
-            at<int4>(a, L.items), two);
+            at<int4>(a, L.items), two, a.sparse_group);
         return hipGetLastError();
     });
 }

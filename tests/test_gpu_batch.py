@@ -145,6 +145,9 @@ def test_tune_cache_roundtrip(tmp_path):
     t1 = (p1.info()["sym_blocks"], p1.info()["sym_window"])
     assert t1 in {(16, 512), (16, 256), (64, 512), (4, 512), (0, 512)}
     assert (p2.info()["sym_blocks"], p2.info()["sym_window"]) == t1
+    # and the targets per item of sparse cells
+    assert p1.info()["sparse_group"] in {16, 32, 8}
+    assert p2.info()["sparse_group"] == p1.info()["sparse_group"]
     assert np.array_equal(a1.view(np.uint32), a2.view(np.uint32))
     import json
     assert p1.info()["tune_key"] in json.load(open(path))

@@ -447,10 +447,7 @@ sr_status sr_power_spectrum(sr_pk_plan *plan, const float *pos, const float *mas
  * writes the forward kernel's values in effect to cur (host, nullable,
  * int[3]).  The initial values differ per kernel (forward: 32, 1, 6; adjoint:
  * 24, 2, 0, the fastest measured); SR_WAVES_PER_CU / SR_TARGETS_PER_LANE /
- * SR_OCCUPANCY override them for both.  SR_SPARSE_GROUP (8, 16, 32 or 64;
- * default 16) sets the most targets per item of a cell, or the remainder of
- * a cell, with fewer than 64 targets; it changes the order of float32 sums
- * only. */
+ * SR_OCCUPANCY override them for both (see also sr_sparse_group). */
 sr_status sr_launch_config(int waves_per_cu, int targets_per_lane, int occupancy,
                            int *cur /*host out*/);
 
@@ -476,6 +473,13 @@ sr_status sr_launch_config_kernel(const char *kernel /*host*/, int waves_per_cu,
  * receives {blocks_per_item, window}. */
 sr_status sr_tile_config(const char *kernel /*host*/, int blocks_per_item, int window,
                          int *cur /*host out*/);
+
+/* Host only.  Most targets per item of a cell, or the remainder of a cell,
+ * with fewer than 64 targets: 8, 16, 32 or 64 (-1 keeps the value; initial
+ * 16, or SR_SPARSE_GROUP).  Smaller groups have tighter boxes and stage their
+ * sources more often; the choice changes only the order of float32 sums.
+ * Batch plans tune their own.  cur (nullable) receives the value in effect. */
+sr_status sr_sparse_group(int group, int *cur /*host out*/);
 
 /* Host only.  When the symmetric tiles pay: they run only if their work (tile
  * steps of all items) spread over the persistent grid's waves is at least

@@ -36,7 +36,7 @@ EXPORTS = ("sr_abi_version", "sr_status_str", "sr_grid", "sr_workspace_bytes", "
            "sr_blocks_problems", "sr_blocks_partition", "sr_blocks_gather", "sr_blocks_reconcile",
            "sr_blocks_reconcile_grad", "sr_centres_plan_create", "sr_centres_plan_destroy",
            "sr_centres", "sr_pk_plan_create", "sr_pk_plan_destroy", "sr_pk_deposit", "sr_pk_grid",
-           "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_tile_config", "sr_tile_balance",
+           "sr_power_spectrum", "sr_launch_config", "sr_launch_config_kernel", "sr_tile_config", "sr_tile_balance", "sr_sparse_group",
            "sr_timing_enable",
            "sr_timing_read")
 
@@ -126,6 +126,7 @@ def lib():
         L.sr_launch_config_kernel.argtypes = [C.c_char_p, C.c_int, C.c_int, C.c_int, p]
         L.sr_tile_config.argtypes = [C.c_char_p, C.c_int, C.c_int, p]
         L.sr_tile_balance.argtypes = [C.c_double, p]
+        L.sr_sparse_group.argtypes = [C.c_int, p]
         L.sr_timing_enable.argtypes = [C.c_int]
         L.sr_timing_read.argtypes = [C.c_char_p, p, p]
         for name in EXPORTS:
@@ -668,6 +669,14 @@ def launch_config(waves_per_cu: int = 0, targets_per_lane: int = 0, occupancy: i
         _check(lib().sr_launch_config_kernel(kernel.encode(), int(waves_per_cu), int(targets_per_lane),
                                              int(occupancy), cur), "sr_launch_config_kernel")
     return int(cur[0]), int(cur[1]), int(cur[2])
+
+
+def sparse_group(group: int = -1) -> int:
+    """Set and return the most targets per item of cells with fewer than 64 targets
+    (8, 16, 32 or 64; -1 keeps the value)."""
+    cur = C.c_int()
+    _check(lib().sr_sparse_group(int(group), C.byref(cur)), "sr_sparse_group")
+    return int(cur.value)
 
 
 def tile_balance(min_ratio: float = -1.0) -> float:

@@ -1083,6 +1083,14 @@ sr_status sr_tile_config(const char *kernel, int blocks_per_item, int window, in
     return SR_OK;
 }
 
+sr_status sr_sparse_group(int group, int *cur)
+{
+    if (group != -1 && group != 8 && group != 16 && group != 32 && group != 64) return SR_E_ARG;
+    if (group > 0) g_sparse_group = group;
+    if (cur) *cur = g_sparse_group.load();
+    return SR_OK;
+}
+
 sr_status sr_tile_balance(double min_ratio, double *cur)
 {
     if (!(min_ratio >= 0.0 || min_ratio == -1.0) || !std::isfinite(min_ratio)) return SR_E_ARG;

@@ -252,3 +252,17 @@ def test_tile_balance_validation():
     assert L.sr_tile_balance(-1.0, None) == 0
     _sr.tile_balance(saved)
     assert _sr.tile_balance() == saved
+
+
+def test_sparse_group_validation():
+    L = _sr.lib()
+    cur = C.c_int()
+    saved = _sr.sparse_group()
+    assert saved == 16
+    for bad in (0, 4, 12, 48, 128, -2):
+        assert L.sr_sparse_group(bad, C.byref(cur)) == 1, bad
+    assert _sr.sparse_group() == saved
+    for g in (8, 32, 64, 16):
+        assert _sr.sparse_group(g) == g
+    assert L.sr_sparse_group(-1, None) == 0
+    _sr.sparse_group(saved)

@@ -317,3 +317,26 @@ def test_persistent_loop_bound_flags_the_workspace(monkeypatch):
     plan.close()
     # without the limit everything is whole again
     assert_force_close(gpu_force(w), oracle_force(w), what="after the pull-limit runs")
+
+
+@pytest.mark.parametrize("group", [8, 32, 64])
+def test_sparse_group_sizes_match_oracle(group):
+    # items of sparse cells and remainders with 8, 32 or 64 targets (the
+    # default is 16): each matches the oracle, forward and adjoint, and
+    # differs from the default only in the order of float32 sums
+    w = synth.clustered_box(65536, 40.0, 61, 0)
+    w.mass = np.random.default_rng(2).uniform(0.5, 2.0, w.n).astype(np.float32)
+    g = synth.cotangent(w.n_active, 12)
+    announce(f"sparse group {group} n={w.n}")
+    saved = sr.sparse_group()
+    try:
+        a16, g16 = gpu_force(w), gpu_vjp(w, g)
+        sr.sparse_group(group)
+        a, gr = gpu_force(w), gpu_vjp(w, g)
+    finally:
+        sr.sparse_group(saved)
+    assert_force_close(a, oracle_force(w), what=f"group {group}")
+    e = oracle.rms_rel(gr, oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g))
+    assert e <= VJP_TOL, e
+    assert oracle.rms_rel(a, a16) <= 2e-6
+    assert oracle.rms_rel(gr, g16) <= 2e-5

@@ -241,7 +241,7 @@ std::atomic<int> g_occ_default[2] = {{6}, {0}};
 // Symmetric tiles of the dense cells, per kernel: blocks of 64 targets per
 // item (0: off) and sources per window (256 or 512).
 std::atomic<int> g_sym_blocks[2] = {{16}, {16}};
-std::atomic<int> g_sym_window[2] = {{512}, {256}};
+std::atomic<int> g_sym_window[2] = {{256}, {256}};
 std::atomic<int> g_sym_occ[2] = {{5}, {5}};
 std::atomic<double> g_sym_balance{1.0};
 std::atomic<int> g_sparse_group{kSparseGroup};

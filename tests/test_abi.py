@@ -225,7 +225,7 @@ def test_tile_config_validation():
     L = _sr.lib()
     cur = (C.c_int * 2)()
     saved = {k: _sr.tile_config(kernel=k) for k in ("force", "vjp")}
-    assert saved["force"] == (16, 512) and saved["vjp"] == (16, 256)
+    assert saved["force"] == (16, 256) and saved["vjp"] == (16, 256)
     assert L.sr_tile_config(b"bogus", 4, 256, cur) == 1
     assert L.sr_tile_config(None, 4, 256, cur) == 1
     assert L.sr_tile_config(b"force", 257, -1, cur) == 1

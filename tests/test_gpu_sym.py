@@ -83,7 +83,7 @@ def test_symmetric_tiles_match_oracle_and_one_sided(name):
     a0, g0, f0, v0 = run(w, g, (0, -1))
     assert f0 == 0 and v0 == 0
     assert_force_close(a0, ref, what=f"{name} one-sided")
-    for tiles in [(16, 512), (1, 256), (3, 512), (256, 256)]:
+    for tiles in [(16, 256), (16, 512), (1, 256), (3, 512), (256, 256)]:
         a, gr, ok_f, ok_v = run(w, g, tiles)
         assert ok_f == 1 and ok_v == 1, (tiles, ok_f, ok_v)
         assert_force_close(a, ref, what=f"{name} tiles {tiles}")

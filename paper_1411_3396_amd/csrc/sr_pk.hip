@@ -592,10 +592,15 @@ __global__ __launch_bounds__(256) void k_mass_final(const double *__restrict__ p
 
 // Modes of the half spectrum (iz in [0, ng/2]).  Each wave of a workgroup
 // takes whole rows (ix, iy) in a fixed order and keeps its own bins in LDS.
-// Along a row |n| grows with iz, so the bins of 64 consecutive modes form
-// runs: a segmented scan sums each run in a fixed tree order and the run's last
-// lane adds it to the wave's bins (within a chunk every run has its own bin,
-// so no two lanes touch one bin at once, and chunks go in order).  The waves'
+// Along a row |n| grows with iz, so each bin is one run of consecutive modes.
+// Lane l takes the S = ceil((ng/2 + 1) / 64) modes from l S on and sums its
+// runs in order; a run that starts and ends inside the lane goes to the bins
+// at once.  The runs at the lane edges are joined across lanes: F(l), the sum
+// of lane l's last run from where it starts (possibly in earlier lanes whose
+// single run it continues), is a segmented scan over the lanes, in a fixed
+// tree; a lane's first run adds F(l - 1) when it continues it; and each run is
+// added to the bins by the lane where it ends.  Within a row every bin is added
+// once and no two lanes touch one bin in the same instruction.  The waves'
 // bins are then added in wave order and written transposed,
 // part[(3 b + j) blocks + workgroup], for the last pass.  The sums therefore do
 // not depend on scheduling: the spectrum is bitwise reproducible.
@@ -612,52 +617,95 @@ __global__ __launch_bounds__(256) void k_pk_bins(const float2 *__restrict__ c, i
     for (int b = threadIdx.x; b < nw * nb3; b += blockDim.x) bins[b] = 0.0;
     __syncthreads();
     const int nzh = ng / 2 + 1;
+    const int S = (nzh + kWave - 1) / kWave;  // modes per lane
     const int64_t rows = (int64_t)ng * ng;
     const int64_t stride = (int64_t)gridDim.x * nw;
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+    auto add = [&](int key, double p, double km, double wt) {
+        if (key >= 0 && key < n_bins) {
+            wb[key] += p;
+            wb[n_bins + key] += km;
+            wb[2 * n_bins + key] += wt;
+        }
+    };
     for (int64_t r = (int64_t)blockIdx.x * nw + wv; r < rows; r += stride) {
         const int iy = (int)(r % ng), ix = (int)(r / ng);
         const int nx = ix <= ng / 2 ? ix : ix - ng;
         const int ny = iy <= ng / 2 ? iy : iy - ng;
         const double wxy = iw[ix] * iw[iy];
         const double r2 = (double)nx * nx + (double)ny * ny;
-        for (int z0 = 0; z0 < nzh; z0 += kWave) {
-            const int iz = z0 + lane;
+        // this lane's runs: the first (hk; hp, hm, hw), the current one (tk; tp, tm, tw);
+        // keys: a bin, -1 for k = 0, n_bins beyond the last bin (both never added)
+        int hk = -2, tk = -2, have = 0, single = 1;
+        double hp = 0.0, hm = 0.0, hw = 0.0, tp = 0.0, tm = 0.0, tw = 0.0;
+        for (int j = 0; j < S; ++j) {
+            const int iz = lane * S + j;
+            if (iz >= nzh) break;
             double p = 0.0, km = 0.0, wt = 0.0;
-            int key = -1;  // outside every bin: k = 0, beyond the last bin, past the row
-            if (iz < nzh) {
-                const double mag = sqrt(r2 + (double)iz * iz);
-                const int b = (int)floor(mag * inv_dn);
-                if (mag != 0.0 && b < n_bins) {
-                    const float2 v = c[r * nzh + iz];
-                    const double w = (iz == 0 || 2 * iz == ng) ? 1.0 : 2.0;
-                    p = w * (((double)v.x * v.x + (double)v.y * v.y) * (wxy * iw[iz]));
-                    km = w * mag;
-                    wt = w;
-                    key = b;
-                } else if (mag != 0.0) {
-                    key = n_bins;
-                }
+            const double mag = sqrt(r2 + (double)iz * iz);
+            const int b = (int)floor(mag * inv_dn);
+            int key = n_bins;
+            if (mag == 0.0) {
+                key = -1;
+            } else if (b < n_bins) {
+                const float2 v = c[r * nzh + iz];
+                const double w = (iz == 0 || 2 * iz == ng) ? 1.0 : 2.0;
+                p = w * (((double)v.x * v.x + (double)v.y * v.y) * (wxy * iw[iz]));
+                km = w * mag;
+                wt = w;
+                key = b;
             }
-            const int prev = __shfl_up(key, 1);
-            const uint64_t heads = __ballot(lane == 0 || prev != key);
-            const uint64_t upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1));
-            const int first = 63 - __clzll(upto);  // first lane of this lane's run
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const double yp = __shfl_up(p, o), yk = __shfl_up(km, o), yw = __shfl_up(wt, o);
-                if (lane - o >= first) {
-                    p += yp;
-                    km += yk;
-                    wt += yw;
+            if (!have) {
+                have = 1;
+                hk = tk = key;
+                tp = p;
+                tm = km;
+                tw = wt;
+            } else if (key == tk) {
+                tp += p;
+                tm += km;
+                tw += wt;
+            } else {
+                if (single) {  // the first run ends here: it may continue an earlier lane's
+                    hp = tp;
+                    hm = tm;
+                    hw = tw;
+                    single = 0;
+                } else {  // a run inside this lane
+                    add(tk, tp, tm, tw);
                 }
-            }
-            const int next = __shfl_down(key, 1);
-            if ((lane == 63 || next != key) && key >= 0 && key < n_bins) {
-                wb[key] += p;
-                wb[n_bins + key] += km;
-                wb[2 * n_bins + key] += wt;
+                tk = key;
+                tp = p;
+                tm = km;
+                tw = wt;
             }
         }
+        // F: sum of this lane's last run from its start, over the lanes whose single run it continues
+        const int ptk = __shfl_up(tk, 1), phave = __shfl_up(have, 1);
+        const bool joins = lane > 0 && have && phave && ptk == hk;  // first run continues lane l - 1's last
+        const bool cont = joins && single;
+        const uint64_t heads = __ballot(!cont);
+        const int first = 63 - __clzll(heads & upto);
+        double fp = tp, fm = tm, fw = tw;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const double yp = __shfl_up(fp, o), ym = __shfl_up(fm, o), yw = __shfl_up(fw, o);
+            if (lane - o >= first) {
+                fp += yp;
+                fm += ym;
+                fw += yw;
+            }
+        }
+        const double cp = __shfl_up(fp, 1), cm = __shfl_up(fm, 1), cw = __shfl_up(fw, 1);
+        // a first run that ends inside this lane, with what it continues
+        if (have && !single) {
+            if (joins) add(hk, hp + cp, hm + cm, hw + cw);
+            else add(hk, hp, hm, hw);
+        }
+        // the last run, by the lane where it ends
+        const int nhk = __shfl_down(hk, 1), nhave = __shfl_down(have, 1);
+        const bool goes_on = lane < kWave - 1 && nhave && nhk == tk;
+        if (have && !goes_on) add(tk, fp, fm, fw);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nb3; b += blockDim.x) {

@@ -511,17 +511,23 @@ __global__ __launch_bounds__(256) void k_brick_tile(const int *__restrict__ cbas
 // Grid point (ix, iy, iz): per axis, its own brick at offset i mod 8 and, for
 // i mod 8 == 0, also the brick below at tile index 8; the chunk tiles of those
 // (up to 8) bricks are added in a fixed order in float64.  One thread takes
-// the 8 points of a brick row along z (grid: x covers the z bricks, y is iy,
-// z is ix, so no index is divided): one lookup of a brick's chunks serves 8
-// independent loads, and a wave stores 64 x 32 contiguous bytes.
-__global__ __launch_bounds__(256) void k_brick_combine(const int *__restrict__ cbase, int ng,
+// the 8 points of a brick row along z (a workgroup covers the z bricks of one
+// grid row): one lookup of a brick's chunks serves 8 independent loads, and a
+// wave stores 64 x 32 contiguous bytes.
+__global__ __launch_bounds__(256) void k_brick_combine(const int *__restrict__ cbase, int ng, int gx,
                                                        const float *__restrict__ ctile, int pad,
                                                        float *__restrict__ grid)
 {
     const int nb = ng / kBrick;
-    const int bz = blockIdx.x * blockDim.x + threadIdx.x;
+    // workgroups go to the 8 XCDs in turn: renumbered so that each XCD takes a
+    // contiguous run of rows, whose points share tiles (and so its L2)
+    const unsigned nwg = gridDim.x;
+    const unsigned L = nwg % kXcds == 0 ? (blockIdx.x % kXcds) * (nwg / kXcds) + blockIdx.x / kXcds
+                                        : blockIdx.x;
+    const int row = (int)(L / (unsigned)gx);
+    const int bz = (int)(L - (unsigned)row * gx) * blockDim.x + threadIdx.x;
     if (bz >= nb) return;
-    const int iy = blockIdx.y, ix = blockIdx.z;
+    const int iy = row % ng, ix = row / ng;
     const int bx = ix >> 3, by = iy >> 3;
     const int tx = ix & 7, ty = iy & 7;
     const int bzm = bz == 0 ? nb - 1 : bz - 1;
@@ -887,8 +893,8 @@ sr_status deposit_bricks(sr_pk_plan *P, const float *pos, const float *mass, int
     }
     const int nbz = P->ng / kBrick;
     const int tz = std::min(256, (nbz + 63) / 64 * 64);
-    const dim3 cg((unsigned)((nbz + tz - 1) / tz), (unsigned)P->ng, (unsigned)P->ng);
-    k_brick_combine<<<cg, tz, 0, s>>>(cbase, P->ng, ctile, pad, grid);
+    const int gx = (nbz + tz - 1) / tz;
+    k_brick_combine<<<(unsigned)((int64_t)gx * P->ng * P->ng), tz, 0, s>>>(cbase, P->ng, gx, ctile, pad, grid);
     return hipGetLastError() == hipSuccess ? SR_OK : SR_E_DEVICE;
 }
 

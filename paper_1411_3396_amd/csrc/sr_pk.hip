@@ -313,7 +313,11 @@ __global__ __launch_bounds__(kSortThreads) void k_brick_scatter(
     __shared__ float4 lv[kRadixTile];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int R = 1 << bits;
-    const int tile = blockIdx.x;
+    // tiles renumbered so that each XCD takes a contiguous run of them: a
+    // digit's runs from neighbouring tiles are neighbours in the output, and
+    // their partial cache lines then merge in one L2
+    const int tile = ntiles % kXcds == 0 ? (int)((blockIdx.x % kXcds) * (ntiles / kXcds) + blockIdx.x / kXcds)
+                                         : (int)blockIdx.x;
     gstart[tid] = tid < R ? table_x[(int64_t)tid * ntiles + tile] : 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
@@ -871,14 +875,14 @@ sr_status deposit_bricks(sr_pk_plan *P, const float *pos, const float *mass, int
                                                            I(P->tabx_off), tiles, K(out), Vb(out));
             if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         }
+        if (dev_bounds(K(0), n, nbricks, 0, bstart, s) != hipSuccess) return SR_E_DEVICE;
+        int4 *rec = reinterpret_cast<int4 *>(w + P->owner_off);
         k_brick_mass<<<1, 256, 0, s>>>(msum, mmax, tiles, mstat);
         if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
-        if (dev_bounds(K(0), n, nbricks, 0, bstart, s) != hipSuccess) return SR_E_DEVICE;
         const unsigned bb = (unsigned)((nbricks + 255) / 256);
         k_brick_chunks<<<bb, 256, 0, s>>>(bstart, nbricks, I(P->chunks_off));
         if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         if (dev_scan(I(P->chunks_off), cbase, nbricks, I(P->scan_off), s) != hipSuccess) return SR_E_DEVICE;
-        int4 *rec = reinterpret_cast<int4 *>(w + P->owner_off);
         k_brick_owner<<<bb, 256, 0, s>>>(bstart, cbase, nbricks, rec);
         if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         // workgroups: an upper bound on the chunks, sum over bricks of ceil(np / kChunk)

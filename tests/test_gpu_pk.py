@@ -150,3 +150,26 @@ def test_non_finite_position_reaches_the_spectrum(ng):
     p, _, modes = (t.cpu().numpy() for t in plan.run(to_dev(pos), to_dev(mass), ws))
     assert np.all(np.isnan(p[modes > 0]))
     plan.close()
+
+
+def test_deposit_large_brick_count():
+    # ng = 328: 41^3 = 68,921 bricks (the largest grid here besides the bench's),
+    # a grid side that is not a power of two, and a crowd of 6000 particles in
+    # one brick that spans 3 chunks
+    ng = 328
+    box = float(ng)
+    rng = np.random.default_rng(328)
+    pos = np.concatenate([rng.random((60000, 3)) * box,
+                          np.array([100.0, 200.0, 300.0]) + rng.random((6000, 3)) * 7.9]).astype(np.float32)
+    mass = rng.uniform(0.5, 2.0, len(pos)).astype(np.float32)
+    announce(f"cic deposit ng={ng} n={len(pos)}")
+    plan = sr.PkPlan(ng, box, 8, n_max=len(pos))
+    ws = sr.new_workspace(plan.ws_bytes, DEV)
+    grid, mtot = plan.deposit(to_dev(pos), to_dev(mass), ws)
+    got = grid.cpu().numpy()
+    ref = opk.cic_deposit(pos, mass, ng, box)
+    np.testing.assert_allclose(got.astype(np.float64), ref, rtol=GRID_RTOL, atol=1e-30)
+    assert float(mtot.cpu()[0]) == pytest.approx(float(np.sum(mass.astype(np.float64))), rel=1e-12)
+    again, _ = plan.deposit(to_dev(pos), to_dev(mass), ws)
+    assert np.array_equal(again.cpu().numpy().view(np.uint32), got.view(np.uint32))
+    plan.close()

@@ -196,8 +196,7 @@ constexpr double kMagic52 = 6755399441055744.0;             // 1.5 * 2^52
 // the coordinate in grid units from the brick's lower corner.  u wraps by the
 // cell deposit's rule; lu = u - 8 b is exact (Sterbenz), so floor(lu) and
 // lu - floor(lu) are the cell deposit's cell offset and fraction bit for bit.
-__device__ __forceinline__ void brick_of(const float *__restrict__ pos, const float *__restrict__ mass,
-                                         int64_t i, int ng, float inv_h, int &key, float4 &v)
+__device__ __forceinline__ void brick_of(const float (&x)[3], float m, int ng, float inv_h, int &key, float4 &v)
 {
     const float fng = (float)ng;
     const int nb = ng / kBrick;
@@ -205,7 +204,7 @@ __device__ __forceinline__ void brick_of(const float *__restrict__ pos, const fl
     float lu[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        float u = pos[3 * i + d] * inv_h;
+        float u = x[d] * inv_h;
         // for 0 <= u < ng, u / ng rounds below 1, so the wrap is the identity
         if (!(u >= 0.f && u < fng)) u = u - floorf(u / fng) * fng;
         float fk = floorf(u);
@@ -222,7 +221,7 @@ __device__ __forceinline__ void brick_of(const float *__restrict__ pos, const fl
         lu[d] = u - (float)(b[d] * kBrick);
     }
     key = (b[0] * nb + b[1]) * nb + b[2];
-    v = make_float4(lu[0], lu[1], lu[2], mass[i]);
+    v = make_float4(lu[0], lu[1], lu[2], m);
 }
 
 // Keys and payloads of one tile of kRadixTile particles, the first sort
@@ -241,19 +240,34 @@ __global__ __launch_bounds__(kSortThreads) void k_brick_hist0(const float *__res
     __shared__ int h[256];
     __shared__ double ls[kSortThreads];
     __shared__ float lm[kSortThreads];
+    __shared__ float4 lp4[3 * kRadixTile / 4];  // the tile's positions, staged with 16-byte loads
+    const float *lp = reinterpret_cast<const float *>(lp4);
     const int tid = threadIdx.x;
     const int R = 1 << bits;
     if (tid < R) h[tid] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int nt = (int)min((int64_t)kRadixTile, (int64_t)n - base);
+    {
+        // 3 nt floats from pos + 3 base, as float4 when pos is 16-byte aligned
+        // (then so is pos + 3 base: base is a multiple of 2048)
+        const int nf = 3 * nt;
+        const int n4 = (reinterpret_cast<uintptr_t>(pos) & 15) == 0 ? nf / 4 : 0;
+        const float4 *g4 = reinterpret_cast<const float4 *>(pos + 3 * base);
+        for (int j = tid; j < n4; j += kSortThreads) lp4[j] = g4[j];
+        float *lpw = reinterpret_cast<float *>(lp4);
+        for (int j = 4 * n4 + tid; j < nf; j += kSortThreads) lpw[j] = pos[3 * base + j];
+    }
+    __syncthreads();
     double s = 0.0;
     float mx = 0.f;
     for (int r = 0; r < kSortSteps; ++r) {
-        const int64_t i = base + r * kSortThreads + tid;
-        if (i < n) {
+        const int e = r * kSortThreads + tid;
+        const int64_t i = base + e;
+        if (e < nt) {
             int key;
             float4 v;
-            brick_of(pos, mass, i, ng, inv_h, key, v);
+            const float x[3] = {lp[3 * e], lp[3 * e + 1], lp[3 * e + 2]};
+            brick_of(x, mass[i], ng, inv_h, key, v);
             keys[i] = key;
             vals[i] = v;
             atomicAdd(&h[key & (R - 1)], 1);
@@ -392,10 +406,9 @@ __global__ __launch_bounds__(kSortThreads) void k_brick_scatter(
 }
 
 // Total mass (the tiles' sums in tile order, then a fixed tree) into out[0]
-// and the largest |m| into out[1].
-__global__ __launch_bounds__(256) void k_brick_mass(const double *__restrict__ msum,
-                                                    const float *__restrict__ mmax, int tiles,
-                                                    double *__restrict__ out)
+// and the largest |m| into out[1], by one workgroup of 256 threads.
+__device__ __forceinline__ void mass_totals(const double *__restrict__ msum, const float *__restrict__ mmax,
+                                            int tiles, double *__restrict__ out)
 {
     __shared__ double ls[256];
     __shared__ float lm[256];
@@ -422,14 +435,27 @@ __global__ __launch_bounds__(256) void k_brick_mass(const double *__restrict__ m
     }
 }
 
+__global__ __launch_bounds__(256) void k_brick_mass(const double *__restrict__ msum,
+                                                    const float *__restrict__ mmax, int tiles,
+                                                    double *__restrict__ out)
+{
+    mass_totals(msum, mmax, tiles, out);
+}
+
 // Workgroups of each brick: ceil(particles / kChunk), none for an empty brick.
+// Workgroup 0 also takes the mass totals (k_brick_mass's sums).
 __global__ __launch_bounds__(256) void k_brick_chunks(const int *__restrict__ bstart, int nbricks,
-                                                      int *__restrict__ chunks)
+                                                      int *__restrict__ chunks,
+                                                      const double *__restrict__ msum,
+                                                      const float *__restrict__ mmax, int tiles,
+                                                      double *__restrict__ mstat)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= nbricks) return;
-    const int np = bstart[b + 1] - bstart[b];
-    chunks[b] = (np + kChunk - 1) / kChunk;
+    if (b < nbricks) {
+        const int np = bstart[b + 1] - bstart[b];
+        chunks[b] = (np + kChunk - 1) / kChunk;
+    }
+    if (blockIdx.x == 0) mass_totals(msum, mmax, tiles, mstat);
 }
 
 // Every chunk's record: its brick and its range of sorted particles.
@@ -877,10 +903,8 @@ sr_status deposit_bricks(sr_pk_plan *P, const float *pos, const float *mass, int
         }
         if (dev_bounds(K(0), n, nbricks, 0, bstart, s) != hipSuccess) return SR_E_DEVICE;
         int4 *rec = reinterpret_cast<int4 *>(w + P->owner_off);
-        k_brick_mass<<<1, 256, 0, s>>>(msum, mmax, tiles, mstat);
-        if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         const unsigned bb = (unsigned)((nbricks + 255) / 256);
-        k_brick_chunks<<<bb, 256, 0, s>>>(bstart, nbricks, I(P->chunks_off));
+        k_brick_chunks<<<bb, 256, 0, s>>>(bstart, nbricks, I(P->chunks_off), msum, mmax, tiles, mstat);
         if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         if (dev_scan(I(P->chunks_off), cbase, nbricks, I(P->scan_off), s) != hipSuccess) return SR_E_DEVICE;
         k_brick_owner<<<bb, 256, 0, s>>>(bstart, cbase, nbricks, rec);

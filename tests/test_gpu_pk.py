@@ -173,3 +173,21 @@ def test_deposit_large_brick_count():
     again, _ = plan.deposit(to_dev(pos), to_dev(mass), ws)
     assert np.array_equal(again.cpu().numpy().view(np.uint32), got.view(np.uint32))
     plan.close()
+
+
+def test_deposit_unaligned_positions():
+    # positions that start 4 bytes past a 16-byte boundary take the scalar
+    # staging path of the first sort pass: the same grid bit for bit
+    w = synth.clustered_box(100000, 64.0, 30, 6)
+    pos, mass, box = w.pos, w.mass, 64.0
+    announce("cic deposit unaligned positions")
+    plan = sr.PkPlan(64, box, 8, n_max=len(pos))
+    ws = sr.new_workspace(plan.ws_bytes, DEV)
+    g0 = plan.deposit(to_dev(pos), to_dev(mass), ws)[0].cpu().numpy().copy()
+    flat = torch.empty(3 * len(pos) + 1, dtype=torch.float32, device=DEV)
+    flat[1:] = to_dev(pos).reshape(-1)
+    shifted = flat[1:].view(len(pos), 3)
+    assert shifted.data_ptr() % 16 != 0
+    g1 = plan.deposit(shifted, to_dev(mass), ws)[0].cpu().numpy()
+    assert np.array_equal(g0.view(np.uint32), g1.view(np.uint32))
+    plan.close()

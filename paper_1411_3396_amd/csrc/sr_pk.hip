@@ -292,21 +292,46 @@ __global__ __launch_bounds__(kSortThreads) void k_brick_hist0(const float *__res
     }
 }
 
-// Later sort passes, histogram side: digit counts of one tile of keys.
+// Later sort passes, histogram side: digit counts of one tile of keys.  Each
+// thread takes kSortSteps consecutive keys and adds each run of equal digits
+// with one LDS atomic (sorted, clustered keys come in long runs).
 __global__ __launch_bounds__(kSortThreads) void k_brick_hist(const int *__restrict__ keys, int n, int shift,
                                                              int bits, int *__restrict__ table, int ntiles)
 {
     __shared__ int h[256];
+    const int tid = threadIdx.x;
     const int R = 1 << bits;
-    if ((int)threadIdx.x < R) h[threadIdx.x] = 0;
+    if (tid < R) h[tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-    for (int r = 0; r < kSortSteps; ++r) {
-        const int64_t i = base + r * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (R - 1)], 1);
+    const int64_t e0 = (int64_t)blockIdx.x * kRadixTile + (int64_t)tid * kSortSteps;
+    static_assert(kSortSteps == 8, "two int4 loads per thread");
+    int d[kSortSteps];
+    if (e0 + kSortSteps <= n) {
+        // keys is 16-byte aligned and e0 a multiple of 8
+        const int4 *k4 = reinterpret_cast<const int4 *>(keys + e0);
+        const int4 a = k4[0], b = k4[1];
+        const int k[kSortSteps] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int j = 0; j < kSortSteps; ++j) d[j] = (k[j] >> shift) & (R - 1);
+    } else {
+        // the tail: digits past n are -1 and come last
+#pragma unroll
+        for (int j = 0; j < kSortSteps; ++j) d[j] = e0 + j < n ? (keys[e0 + j] >> shift) & (R - 1) : -1;
     }
+    int cur = d[0], run = 1;
+#pragma unroll
+    for (int j = 1; j < kSortSteps; ++j) {
+        if (d[j] == cur) {
+            ++run;
+        } else {
+            if (cur >= 0) atomicAdd(&h[cur], run);
+            cur = d[j];
+            run = 1;
+        }
+    }
+    if (cur >= 0) atomicAdd(&h[cur], run);
     __syncthreads();
-    if ((int)threadIdx.x < R) table[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+    if (tid < R) table[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
 }
 
 // Stable scatter of one tile: each wave ranks 64 particles at a time within
@@ -405,6 +430,35 @@ __global__ __launch_bounds__(kSortThreads) void k_brick_scatter(
     }
 }
 
+// Brick starts from the sorted brick keys: slot b starts every brick in
+// (key[b-1], key[b]], and slot n every brick after the last key, so each
+// entry of start[0 .. nbricks] is written once.  Four keys per thread.
+__global__ __launch_bounds__(256) void k_brick_bounds(const int *__restrict__ key, int n, int nbricks,
+                                                      int *__restrict__ start)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b0 = 4 * q;  // slots b0 .. b0 + 3
+    if (b0 > n) return;
+    int k[5];  // k[0] = key[b0 - 1] (-1 before the first), k[1 + j] = key[b0 + j] (nbricks from n on)
+    k[0] = b0 == 0 ? -1 : key[b0 - 1];
+    if (b0 + 4 <= n) {
+        // key is 16-byte aligned
+        const int4 v = reinterpret_cast<const int4 *>(key)[q];
+        k[1] = v.x;
+        k[2] = v.y;
+        k[3] = v.z;
+        k[4] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[1 + j] = b0 + j < n ? key[b0 + j] : nbricks;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (b0 + j > n) break;
+        for (int c = k[j] + 1; c <= k[j + 1]; ++c) start[c] = (int)(b0 + j);
+    }
+}
+
 // Total mass (the tiles' sums in tile order, then a fixed tree) into out[0]
 // and the largest |m| into out[1], by one workgroup of 256 threads.
 __device__ __forceinline__ void mass_totals(const double *__restrict__ msum, const float *__restrict__ mmax,
@@ -415,9 +469,23 @@ __device__ __forceinline__ void mass_totals(const double *__restrict__ msum, con
     const int tid = threadIdx.x;
     double s = 0.0;
     float mx = 0.f;
-    for (int t = tid; t < tiles; t += 256) {
-        s += msum[t];
-        mx = fmaxf(mx, mmax[t]);
+    // eight loads in flight per thread, then added in the same order as a
+    // plain strided loop (a missing partial adds 0, which leaves s as it is)
+    constexpr int kU = 8;
+    for (int t0 = tid; t0 < tiles; t0 += kU * 256) {
+        double v[kU];
+        float m[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int t = t0 + u * 256;
+            v[u] = t < tiles ? msum[t] : 0.0;
+            m[u] = t < tiles ? mmax[t] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            s += v[u];
+            mx = fmaxf(mx, m[u]);
+        }
     }
     ls[tid] = s;
     lm[tid] = mx;
@@ -814,7 +882,7 @@ struct sr_pk_plan {
     int ng = 0, n_bins = 0;
     double box = 0.0, dn = 1.0;
     int64_t n_max = 0;
-    int passes = 1, digit_bits = 1;
+    int passes = 1, digit_bits = 1, key_bits = 1;
     int64_t tiles = 1;
     bool brick = false;      // brick deposit (ng a multiple of 8), else the cell deposit
     int64_t nbricks = 0, max_chunks = 0;
@@ -875,7 +943,6 @@ sr_status deposit_bricks(sr_pk_plan *P, const float *pos, const float *mass, int
     float *ctile = reinterpret_cast<float *>(w + P->ctile_off);
     if (n > 0) {
         const int tiles = (int)((n + kRadixTile - 1) / kRadixTile);
-        const int R = 1 << P->digit_bits;
         double *msum = reinterpret_cast<double *>(w + P->msum_off);
         float *mmax = reinterpret_cast<float *>(w + P->mmax_off);
         // keys and payloads (with the first pass's digit counts) into buffer
@@ -886,22 +953,26 @@ sr_status deposit_bricks(sr_pk_plan *P, const float *pos, const float *mass, int
         auto Vb = [&](int q) { return V(q ? P->spf_off : P->pf_off); };
         const int first = P->passes & 1;
         for (int p = 0; p < P->passes; ++p) {
+            // the last pass takes only the key bits left
             const int shift = p * P->digit_bits;
+            const int bits = std::min(P->digit_bits, P->key_bits - shift);
+            const int R = 1 << bits;
             const int in = (first + p) & 1, out = in ^ 1;
             if (p == 0)
-                k_brick_hist0<<<tiles, kSortThreads, 0, s>>>(pos, mass, (int)n, P->ng, inv_h, P->digit_bits,
+                k_brick_hist0<<<tiles, kSortThreads, 0, s>>>(pos, mass, (int)n, P->ng, inv_h, bits,
                                                              I(P->tab_off), tiles, K(in), Vb(in), msum, mmax);
             else
-                k_brick_hist<<<tiles, kSortThreads, 0, s>>>(K(in), (int)n, shift, P->digit_bits, I(P->tab_off),
+                k_brick_hist<<<tiles, kSortThreads, 0, s>>>(K(in), (int)n, shift, bits, I(P->tab_off),
                                                             tiles);
             if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
             if (dev_scan(I(P->tab_off), I(P->tabx_off), (int64_t)R * tiles, I(P->scan_off), s) != hipSuccess)
                 return SR_E_DEVICE;
-            k_brick_scatter<<<tiles, kSortThreads, 0, s>>>(K(in), Vb(in), (int)n, shift, P->digit_bits,
+            k_brick_scatter<<<tiles, kSortThreads, 0, s>>>(K(in), Vb(in), (int)n, shift, bits,
                                                            I(P->tabx_off), tiles, K(out), Vb(out));
             if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         }
-        if (dev_bounds(K(0), n, nbricks, 0, bstart, s) != hipSuccess) return SR_E_DEVICE;
+        k_brick_bounds<<<(unsigned)((n / 4 + 1 + 255) / 256), 256, 0, s>>>(K(0), (int)n, nbricks, bstart);
+        if (hipGetLastError() != hipSuccess) return SR_E_DEVICE;
         int4 *rec = reinterpret_cast<int4 *>(w + P->owner_off);
         const unsigned bb = (unsigned)((nbricks + 255) / 256);
         k_brick_chunks<<<bb, 256, 0, s>>>(bstart, nbricks, I(P->chunks_off), msum, mmax, tiles, mstat);
@@ -1009,6 +1080,7 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
         P->nbricks = nb * nb * nb;  // brick keys fit 21 bits
         int bits = 1;
         while ((int64_t(1) << bits) < P->nbricks) ++bits;
+        P->key_bits = bits;
         P->passes = (bits + 7) / 8;
         P->digit_bits = (bits + P->passes - 1) / P->passes;
         const int64_t m = std::max<int64_t>(1, n_max);
@@ -1047,6 +1119,7 @@ sr_status sr_pk_plan_create(int32_t ng, double box, int32_t n_bins, double dn, i
         const int64_t cells = (int64_t)ng * ng * ng;  // cell keys fit 30 bits
         int bits = 1;
         while ((int64_t(1) << bits) < cells) ++bits;
+        P->key_bits = bits;
         P->passes = (bits + 7) / 8;
         P->digit_bits = (bits + P->passes - 1) / P->passes;
         const int64_t m = std::max<int64_t>(1, n_max);

@@ -1478,26 +1478,44 @@ __global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *_
             const SegParams &S = acc.get(acc.seg_of_cell(c));
             int ix, iy, iz;
             decode_cell(S, c, ix, iy, iz);
-            int64_t sv = 0;
-            auto runs_of = [&](int a) { return (dense_count(nact[a]) / kWave + K - 1) / K; };
-            for (int e = 0; e < kSymDirs; ++e) {
-                int dx, dy, dz, b;
-                float sx, sy, sz;
-                half_dir(e, dx, dy, dz);
-                if (D > 0 && cell_at(S, ix, iy, iz, dx, dy, dz, b, sx, sy, sz)) sv += dense_count(nact[b]);
-                int64_t sc = 0;
-                if (D > 0 && cell_at(S, ix, iy, iz, -dx, -dy, -dz, b, sx, sy, sz)) sc = (int64_t)runs_of(b) * D;
-                row[1 + e] = (int)min(sc, (int64_t)INT32_MAX);
-                slots += (unsigned long long)sc;
-            }
+            // dense and non-dense counts of the 27 cells of the stencil (0
+            // outside an open domain), all loads in flight together; every
+            // group below reads them from here
+            int nd[kSymNdDirs], nn[kSymNdDirs];
+#pragma unroll
             for (int f = 0; f < kSymNdDirs; ++f) {
                 int dx, dy, dz, b;
                 float sx, sy, sz;
                 full_dir(f, dx, dy, dz);
-                if (D > 0 && cell_at(S, ix, iy, iz, dx, dy, dz, b, sx, sy, sz))
-                    sv += start[b + 1] - start[b] - dense_count(nact[b]);
+                nd[f] = 0;
+                nn[f] = 0;
+                if ((D > 0 || ND > 0) && cell_at(S, ix, iy, iz, dx, dy, dz, b, sx, sy, sz)) {
+                    nd[f] = dense_count(nact[b]);
+                    nn[f] = start[b + 1] - start[b] - nd[f];
+                }
+            }
+            // direction (dx, dy, dz) is full-stencil index f = 9 (dx + 1) + 3 (dy + 1) + dz + 1,
+            // and its opposite 26 - f
+            auto runs_of = [&](int f) { return (nd[f] / kWave + K - 1) / K; };
+            int64_t sv = 0;
+#pragma unroll
+            for (int e = 0; e < kSymDirs; ++e) {
+                int dx, dy, dz;
+                half_dir(e, dx, dy, dz);
+                const int f = 9 * (dx + 1) + 3 * (dy + 1) + dz + 1;
                 int64_t sc = 0;
-                if (ND > 0 && cell_at(S, ix, iy, iz, -dx, -dy, -dz, b, sx, sy, sz)) sc = (int64_t)runs_of(b) * ND;
+                if (D > 0) {
+                    sv += nd[f];
+                    sc = (int64_t)runs_of(kSymNdDirs - 1 - f) * D;
+                }
+                row[1 + e] = (int)min(sc, (int64_t)INT32_MAX);
+                slots += (unsigned long long)sc;
+            }
+#pragma unroll
+            for (int f = 0; f < kSymNdDirs; ++f) {
+                if (D > 0) sv += nn[f];
+                int64_t sc = 0;
+                if (ND > 0) sc = (int64_t)runs_of(kSymNdDirs - 1 - f) * ND;
                 row[1 + kSymDirs + f] = (int)min(sc, (int64_t)INT32_MAX);
                 slots += (unsigned long long)sc;
             }

@@ -857,6 +857,17 @@ __device__ __forceinline__ int4 load_item(const int4 *__restrict__ items, int64_
                      __builtin_amdgcn_readfirstlane(it.z), __builtin_amdgcn_readfirstlane(it.w));
 }
 
+// Returns v held in a vector register that the compiler cannot re-derive from
+// its scalar source.  The first Horner step reads the two top coefficients,
+// and a three-operand instruction may read only one scalar register, so with
+// both coefficients in scalar registers the compiler re-copies one of them in
+// every pair step; one copy per work item takes that move out of the loops.
+__device__ __forceinline__ float keep_in_vgpr(float v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 __device__ __forceinline__ float horner5(const float *q, float t)
 {
     float p = fmaf(q[5], t, q[4]);
@@ -1090,6 +1101,7 @@ __device__ __forceinline__ void force_items(const Acc &acc, const int4 *__restri
             float cq[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
+            cq[5] = keep_in_vgpr(cq[5]);
             Stencil st;
             stencil_setup(S, it.x, start, nact, false, lane, st, item_nd(it.w));
             auto fetch_p = [&](int v, float4 &c0, float4 &) { c0 = fetch_pos(st, v, src); };
@@ -1209,6 +1221,7 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
             float cq[6], cd[5];
 #pragma unroll
             for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
+            cq[5] = keep_in_vgpr(cq[5]);
 #pragma unroll
             for (int k = 0; k < 5; ++k) cd[k] = S.pc.dq[k];
             Stencil st;
@@ -1868,6 +1881,7 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
             float cq[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) cq[i] = S.pc.q[i];
+            cq[5] = keep_in_vgpr(cq[5]);
             SymStencil st;
             sym_stencil_setup(S, c, start, nact, sym_base, sym_pref, lane, st);
             const int D = __shfl(st.cnt, 0);  // segment 0 is the cell itself
@@ -2002,8 +2016,10 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
             float cq[6], cd[5];
 #pragma unroll
             for (int i = 0; i < 6; ++i) cq[i] = S.pc.q[i];
+            cq[5] = keep_in_vgpr(cq[5]);
 #pragma unroll
             for (int i = 0; i < 5; ++i) cd[i] = S.pc.dq[i];
+            cd[4] = keep_in_vgpr(cd[4]);
             SymStencil st;
             sym_stencil_setup(S, c, start, nact, sym_base, sym_pref, lane, st);
             const int D = __shfl(st.cnt, 0);

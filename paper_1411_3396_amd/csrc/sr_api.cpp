@@ -80,7 +80,8 @@ PairConsts pair_consts(const sr_problem *p)
         }
     }
     for (int m = 0; m < 6; ++m) pc.q[m] = (float)Q[m];
-    for (int m = 0; m < 5; ++m) pc.dq[m] = (float)(2.0 * (m + 1) * Q[m + 1]);
+    for (int m = 0; m < 6; ++m) pc.qa[m] = (float)(Q[m] / 3.0);
+    for (int m = 0; m < 5; ++m) pc.dqa[m] = (float)(2.0 * (m + 1) * Q[m + 1] / 3.0);
     return pc;
 }
 

@@ -26,13 +26,18 @@ constexpr int kMaxLeafDepth = 4;     // deepest in-cell octree order
 
 // Constants of the pair kernel, evaluated in t = s + eps^2:
 //   f_SR = t^-3/2 - Q(t),  Q(t) = sum_k q[k] t^k = sum_k poly[k] (t - eps^2)^k,
-//   2 f_SR' = -3 t^-5/2 - D(t),  D(t) = sum_k dq[k] t^k = 2 Q'(t).
+//   2 f_SR' = -3 t^-5/2 - D(t),  D(t) = 2 Q'(t).
+// The adjoint evaluates both at the scale -1/3, which saves it one product
+// per pair (the factor -3 is applied once per output row):
+//   f_SR / -3 = A(t) - t^-3/2 / 3,   A(t) = sum_k qa[k] t^k = Q(t) / 3,
+//   2 f_SR' / -3 = t^-5/2 + B(t),    B(t) = sum_k dqa[k] t^k = D(t) / 3.
 struct PairConsts {
     float eps2;   // eps * eps
     float tc2;    // r_s^2 + eps^2: pairs with t < tc2 interact
     float cull2;  // r_s^2 (1 + 1e-5): sources farther than this from the targets' box are skipped
     float q[6];
-    float dq[5];
+    float qa[6];
+    float dqa[5];
     int32_t softened;  // eps > 0
 };
 
@@ -53,7 +58,7 @@ struct SegParams {
     int32_t tile_off;  // first momentum partial
     PairConsts pc;
     int32_t leaf_depth;  // octree depth of the in-cell order (1 = octants)
-    int32_t pad[3];
+    int32_t pad[1];
 };
 static_assert(sizeof(SegParams) % 16 == 0, "SegParams must stay 16-byte sized");
 

@@ -862,6 +862,9 @@ __device__ __forceinline__ int4 load_item(const int4 *__restrict__ items, int64_
 // and a three-operand instruction may read only one scalar register, so with
 // both coefficients in scalar registers the compiler re-copies one of them in
 // every pair step; one copy per work item takes that move out of the loops.
+// The adjoint's pair terms are evaluated at this scale.
+constexpr float kMinusThird = -1.0f / 3.0f;
+
 __device__ __forceinline__ float keep_in_vgpr(float v)
 {
     asm volatile("" : "+v"(v));
@@ -906,8 +909,10 @@ __device__ __forceinline__ void force_pair(const float4 s, float px, float py, f
     }
 }
 
-// One adjoint pair term: r += f u + 2 f' (u.d) d, u = m_k g_j - m_j g_k.
-// With kUM, u / m = g_j - g_k is summed and the mass applied once at the end.
+// One adjoint pair term: r += f u + 2 f' (u.d) d, u = m_k g_j - m_j g_k,
+// at the scale -1/3 (cq, cd: the adjoint's coefficients qa, dqa): the sums
+// are multiplied by -3 once per output row.  With kUM, u / m = g_j - g_k is
+// summed and the mass applied at the same time.
 // Both products of u are rounded before the difference (no fused form), so u
 // is exactly antisymmetric and the target's own entry (j = k, d = 0) adds
 // exactly zero.  A distinct particle at the same position (d = 0) adds
@@ -926,8 +931,8 @@ __device__ __forceinline__ void vjp_pair(const float4 s, const float4 gj, float 
     const float q2 = qi * qi;
     const float q3 = q2 * qi;
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-    const float f = q3 - horner5(cq, tt);
-    const float fp2 = fmaf(-3.0f, q3 * q2, -horner4(cd, tt));
+    const float f = fmaf(q3, kMinusThird, horner5(cq, tt));
+    const float fp2 = fmaf(q3, q2, horner4(cd, tt));
     const float ux = kUM ? gj.x - gkx : mk * gj.x - s.w * gkx;
     const float uy = kUM ? gj.y - gky : mk * gj.y - s.w * gky;
     const float uz = kUM ? gj.z - gkz : mk * gj.z - s.w * gkz;
@@ -1204,7 +1209,8 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
                                           int64_t pull_limit)
 {
     const int lane = threadIdx.x;
-    const float m0 = kUM ? src.m[0] : 1.0f;
+    // the common mass (or 1), times -3: the pair sums are at the scale -1/3
+    const float m0 = -3.0f * (kUM ? src.m[0] : 1.0f);
     const int64_t n_items = hdr[kHdrNItems];
     const int q0 = blockIdx.x & (kQueues - 1);
     PullGuard guard(min(n_items, pull_limit));
@@ -1220,10 +1226,10 @@ __device__ __forceinline__ void vjp_items(const Acc &acc, const int4 *__restrict
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
             float cq[6], cd[5];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) cq[k] = S.pc.q[k];
+            for (int k = 0; k < 6; ++k) cq[k] = S.pc.qa[k];
             cq[5] = keep_in_vgpr(cq[5]);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) cd[k] = S.pc.dq[k];
+            for (int k = 0; k < 5; ++k) cd[k] = S.pc.dqa[k];
             Stencil st;
             stencil_setup(S, it.x, start, nact, item_psrc(it.w), lane, st, item_nd(it.w));
             auto fetch_pg = [&](int v, float4 &c0, float4 &c1) {
@@ -1755,7 +1761,8 @@ __device__ __forceinline__ void sym_force_step(const float4 s, float px, float p
 }
 
 // One adjoint step: the target gets T = f u + 2 f' (u.d) d, the source -T
-// (u = m_k g_j - m_j g_k, d = x_j - x_k; with kUM, u / m).
+// (u = m_k g_j - m_j g_k, d = x_j - x_k; with kUM, u / m), at the scale -1/3
+// of the one-sided adjoint.
 template <bool kSoft, bool kUM>
 __device__ __forceinline__ void sym_vjp_step(const float4 s, const float4 gj, float px, float py,
                                              float pz, float mk, float gkx, float gky, float gkz,
@@ -1770,8 +1777,8 @@ __device__ __forceinline__ void sym_vjp_step(const float4 s, const float4 gj, fl
     const float q2 = qi * qi;
     const float q3 = q2 * qi;
     const bool in = kSoft ? (tt < tc2) : (tt < tc2 && tt > 0.f);
-    const float f = q3 - horner5(cq, tt);
-    const float fp2 = fmaf(-3.0f, q3 * q2, -horner4(cd, tt));
+    const float f = fmaf(q3, kMinusThird, horner5(cq, tt));
+    const float fp2 = fmaf(q3, q2, horner4(cd, tt));
     const float ux = kUM ? gj.x - gkx : mk * gj.x - s.w * gkx;
     const float uy = kUM ? gj.y - gky : mk * gj.y - s.w * gky;
     const float uz = kUM ? gj.z - gkz : mk * gj.z - s.w * gkz;
@@ -2015,10 +2022,10 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
             float cq[6], cd[5];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) cq[i] = S.pc.q[i];
+            for (int i = 0; i < 6; ++i) cq[i] = S.pc.qa[i];
             cq[5] = keep_in_vgpr(cq[5]);
 #pragma unroll
-            for (int i = 0; i < 5; ++i) cd[i] = S.pc.dq[i];
+            for (int i = 0; i < 5; ++i) cd[i] = S.pc.dqa[i];
             cd[4] = keep_in_vgpr(cd[4]);
             SymStencil st;
             sym_stencil_setup(S, c, start, nact, sym_base, sym_pref, lane, st);
@@ -2139,8 +2146,8 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, co
 // the 14 directions and runs; it has no one-sided item, so the sum is its
 // row (out[row] = m0 * sum).  A non-dense particle: its source slots over the
 // 27 directions and runs, added to the row its one-sided item wrote
-// (out[row] += m0 * sum).  m0 is the common mass when every mass is equal,
-// else 1.  rows: out_row (forward, n_out = rows of acc; passive particles
+// (out[row] += m0 * sum).  m0 is scale (1 forward, -3 adjoint) times the
+// common mass when every mass is equal, else times 1.  rows: out_row (forward, n_out = rows of acc; passive particles
 // have none) or perm (adjoint, n_out = N).
 __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const int *__restrict__ key,
                                                     const int *__restrict__ start,
@@ -2151,7 +2158,7 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
                                                     const int *__restrict__ rows,
                                                     const float *__restrict__ mass /*binned*/,
                                                     const uint32_t *hdr,
-                                                    float *__restrict__ out, int n_out)
+                                                    float *__restrict__ out, int n_out, float scale)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= N || hdr[kHdrSymOk] == 0) return;
@@ -2198,7 +2205,7 @@ __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const i
     const float sx = (x[0] + x[1]) + (x[2] + x[3]);
     const float sy = (y[0] + y[1]) + (y[2] + y[3]);
     const float sz = (z[0] + z[1]) + (z[2] + z[3]);
-    const float m0 = hdr[kHdrMassInfo] == 0 ? mass[0] : 1.0f;
+    const float m0 = scale * (hdr[kHdrMassInfo] == 0 ? mass[0] : 1.0f);
     const int64_t q = 3 * (int64_t)r;
     if (dense) {
         out[q] = m0 * sx;
@@ -2524,13 +2531,13 @@ void launch_vjp_sym(const DevArgs &a, Acc acc)
 }
 
 // Adds the symmetric partial sums to the rows the one-sided kernel wrote.
-hipError_t sym_gather(const DevArgs &a, const int *rows, float *out, int n_out)
+hipError_t sym_gather(const DevArgs &a, const int *rows, float *out, int n_out, float scale)
 {
     const Layout &L = *a.L;
     k_sym_gather<<<blocks_for(L.N, 256), 256, 0, a.st>>>(
         (int)L.N, L.key_bits, at<int>(a, L.sorted_keys()), at<int>(a, L.start), at<int>(a, L.nact),
         at<int>(a, L.sym_pref), at<int>(a, L.sym_base), at<float>(a, L.sym_pool), rows, at<float>(a, L.bm),
-        at<uint32_t>(a, L.hdr), out, n_out);
+        at<uint32_t>(a, L.hdr), out, n_out, scale);
     return hipGetLastError();
 }
 
@@ -2560,7 +2567,7 @@ hipError_t dev_force(const DevArgs &a, float *acc_out)
             if (soft) launch_force_sym<A, true>(a, acc);
             else launch_force_sym<A, false>(a, acc);
             if ((le = hipGetLastError()) == hipSuccess)
-                le = sym_gather(a, at<int>(a, a.L->out_row), acc_out, a.n_rows);
+                le = sym_gather(a, at<int>(a, a.L->out_row), acc_out, a.n_rows, 1.0f);
         }
         timing_end(tok, a.st);
         return le;
@@ -2595,7 +2602,7 @@ hipError_t dev_vjp(const DevArgs &a, const float *g, float *grad)
             if (soft) launch_vjp_sym<A, true>(a, acc);
             else launch_vjp_sym<A, false>(a, acc);
             if ((le = hipGetLastError()) == hipSuccess)
-                le = sym_gather(a, at<int>(a, a.L->perm()), grad, (int)a.L->N);
+                le = sym_gather(a, at<int>(a, a.L->perm()), grad, (int)a.L->N, -3.0f);
         }
         timing_end(tok, a.st);
         return le;

@@ -1732,6 +1732,22 @@ __device__ __forceinline__ float rotate_down(float v)
                                                               false));
 }
 
+// Lane l takes lane l + 1's value within its row of 16 lanes (mod 16): the
+// rotation of a step of the row tiles that finish a stream.
+__device__ __forceinline__ float rotate_row(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x12f, 0xf, 0xf,
+                                                              false));
+}
+
+// Sum of v over the four rows of 16 lanes, the same on each row, in a fixed
+// order: (row 0 + row 1) + (row 2 + row 3).
+__device__ __forceinline__ float sum_rows(float v)
+{
+    v += __shfl_xor(v, 16);
+    return v + __shfl_xor(v, 32);
+}
+
 // One forward step: target (px, py, pz, mi) gets m_j d f, the source's running
 // sum gets -m_i d f (t = s + eps^2 < tc2).  With kUM both masses are applied
 // once, by the gather.
@@ -1809,11 +1825,14 @@ struct SymRed {
 // e + 64, so that step s of lane l reads entry l + s without a wrap) with
 // their window index in tix.  Whenever 64 are in, `tile(my)` runs (my: the
 // window index of this lane's entry, -1 for padding); survivors of the same
-// batch beyond the 64th start the next tile.  Every lane must call this.
-template <int kParts, class Fetch, class Tile>
+// batch beyond the 64th start the next tile.  The last n <= 48 survivors of
+// the stream run as `rows(c)`, c = ceil(n / 16) chunks of 16 entries (padded)
+// that each meet all 64 targets in 16 steps, instead of a 64-step tile that
+// is mostly padding.  Every lane must call this.
+template <int kParts, class Fetch, class Tile, class Rows>
 __device__ __forceinline__ void sym_stream(int vs, int w1, int w0, const Box &box, float cull2, int lane,
                                            float4 *tile0, float4 *tile1, int *tix, Fetch &&fetch,
-                                           Tile &&tile)
+                                           Tile &&tile, Rows &&rows)
 {
     if (vs >= w1) return;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -1854,8 +1873,29 @@ __device__ __forceinline__ void sym_stream(int vs, int w1, int w0, const Box &bo
     if (fill > 0) {
         if (lane >= fill)
             put(lane, make_float4(kFar, kFar, kFar, 0.f), make_float4(0.f, 0.f, 0.f, 0.f), -1);
-        run();
+        const int chunks = (fill + 15) >> 4;
+        if (chunks < 4) {
+            __syncthreads();
+            rows(chunks);
+            __syncthreads();
+        } else {
+            run();
+        }
     }
+}
+
+// Entry chunk k (16 entries) of a tile in the row layout: entry j at rt[j]
+// and rt[j + 16], so that step s of lane l reads rt[(l mod 16) + s].  The
+// second half of the tile (its wrap copy, unused by row tiles) holds it.
+__device__ __forceinline__ void row_chunk(float4 *tile, int k, int lane)
+{
+    __syncthreads();
+    if (lane < 16) {
+        const float4 e = tile[16 * k + lane];
+        tile[kWave + lane] = e;
+        tile[kWave + 16 + lane] = e;
+    }
+    __syncthreads();
 }
 
 // Forward symmetric items.
@@ -1945,6 +1985,31 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                         red.x[my] += bx;
                         red.y[my] += by;
                         red.z[my] += bz;
+                    }
+                }, [&](int chunks) {
+                    const float4 *t = tile + kWave + (lane & 15);
+                    for (int k = 0; k < chunks; ++k) {
+                        row_chunk(tile, k, lane);
+                        float bx = 0.f, by = 0.f, bz = 0.f;
+                        for (int s = 0; s < 16; s += 8) {
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                sym_force_step<kSoft, kUM>(t[s + u], px, py, pz, mi, eps2, tc2, cq, ax, ay,
+                                                           az, bx, by, bz);
+                                bx = rotate_row(bx);
+                                by = rotate_row(by);
+                                bz = rotate_row(bz);
+                            }
+                        }
+                        bx = sum_rows(bx);
+                        by = sum_rows(by);
+                        bz = sum_rows(bz);
+                        const int my = tix[16 * k + (lane & 15)];
+                        if (lane < 16 && my >= 0) {
+                            red.x[my] += bx;
+                            red.y[my] += by;
+                            red.z[my] += bz;
+                        }
                     }
                 });
                 const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
@@ -2094,6 +2159,35 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
                                       red.x[my] += bx;
                                       red.y[my] += by;
                                       red.z[my] += bz;
+                                  }
+                              },
+                              [&](int chunks) {
+                                  const float4 *tp = tile_p + kWave + (lane & 15);
+                                  const float4 *tg = tile_g + kWave + (lane & 15);
+                                  for (int k = 0; k < chunks; ++k) {
+                                      row_chunk(tile_p, k, lane);
+                                      row_chunk(tile_g, k, lane);
+                                      float bx = 0.f, by = 0.f, bz = 0.f;
+                                      for (int s = 0; s < 16; s += 4) {
+#pragma unroll
+                                          for (int u = 0; u < 4; ++u) {
+                                              sym_vjp_step<kSoft, kUM>(tp[s + u], tg[s + u], px, py, pz, mk,
+                                                                       gkx, gky, gkz, eps2, tc2, cq, cd, rx,
+                                                                       ry, rz, bx, by, bz);
+                                              bx = rotate_row(bx);
+                                              by = rotate_row(by);
+                                              bz = rotate_row(bz);
+                                          }
+                                      }
+                                      bx = sum_rows(bx);
+                                      by = sum_rows(by);
+                                      bz = sum_rows(bz);
+                                      const int my = tix[16 * k + (lane & 15)];
+                                      if (lane < 16 && my >= 0) {
+                                          red.x[my] += bx;
+                                          red.y[my] += by;
+                                          red.z[my] += bz;
+                                      }
                                   }
                               });
                 const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);

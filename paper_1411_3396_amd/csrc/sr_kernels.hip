@@ -1414,9 +1414,12 @@ __global__ __launch_bounds__(64) void k_count(Acc acc, const int4 *__restrict__ 
 //                 dense particle j of B.
 // Every slot has exactly one writer.  k_sym_gather then adds the slots of each
 // dense particle in a fixed order to what its one-sided item (non-dense
-// sources only) wrote.  Each pair term equals, bit for bit, the one the
-// one-sided kernels evaluate from either end (subtraction and the products of
-// u are antisymmetric in float32); only the order of the sums differs.
+// sources only) wrote.  A forward pair term equals, bit for bit, the one the
+// one-sided kernel evaluates from either end, and only the order of the sums
+// differs.  An adjoint term T is formed once and added to one end and
+// subtracted from the other (subtraction and the products of u are
+// antisymmetric in float32); the one-sided kernel instead fuses its two
+// products into the target's sum, so the two differ by rounding as well.
 //
 // A tile pairs 64 targets (one per lane) with 64 staged sources: at step s
 // lane l takes source (l + s) mod 64, and the lane's running sum for that

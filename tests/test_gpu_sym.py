@@ -161,3 +161,29 @@ def test_balance_rule_keeps_long_items_off():
         assert_force_close(a, ref, what="balance rule")
     assert oracle.rms_rel(a0, a1) <= 2e-6
     assert oracle.rms_rel(g0, g1) <= 2e-5
+
+
+@pytest.mark.parametrize("rest", [1, 15, 16, 17, 33, 48, 49, 63])
+def test_stream_tails_of_every_row_count(rest):
+    # one cluster of 128 + rest particles inside one cell of a 3-cell periodic
+    # box, every pair within reach: block 0 streams block 1 and the rest, block
+    # 1 the rest, so both streams end with `rest` survivors and finish with
+    # ceil(rest / 16) row chunks (a full 64-step tile past 48), on top of the
+    # triangles of both blocks and the one-sided items of the rest
+    rng = np.random.default_rng(100 + rest)
+    n = 128 + rest
+    w = synth.uniform_box(n, 9.3, 12)
+    w.pos = (np.float32(4.65) + rng.uniform(-0.5, 0.5, (n, 3))).astype(np.float32)
+    w.mass = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    g = synth.cotangent(n, 13)
+    ref = oracle_force(w)
+    gref = oracle.vjp(w.pos, w.mass, w.n_active, w.problem, g)
+    announce(f"stream tails rest={rest} n={n}")
+    a0, g0, f0, v0 = run(w, g, (0, -1))
+    assert f0 == 0 and v0 == 0
+    a, gr, ok_f, ok_v = run(w, g, (16, 256))
+    assert ok_f == 1 and ok_v == 1
+    assert_force_close(a, ref, what=f"tails rest={rest}")
+    assert oracle.rms_rel(gr, gref) <= VJP_TOL
+    assert oracle.rms_rel(a, a0) <= 2e-6
+    assert oracle.rms_rel(gr, g0) <= 2e-5

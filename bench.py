@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -51,20 +52,26 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_1411_3396_amd", "csrc", "sr_kernels.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def kernel_code_hash() -> str:
+    """sha256 prefix of the pair kernels' code: sr_kernels.hip with its comments removed and its
+    blank space collapsed, so that a counter summary stays valid across comment-only edits."""
+    with open(os.path.join(ROOT, "paper_1411_3396_amd", "csrc", "sr_kernels.hip")) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"\s+", " ", src).strip()
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def committed_profile(kind: str, kernel: str, workload: str):
     """A committed rocprofv3 counter summary of one pass (profiles/<kind>_<pass>_<workload>.json),
-    if it was taken on this kernel source; else None."""
+    if it was taken on this kernel code; else None."""
     path = os.path.join(ROOT, "profiles", f"{kind}_{PASS_NAME[kernel]}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_code_sha256_16") != kernel_code_hash():
         return None
     return t
 

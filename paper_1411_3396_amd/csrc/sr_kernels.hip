@@ -857,14 +857,14 @@ __device__ __forceinline__ int4 load_item(const int4 *__restrict__ items, int64_
                      __builtin_amdgcn_readfirstlane(it.z), __builtin_amdgcn_readfirstlane(it.w));
 }
 
+// The adjoint's pair terms are evaluated at this scale.
+constexpr float kMinusThird = -1.0f / 3.0f;
+
 // Returns v held in a vector register that the compiler cannot re-derive from
 // its scalar source.  The first Horner step reads the two top coefficients,
 // and a three-operand instruction may read only one scalar register, so with
 // both coefficients in scalar registers the compiler re-copies one of them in
 // every pair step; one copy per work item takes that move out of the loops.
-// The adjoint's pair terms are evaluated at this scale.
-constexpr float kMinusThird = -1.0f / 3.0f;
-
 __device__ __forceinline__ float keep_in_vgpr(float v)
 {
     asm volatile("" : "+v"(v));
@@ -2244,8 +2244,9 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, co
 // row (out[row] = m0 * sum).  A non-dense particle: its source slots over the
 // 27 directions and runs, added to the row its one-sided item wrote
 // (out[row] += m0 * sum).  m0 is scale (1 forward, -3 adjoint) times the
-// common mass when every mass is equal, else times 1.  rows: out_row (forward, n_out = rows of acc; passive particles
-// have none) or perm (adjoint, n_out = N).
+// common mass when every mass is equal, else times 1.  rows: out_row
+// (forward, n_out = rows of acc; passive particles have none) or perm
+// (adjoint, n_out = N).
 __global__ __launch_bounds__(256) void k_sym_gather(int N, int key_bits, const int *__restrict__ key,
                                                     const int *__restrict__ start,
                                                     const int *__restrict__ nact,

@@ -1887,6 +1887,62 @@ __device__ __forceinline__ void sym_stream(int vs, int w1, int w0, const Box &bo
     }
 }
 
+// sym_stream for a window whose kB batches of 64 candidates an item fetched
+// once into registers (held[i]: sources w0 + 64 i + lane), for the forward's
+// one float4 per source: every block of the item culls the same held
+// candidates instead of fetching the window again.  Batches before vs are
+// skipped, entries of a batch before vs are masked.  Every lane must call it.
+template <int kB, class Tile, class Rows>
+__device__ __forceinline__ void sym_stream_held(const float4 (&held)[kB], int vs, int w1, int w0,
+                                                const Box &box, float cull2, int lane, float4 *tile0,
+                                                int *tix, Tile &&tile, Rows &&rows)
+{
+    if (vs >= w1) return;
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int fill = 0;
+    auto put = [&](int at, const float4 &c0, int ix) {
+        tile0[at] = c0;
+        tile0[at + kWave] = c0;
+        tix[at] = ix;
+    };
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+        const int base = w0 + i * kWave;
+        if (base < w1 && base + kWave > vs) {
+            const float4 c0 = held[i];
+            const int v = base + lane;
+            const bool keep = v >= vs && v < w1 && may_reach(box, c0.x, c0.y, c0.z, cull2);
+            const uint64_t m = __ballot(keep);
+            const int cnt = __popcll(m);
+            const int at = fill + __popcll(m & below);
+            const int ix = v - w0;
+            if (keep && at < kWave) put(at, c0, ix);
+            if (fill + cnt >= kWave) {
+                __syncthreads();
+                const int my = tix[lane];
+                tile(my);
+                __syncthreads();
+                if (keep && at >= kWave) put(at - kWave, c0, ix);
+                fill += cnt - kWave;
+            } else {
+                fill += cnt;
+            }
+        }
+    }
+    if (fill > 0) {
+        if (lane >= fill) put(lane, make_float4(kFar, kFar, kFar, 0.f), -1);
+        const int chunks = (fill + 15) >> 4;
+        __syncthreads();
+        if (chunks < 4) {
+            rows(chunks);
+        } else {
+            const int my = tix[lane];
+            tile(my);
+        }
+        __syncthreads();
+    }
+}
+
 // Entry chunk k (16 entries) of a tile in the row layout: entry j at rt[j]
 // and rt[j + 16], so that step s of lane l reads rt[(l mod 16) + s].  The
 // second half of the tile (its wrap copy, unused by row tiles) holds it.
@@ -1944,6 +2000,17 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                 int slot;
                 a = sym_fetch_pos(st, v, w1, src, slot);
             };
+            // windows of 256: the window's sources once, held in registers for all blocks
+            constexpr int kHeld = kW == 256 ? kW / kWave : 1;
+            float4 held[kHeld];
+#pragma unroll
+            for (int i = 0; i < kHeld; ++i) {
+                held[i] = make_float4(kFar, kFar, kFar, 0.f);
+                if (kW == 256 && w0 + i * kWave < w1) {
+                    int slot;
+                    held[i] = sym_fetch_pos(st, w0 + i * kWave + lane, w1, src, slot);
+                }
+            }
             for (int p = p0; p < p1; ++p) {
                 const int b = c0s + p * kWave + lane;
                 const float px = src.x[b], py = src.y[b], pz = src.z[b];
@@ -1971,7 +2038,7 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                     red.z[r] += bz;
                 }
                 const int vs = max(w0, (p + 1) * kWave);
-                sym_stream<1>(vs, w1, w0, box, cull2, lane, tile, tile, tix, fetch_p, [&](int my) {
+                auto tile_fn = [&](int my) {
                     float bx = 0.f, by = 0.f, bz = 0.f;
                     const float4 *t = tile + lane;
                     for (int s = 0; s < kWave; s += 8) {
@@ -1989,7 +2056,8 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                         red.y[my] += by;
                         red.z[my] += bz;
                     }
-                }, [&](int chunks) {
+                };
+                auto rows_fn = [&](int chunks) {
                     const float4 *t = tile + kWave + (lane & 15);
                     for (int k = 0; k < chunks; ++k) {
                         row_chunk(tile, k, lane);
@@ -2014,7 +2082,11 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                             red.z[my] += bz;
                         }
                     }
-                });
+                };
+                if constexpr (kW == 256)
+                    sym_stream_held(held, vs, w1, w0, box, cull2, lane, tile, tix, tile_fn, rows_fn);
+                else
+                    sym_stream<1>(vs, w1, w0, box, cull2, lane, tile, tile, tix, fetch_p, tile_fn, rows_fn);
                 const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
                 pool[o] = ax;
                 pool[o + 1] = ay;

@@ -244,6 +244,10 @@ std::atomic<int> g_occ_default[2] = {{6}, {0}};
 std::atomic<int> g_sym_blocks[2] = {{16}, {16}};
 std::atomic<int> g_sym_window[2] = {{256}, {256}};
 std::atomic<int> g_sym_occ[2] = {{5}, {5}};
+// Consecutive windows per symmetric item: an item sums its blocks' targets
+// over both windows into one partial slot, halving the target slots the
+// gather reads and the per-block set-up (boxes, target loads) per window.
+std::atomic<int> g_sym_rounds[2] = {{2}, {2}};
 std::atomic<double> g_sym_balance{1.0};
 std::atomic<int> g_sparse_group{kSparseGroup};
 
@@ -272,6 +276,10 @@ struct EnvDefaults {
             if (const char *v = std::getenv("SR_SYM_WINDOW")) {
                 const int w = std::atoi(v);
                 if (w == 256 || w == 512) g_sym_window[k] = w;
+            }
+            if (const char *v = std::getenv("SR_SYM_ROUNDS")) {
+                const int r = std::atoi(v);
+                if (r == 1 || r == 2) g_sym_rounds[k] = r;
             }
             if (const char *v = std::getenv("SR_SYM_OCC")) {
                 const int o = std::atoi(v);
@@ -333,6 +341,7 @@ sr_status device_args(DevArgs &a, void *ws, const Layout *L, const SegParams *se
     a.occupancy = g_occ_default[cfg].load();
     a.sym_blocks = g_sym_blocks[cfg].load();
     a.sym_window = g_sym_window[cfg].load();
+    a.sym_rounds = g_sym_rounds[cfg].load();
     a.sym_occupancy = g_sym_occ[cfg].load();
     a.sym_balance = g_sym_balance.load();
     a.sparse_group = g_sparse_group.load();
@@ -434,6 +443,9 @@ sr_status run_batched(sr_batch_plan *P, const float *pos, const float *mass, voi
     // the plan's tuner already timed the tiles against none, and the same
     // decision must hold in every mode (bitwise agreement): no balance rule
     a.sym_balance = 0.0;
+    // one window per item: the tuner's tile choices were timed that way, and
+    // a plan's many small problems gain little from fewer target slots
+    a.sym_rounds = 1;
     hipError_t e = hipMemcpyAsync(static_cast<char *>(ws) + P->L.seg, P->pinned,
                                   sizeof(SegParams) * P->B, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return SR_E_DEVICE;
@@ -460,6 +472,7 @@ sr_status run_per_subvolume(sr_batch_plan *P, const float *pos, const float *mas
         if (P->sym_window > 0) a.sym_window = P->sym_window;
         if (P->sparse_group > 0) a.sparse_group = P->sparse_group;
         a.sym_balance = 0.0;
+        a.sym_rounds = 1;
         if (n > 0) {
             if (dev_bin(a, pos + 3 * off, mass + off) != hipSuccess) return SR_E_DEVICE;
             if (P->n_active[b] > 0 && dev_force(a, acc + 3 * out_off) != hipSuccess) return SR_E_DEVICE;

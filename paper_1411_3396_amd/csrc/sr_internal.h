@@ -145,6 +145,7 @@ struct DevArgs {
     int occupancy;         // register-allocation hint of the pair kernels: 0, 6 or 8 waves/SIMD
     int sym_blocks;        // symmetric tiles: blocks of 64 targets per item (0: symmetric tiles off)
     int sym_window;        // symmetric tiles: sources per item window (256 or 512)
+    int sym_rounds;        // symmetric tiles: consecutive windows per item (1 or 2)
     int sym_occupancy;     // symmetric tiles: register-allocation hint, 0 or 5 waves/SIMD
     double sym_balance;    // symmetric tiles run only if their steps per wave reach this many longest items
     int sparse_group;      // most targets per item of a cell (or remainder) with fewer than 64: 8, 16, 32 or 64

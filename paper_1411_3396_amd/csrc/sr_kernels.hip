@@ -1459,19 +1459,20 @@ __device__ __forceinline__ void full_dir(int f, int &dx, int &dy, int &dz)
 }
 
 // Per cell c, the partial-slot counts of its row of kSymStride groups: [0]
-// target slots (windows of c times its dense particles); [1 + e] source slots
+// target slots (items per run, each R consecutive windows, times its dense
+// particles); [1 + e] source slots
 // of its dense particles for direction e of the half stencil (runs of the
 // cell c - dir_e times the dense particles); [15 + f] source slots of its
 // non-dense particles for direction f of the full stencil (runs of the cell
 // c - dir_f times the non-dense particles).  Stored as the row's exclusive
 // prefix sums in pref and the row total in tot[c]; a scan of tot gives each
 // cell's first slot, so group e of cell c starts at base[c] + pref[c][e].
-// Also the item count and cost class of c as a home cell (runs times
-// windows) in info[c], and the slot total of all cells (int64, header).  The
+// Also the item count and cost class of c as a home cell (runs times window
+// groups) in info[c], and the slot total of all cells (int64, header).  The
 // workgroup's rows are assembled in LDS and stored as one contiguous run.
 template <class Acc>
 __global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *__restrict__ start,
-                                                   const int *__restrict__ nact, int K, int W,
+                                                   const int *__restrict__ nact, int K, int W, int R,
                                                    int *__restrict__ pref, int *__restrict__ tot_out,
                                                    uint32_t *__restrict__ info, uint32_t *hdr,
                                                    uint32_t magic)
@@ -1544,13 +1545,14 @@ __global__ __launch_bounds__(256) void k_sym_count(Acc acc, int NC, const int *_
             row[0] = 0;
             if (D > 0) {
                 const int nb = D / kWave;
-                const int64_t C = (sv + W - 1) / W;
+                const int64_t C = (sv + W - 1) / W;         // windows
+                const int64_t CR = (C + R - 1) / R;         // items per run: R windows each
                 const int64_t G = (nb + K - 1) / K;
-                row[0] = (int)min(C * D, (int64_t)INT32_MAX);
-                slots += (unsigned long long)(C * D);
-                const int64_t n_items = G * C;
-                // tile steps of the widest item: its blocks times its window
-                int64_t cost = (int64_t)min(nb, K) * min((int64_t)W, sv);
+                row[0] = (int)min(CR * D, (int64_t)INT32_MAX);
+                slots += (unsigned long long)(CR * D);
+                const int64_t n_items = G * CR;
+                // tile steps of the widest item: its blocks times its windows
+                int64_t cost = (int64_t)min(nb, K) * min((int64_t)R * W, sv);
                 if (cost < 1) cost = 1;
                 int cls = 63 - __clzll((unsigned long long)cost);
                 cls = cls > 31 ? 31 : cls;
@@ -1964,7 +1966,7 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
                                                 const int *__restrict__ nact,
                                                 const int *__restrict__ sym_base,
                                                 const int *__restrict__ sym_pref, const Src &src,
-                                                float *__restrict__ pool, int K, float4 *tile,
+                                                float *__restrict__ pool, int K, int R, float4 *tile,
                                                 int *tix, SymRed<kW> &red, int64_t pull_limit)
 {
     const int lane = threadIdx.x;
@@ -1981,7 +1983,7 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
             const int64_t gi = next_item(hdr, q, lane, kHdrSymQueue);
             if (gi >= n_items || !guard.accept(gi)) break;
             const int4 it = load_item(items, gi);
-            const int c = it.x, g = it.y, k = it.z;
+            const int c = it.x, g = it.y, kk = it.z;  // kk: the item's group of R windows
             const SegParams &S = acc.get(it.w);
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
             float cq[6];
@@ -1992,120 +1994,132 @@ __device__ __forceinline__ void force_sym_items(const Acc &acc, const int4 *__re
             sym_stencil_setup(S, c, start, nact, sym_base, sym_pref, lane, st);
             const int D = __shfl(st.cnt, 0);  // segment 0 is the cell itself
             const int c0s = start[c];
-            const int w0 = k * kW, w1 = min(w0 + kW, st.total);
-            const int tbase = sym_base[c] + k * D;  // group 0: the target slots
-            for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
+            const int tbase = sym_base[c] + kk * D;  // group 0: the target slots
             const int p0 = g * K, p1 = min(p0 + K, D / kWave);
-            auto fetch_p = [&](int v, float4 &a, float4 &) {
-                int slot;
-                a = sym_fetch_pos(st, v, w1, src, slot);
-            };
-            // windows of 256: the window's sources once, held in registers for all blocks
-            constexpr int kHeld = kW == 256 ? kW / kWave : 1;
-            float4 held[kHeld];
-#pragma unroll
-            for (int i = 0; i < kHeld; ++i) {
-                held[i] = make_float4(kFar, kFar, kFar, 0.f);
-                if (kW == 256 && w0 + i * kWave < w1) {
+            const int k_end = min((kk + 1) * R, (st.total + kW - 1) / kW);
+            // the group's windows in turn: the first stores each block's target sums
+            // to its slot, the next ones add to it (this wave alone writes the slot)
+            for (int k = kk * R; k < k_end; ++k) {
+                const bool first = k == kk * R;
+                const int w0 = k * kW, w1 = min(w0 + kW, st.total);
+                for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
+                auto fetch_p = [&](int v, float4 &a, float4 &) {
                     int slot;
-                    held[i] = sym_fetch_pos(st, w0 + i * kWave + lane, w1, src, slot);
-                }
-            }
-            for (int p = p0; p < p1; ++p) {
-                const int b = c0s + p * kWave + lane;
-                const float px = src.x[b], py = src.y[b], pz = src.z[b];
-                const float mi = kUM ? 1.f : src.m[b];
-                const Box box = target_box(true, px, py, pz, false, 0.f, 0.f, 0.f);
-                float ax = 0.f, ay = 0.f, az = 0.f;
-                if (p * kWave >= w0 && p * kWave < w1) {
-                    // the block against itself: steps 1..32, the last one on half the lanes
-                    __syncthreads();
-                    tile[lane] = make_float4(px, py, pz, src.m[b]);
-                    tile[lane + kWave] = tile[lane];
-                    __syncthreads();
-                    float bx = 0.f, by = 0.f, bz = 0.f;
-                    for (int s = 1; s <= kWave / 2; ++s) {
-                        float4 sj = tile[lane + s];
-                        if (s == kWave / 2 && lane >= kWave / 2) sj = make_float4(kFar, kFar, kFar, 0.f);
-                        sym_force_step<kSoft, kUM>(sj, px, py, pz, mi, eps2, tc2, cq, ax, ay, az, bx, by, bz);
-                        bx = rotate_down(bx);
-                        by = rotate_down(by);
-                        bz = rotate_down(bz);
-                    }
-                    const int r = p * kWave - w0 + ((lane + kWave / 2 + 1) & (kWave - 1));
-                    red.x[r] += bx;
-                    red.y[r] += by;
-                    red.z[r] += bz;
-                }
-                const int vs = max(w0, (p + 1) * kWave);
-                auto tile_fn = [&](int my) {
-                    float bx = 0.f, by = 0.f, bz = 0.f;
-                    const float4 *t = tile + lane;
-                    for (int s = 0; s < kWave; s += 8) {
+                    a = sym_fetch_pos(st, v, w1, src, slot);
+                };
+                // windows of 256: the window's sources once, held in registers for all blocks
+                constexpr int kHeld = kW == 256 ? kW / kWave : 1;
+                float4 held[kHeld];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            sym_force_step<kSoft, kUM>(t[s + u], px, py, pz, mi, eps2, tc2, cq, ax, ay, az,
-                                                       bx, by, bz);
+                for (int i = 0; i < kHeld; ++i) {
+                    held[i] = make_float4(kFar, kFar, kFar, 0.f);
+                    if (kW == 256 && w0 + i * kWave < w1) {
+                        int slot;
+                        held[i] = sym_fetch_pos(st, w0 + i * kWave + lane, w1, src, slot);
+                    }
+                }
+                for (int p = p0; p < p1; ++p) {
+                    const int b = c0s + p * kWave + lane;
+                    const float px = src.x[b], py = src.y[b], pz = src.z[b];
+                    const float mi = kUM ? 1.f : src.m[b];
+                    const Box box = target_box(true, px, py, pz, false, 0.f, 0.f, 0.f);
+                    float ax = 0.f, ay = 0.f, az = 0.f;
+                    if (p * kWave >= w0 && p * kWave < w1) {
+                        // the block against itself: steps 1..32, the last one on half the lanes
+                        __syncthreads();
+                        tile[lane] = make_float4(px, py, pz, src.m[b]);
+                        tile[lane + kWave] = tile[lane];
+                        __syncthreads();
+                        float bx = 0.f, by = 0.f, bz = 0.f;
+                        for (int s = 1; s <= kWave / 2; ++s) {
+                            float4 sj = tile[lane + s];
+                            if (s == kWave / 2 && lane >= kWave / 2) sj = make_float4(kFar, kFar, kFar, 0.f);
+                            sym_force_step<kSoft, kUM>(sj, px, py, pz, mi, eps2, tc2, cq, ax, ay, az, bx, by, bz);
                             bx = rotate_down(bx);
                             by = rotate_down(by);
                             bz = rotate_down(bz);
                         }
+                        const int r = p * kWave - w0 + ((lane + kWave / 2 + 1) & (kWave - 1));
+                        red.x[r] += bx;
+                        red.y[r] += by;
+                        red.z[r] += bz;
                     }
-                    if (my >= 0) {
-                        red.x[my] += bx;
-                        red.y[my] += by;
-                        red.z[my] += bz;
-                    }
-                };
-                auto rows_fn = [&](int chunks) {
-                    const float4 *t = tile + kWave + (lane & 15);
-                    for (int k = 0; k < chunks; ++k) {
-                        row_chunk(tile, k, lane);
+                    const int vs = max(w0, (p + 1) * kWave);
+                    auto tile_fn = [&](int my) {
                         float bx = 0.f, by = 0.f, bz = 0.f;
-                        for (int s = 0; s < 16; s += 8) {
+                        const float4 *t = tile + lane;
+                        for (int s = 0; s < kWave; s += 8) {
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
-                                sym_force_step<kSoft, kUM>(t[s + u], px, py, pz, mi, eps2, tc2, cq, ax, ay,
-                                                           az, bx, by, bz);
-                                bx = rotate_row(bx);
-                                by = rotate_row(by);
-                                bz = rotate_row(bz);
+                                sym_force_step<kSoft, kUM>(t[s + u], px, py, pz, mi, eps2, tc2, cq, ax, ay, az,
+                                                           bx, by, bz);
+                                bx = rotate_down(bx);
+                                by = rotate_down(by);
+                                bz = rotate_down(bz);
                             }
                         }
-                        bx = sum_rows(bx);
-                        by = sum_rows(by);
-                        bz = sum_rows(bz);
-                        const int my = tix[16 * k + (lane & 15)];
-                        if (lane < 16 && my >= 0) {
+                        if (my >= 0) {
                             red.x[my] += bx;
                             red.y[my] += by;
                             red.z[my] += bz;
                         }
+                    };
+                    auto rows_fn = [&](int chunks) {
+                        const float4 *t = tile + kWave + (lane & 15);
+                        for (int k = 0; k < chunks; ++k) {
+                            row_chunk(tile, k, lane);
+                            float bx = 0.f, by = 0.f, bz = 0.f;
+                            for (int s = 0; s < 16; s += 8) {
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    sym_force_step<kSoft, kUM>(t[s + u], px, py, pz, mi, eps2, tc2, cq, ax, ay,
+                                                               az, bx, by, bz);
+                                    bx = rotate_row(bx);
+                                    by = rotate_row(by);
+                                    bz = rotate_row(bz);
+                                }
+                            }
+                            bx = sum_rows(bx);
+                            by = sum_rows(by);
+                            bz = sum_rows(bz);
+                            const int my = tix[16 * k + (lane & 15)];
+                            if (lane < 16 && my >= 0) {
+                                red.x[my] += bx;
+                                red.y[my] += by;
+                                red.z[my] += bz;
+                            }
+                        }
+                    };
+                    if constexpr (kW == 256)
+                        sym_stream_held(held, vs, w1, w0, box, cull2, lane, tile, tix, tile_fn, rows_fn);
+                    else
+                        sym_stream<1>(vs, w1, w0, box, cull2, lane, tile, tile, tix, fetch_p, tile_fn, rows_fn);
+                    const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
+                    if (first) {
+                        pool[o] = ax;
+                        pool[o + 1] = ay;
+                        pool[o + 2] = az;
+                    } else {
+                        pool[o] += ax;
+                        pool[o + 1] += ay;
+                        pool[o + 2] += az;
                     }
-                };
-                if constexpr (kW == 256)
-                    sym_stream_held(held, vs, w1, w0, box, cull2, lane, tile, tix, tile_fn, rows_fn);
-                else
-                    sym_stream<1>(vs, w1, w0, box, cull2, lane, tile, tile, tix, fetch_p, tile_fn, rows_fn);
-                const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
-                pool[o] = ax;
-                pool[o + 1] = ay;
-                pool[o + 2] = az;
-            }
-            __syncthreads();
-            // the window's opposite sums to their source slots
-            for (int i = 0; i < w1 - w0; i += kWave) {
-                const int v = w0 + i + lane;
-                const int q = sym_locate(st, v);
-                const int64_t slot = (int64_t)__shfl(st.sbase, q) + (int64_t)g * __shfl(st.cnt, q) +
-                                     (min(v, st.total - 1) - __shfl(st.excl, q));
-                if (v < w1) {
-                    pool[3 * slot] = red.x[i + lane];
-                    pool[3 * slot + 1] = red.y[i + lane];
-                    pool[3 * slot + 2] = red.z[i + lane];
                 }
+                __syncthreads();
+                // the window's opposite sums to their source slots
+                for (int i = 0; i < w1 - w0; i += kWave) {
+                    const int v = w0 + i + lane;
+                    const int q = sym_locate(st, v);
+                    const int64_t slot = (int64_t)__shfl(st.sbase, q) + (int64_t)g * __shfl(st.cnt, q) +
+                                         (min(v, st.total - 1) - __shfl(st.excl, q));
+                    if (v < w1) {
+                        pool[3 * slot] = red.x[i + lane];
+                        pool[3 * slot + 1] = red.y[i + lane];
+                        pool[3 * slot + 2] = red.z[i + lane];
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     guard.report(hdr, lane);
@@ -2117,17 +2131,17 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_force_sym(Acc acc, 
                                                   const int *__restrict__ nact,
                                                   const int *__restrict__ sym_base,
                                                   const int *__restrict__ sym_pref, Src src,
-                                                  float *__restrict__ pool, int K, int64_t pull_limit)
+                                                  float *__restrict__ pool, int K, int R, int64_t pull_limit)
 {
     __shared__ float4 tile[2 * kWave];
     __shared__ int tix[kWave];
     __shared__ SymRed<kW> red;
     if (hdr[kHdrMassInfo] == 0)
-        force_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, pool, K, tile,
-                                              tix, red, pull_limit);
+        force_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, pool, K, R,
+                                              tile, tix, red, pull_limit);
     else
-        force_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, pool, K, tile,
-                                               tix, red, pull_limit);
+        force_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, pool, K, R,
+                                               tile, tix, red, pull_limit);
 }
 
 // Adjoint symmetric items: as the forward, with the cotangent staged beside
@@ -2140,7 +2154,7 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
                                               const int *__restrict__ sym_pref, const Src &src,
                                               const float *__restrict__ gx, const float *__restrict__ gy,
                                               const float *__restrict__ gz, float *__restrict__ pool,
-                                              int K, float4 *tile_p, float4 *tile_g, int *tix,
+                                              int K, int R, float4 *tile_p, float4 *tile_g, int *tix,
                                               SymRed<kW> &red, int64_t pull_limit)
 {
     const int lane = threadIdx.x;
@@ -2157,7 +2171,7 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
             const int64_t gi = next_item(hdr, q, lane, kHdrSymQueue);
             if (gi >= n_items || !guard.accept(gi)) break;
             const int4 it = load_item(items, gi);
-            const int c = it.x, g = it.y, k = it.z;
+            const int c = it.x, g = it.y, kk = it.z;  // kk: the item's group of R windows
             const SegParams &S = acc.get(it.w);
             const float eps2 = S.pc.eps2, tc2 = S.pc.tc2, cull2 = S.pc.cull2;
             float cq[6], cd[5];
@@ -2171,118 +2185,130 @@ __device__ __forceinline__ void vjp_sym_items(const Acc &acc, const int4 *__rest
             sym_stencil_setup(S, c, start, nact, sym_base, sym_pref, lane, st);
             const int D = __shfl(st.cnt, 0);
             const int c0s = start[c];
-            const int w0 = k * kW, w1 = min(w0 + kW, st.total);
-            const int tbase = sym_base[c] + k * D;  // group 0: the target slots
-            for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
+            const int tbase = sym_base[c] + kk * D;  // group 0: the target slots
             const int p0 = g * K, p1 = min(p0 + K, D / kWave);
-            auto fetch_pg = [&](int v, float4 &a, float4 &gv) {
-                int slot;
-                a = sym_fetch_pos(st, v, w1, src, slot);
-                gv = make_float4(gx[slot], gy[slot], gz[slot], 0.f);
-                if (v >= w1) gv = make_float4(0.f, 0.f, 0.f, 0.f);
-            };
-            for (int p = p0; p < p1; ++p) {
-                const int b = c0s + p * kWave + lane;
-                const float px = src.x[b], py = src.y[b], pz = src.z[b], mk = src.m[b];
-                const float gkx = gx[b], gky = gy[b], gkz = gz[b];
-                const Box box = target_box(true, px, py, pz, false, 0.f, 0.f, 0.f);
-                float rx = 0.f, ry = 0.f, rz = 0.f;
-                if (p * kWave >= w0 && p * kWave < w1) {
-                    __syncthreads();
-                    tile_p[lane] = make_float4(px, py, pz, mk);
-                    tile_p[lane + kWave] = tile_p[lane];
-                    tile_g[lane] = make_float4(gkx, gky, gkz, 0.f);
-                    tile_g[lane + kWave] = tile_g[lane];
-                    __syncthreads();
-                    float bx = 0.f, by = 0.f, bz = 0.f;
-                    for (int s = 1; s <= kWave / 2; ++s) {
-                        float4 sj = tile_p[lane + s];
-                        float4 sg = tile_g[lane + s];
-                        if (s == kWave / 2 && lane >= kWave / 2) {
-                            sj = make_float4(kFar, kFar, kFar, 0.f);
-                            sg = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int k_end = min((kk + 1) * R, (st.total + kW - 1) / kW);
+            // the group's windows in turn: the first stores each block's target sums
+            // to its slot, the next ones add to it (this wave alone writes the slot)
+            for (int k = kk * R; k < k_end; ++k) {
+                const bool first = k == kk * R;
+                const int w0 = k * kW, w1 = min(w0 + kW, st.total);
+                for (int i = lane; i < kW; i += kWave) red.x[i] = red.y[i] = red.z[i] = 0.f;
+                auto fetch_pg = [&](int v, float4 &a, float4 &gv) {
+                    int slot;
+                    a = sym_fetch_pos(st, v, w1, src, slot);
+                    gv = make_float4(gx[slot], gy[slot], gz[slot], 0.f);
+                    if (v >= w1) gv = make_float4(0.f, 0.f, 0.f, 0.f);
+                };
+                for (int p = p0; p < p1; ++p) {
+                    const int b = c0s + p * kWave + lane;
+                    const float px = src.x[b], py = src.y[b], pz = src.z[b], mk = src.m[b];
+                    const float gkx = gx[b], gky = gy[b], gkz = gz[b];
+                    const Box box = target_box(true, px, py, pz, false, 0.f, 0.f, 0.f);
+                    float rx = 0.f, ry = 0.f, rz = 0.f;
+                    if (p * kWave >= w0 && p * kWave < w1) {
+                        __syncthreads();
+                        tile_p[lane] = make_float4(px, py, pz, mk);
+                        tile_p[lane + kWave] = tile_p[lane];
+                        tile_g[lane] = make_float4(gkx, gky, gkz, 0.f);
+                        tile_g[lane + kWave] = tile_g[lane];
+                        __syncthreads();
+                        float bx = 0.f, by = 0.f, bz = 0.f;
+                        for (int s = 1; s <= kWave / 2; ++s) {
+                            float4 sj = tile_p[lane + s];
+                            float4 sg = tile_g[lane + s];
+                            if (s == kWave / 2 && lane >= kWave / 2) {
+                                sj = make_float4(kFar, kFar, kFar, 0.f);
+                                sg = make_float4(0.f, 0.f, 0.f, 0.f);
+                            }
+                            sym_vjp_step<kSoft, kUM>(sj, sg, px, py, pz, mk, gkx, gky, gkz, eps2, tc2, cq, cd, rx,
+                                                     ry, rz, bx, by, bz);
+                            bx = rotate_down(bx);
+                            by = rotate_down(by);
+                            bz = rotate_down(bz);
                         }
-                        sym_vjp_step<kSoft, kUM>(sj, sg, px, py, pz, mk, gkx, gky, gkz, eps2, tc2, cq, cd, rx,
-                                                 ry, rz, bx, by, bz);
-                        bx = rotate_down(bx);
-                        by = rotate_down(by);
-                        bz = rotate_down(bz);
+                        const int r = p * kWave - w0 + ((lane + kWave / 2 + 1) & (kWave - 1));
+                        red.x[r] += bx;
+                        red.y[r] += by;
+                        red.z[r] += bz;
                     }
-                    const int r = p * kWave - w0 + ((lane + kWave / 2 + 1) & (kWave - 1));
-                    red.x[r] += bx;
-                    red.y[r] += by;
-                    red.z[r] += bz;
-                }
-                const int vs = max(w0, (p + 1) * kWave);
-                sym_stream<2>(vs, w1, w0, box, cull2, lane, tile_p, tile_g, tix, fetch_pg,
-                              [&](int my) {
-                                  float bx = 0.f, by = 0.f, bz = 0.f;
-                                  const float4 *tp = tile_p + lane;
-                                  const float4 *tg = tile_g + lane;
-                                  for (int s = 0; s < kWave; s += 4) {
-#pragma unroll
-                                      for (int u = 0; u < 4; ++u) {
-                                          sym_vjp_step<kSoft, kUM>(tp[s + u], tg[s + u], px, py, pz, mk, gkx,
-                                                                   gky, gkz, eps2, tc2, cq, cd, rx, ry, rz,
-                                                                   bx, by, bz);
-                                          bx = rotate_down(bx);
-                                          by = rotate_down(by);
-                                          bz = rotate_down(bz);
-                                      }
-                                  }
-                                  if (my >= 0) {
-                                      red.x[my] += bx;
-                                      red.y[my] += by;
-                                      red.z[my] += bz;
-                                  }
-                              },
-                              [&](int chunks) {
-                                  const float4 *tp = tile_p + kWave + (lane & 15);
-                                  const float4 *tg = tile_g + kWave + (lane & 15);
-                                  for (int k = 0; k < chunks; ++k) {
-                                      row_chunk(tile_p, k, lane);
-                                      row_chunk(tile_g, k, lane);
+                    const int vs = max(w0, (p + 1) * kWave);
+                    sym_stream<2>(vs, w1, w0, box, cull2, lane, tile_p, tile_g, tix, fetch_pg,
+                                  [&](int my) {
                                       float bx = 0.f, by = 0.f, bz = 0.f;
-                                      for (int s = 0; s < 16; s += 4) {
+                                      const float4 *tp = tile_p + lane;
+                                      const float4 *tg = tile_g + lane;
+                                      for (int s = 0; s < kWave; s += 4) {
 #pragma unroll
                                           for (int u = 0; u < 4; ++u) {
-                                              sym_vjp_step<kSoft, kUM>(tp[s + u], tg[s + u], px, py, pz, mk,
-                                                                       gkx, gky, gkz, eps2, tc2, cq, cd, rx,
-                                                                       ry, rz, bx, by, bz);
-                                              bx = rotate_row(bx);
-                                              by = rotate_row(by);
-                                              bz = rotate_row(bz);
+                                              sym_vjp_step<kSoft, kUM>(tp[s + u], tg[s + u], px, py, pz, mk, gkx,
+                                                                       gky, gkz, eps2, tc2, cq, cd, rx, ry, rz,
+                                                                       bx, by, bz);
+                                              bx = rotate_down(bx);
+                                              by = rotate_down(by);
+                                              bz = rotate_down(bz);
                                           }
                                       }
-                                      bx = sum_rows(bx);
-                                      by = sum_rows(by);
-                                      bz = sum_rows(bz);
-                                      const int my = tix[16 * k + (lane & 15)];
-                                      if (lane < 16 && my >= 0) {
+                                      if (my >= 0) {
                                           red.x[my] += bx;
                                           red.y[my] += by;
                                           red.z[my] += bz;
                                       }
-                                  }
-                              });
-                const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
-                pool[o] = rx;
-                pool[o + 1] = ry;
-                pool[o + 2] = rz;
-            }
-            __syncthreads();
-            for (int i = 0; i < w1 - w0; i += kWave) {
-                const int v = w0 + i + lane;
-                const int q = sym_locate(st, v);
-                const int64_t slot = (int64_t)__shfl(st.sbase, q) + (int64_t)g * __shfl(st.cnt, q) +
-                                     (min(v, st.total - 1) - __shfl(st.excl, q));
-                if (v < w1) {
-                    pool[3 * slot] = red.x[i + lane];
-                    pool[3 * slot + 1] = red.y[i + lane];
-                    pool[3 * slot + 2] = red.z[i + lane];
+                                  },
+                                  [&](int chunks) {
+                                      const float4 *tp = tile_p + kWave + (lane & 15);
+                                      const float4 *tg = tile_g + kWave + (lane & 15);
+                                      for (int k = 0; k < chunks; ++k) {
+                                          row_chunk(tile_p, k, lane);
+                                          row_chunk(tile_g, k, lane);
+                                          float bx = 0.f, by = 0.f, bz = 0.f;
+                                          for (int s = 0; s < 16; s += 4) {
+#pragma unroll
+                                              for (int u = 0; u < 4; ++u) {
+                                                  sym_vjp_step<kSoft, kUM>(tp[s + u], tg[s + u], px, py, pz, mk,
+                                                                           gkx, gky, gkz, eps2, tc2, cq, cd, rx,
+                                                                           ry, rz, bx, by, bz);
+                                                  bx = rotate_row(bx);
+                                                  by = rotate_row(by);
+                                                  bz = rotate_row(bz);
+                                              }
+                                          }
+                                          bx = sum_rows(bx);
+                                          by = sum_rows(by);
+                                          bz = sum_rows(bz);
+                                          const int my = tix[16 * k + (lane & 15)];
+                                          if (lane < 16 && my >= 0) {
+                                              red.x[my] += bx;
+                                              red.y[my] += by;
+                                              red.z[my] += bz;
+                                          }
+                                      }
+                                  });
+                    const int64_t o = 3 * ((int64_t)tbase + p * kWave + lane);
+                    if (first) {
+                        pool[o] = rx;
+                        pool[o + 1] = ry;
+                        pool[o + 2] = rz;
+                    } else {
+                        pool[o] += rx;
+                        pool[o + 1] += ry;
+                        pool[o + 2] += rz;
+                    }
                 }
+                __syncthreads();
+                for (int i = 0; i < w1 - w0; i += kWave) {
+                    const int v = w0 + i + lane;
+                    const int q = sym_locate(st, v);
+                    const int64_t slot = (int64_t)__shfl(st.sbase, q) + (int64_t)g * __shfl(st.cnt, q) +
+                                         (min(v, st.total - 1) - __shfl(st.excl, q));
+                    if (v < w1) {
+                        pool[3 * slot] = red.x[i + lane];
+                        pool[3 * slot + 1] = red.y[i + lane];
+                        pool[3 * slot + 2] = red.z[i + lane];
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     guard.report(hdr, lane);
@@ -2296,7 +2322,7 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, co
                                                 const int *__restrict__ sym_pref, Src src,
                                                 const float *__restrict__ gx, const float *__restrict__ gy,
                                                 const float *__restrict__ gz, float *__restrict__ pool, int K,
-                                                int64_t pull_limit)
+                                                int R, int64_t pull_limit)
 {
     __shared__ float4 tile_p[2 * kWave];
     __shared__ float4 tile_g[2 * kWave];
@@ -2304,10 +2330,10 @@ __global__ __launch_bounds__(64, kOcc > 0 ? kOcc : 1) void k_vjp_sym(Acc acc, co
     __shared__ SymRed<kW> red;
     if (hdr[kHdrMassInfo] == 0)
         vjp_sym_items<Acc, kSoft, true, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, gx, gy, gz, pool, K,
-                                            tile_p, tile_g, tix, red, pull_limit);
+                                            R, tile_p, tile_g, tix, red, pull_limit);
     else
         vjp_sym_items<Acc, kSoft, false, kW>(acc, items, hdr, start, nact, sym_base, sym_pref, src, gx, gy, gz, pool, K,
-                                             tile_p, tile_g, tix, red, pull_limit);
+                                             R, tile_p, tile_g, tix, red, pull_limit);
 }
 
 // Adds up the partial slots of every particle, in a fixed order.  A dense
@@ -2510,7 +2536,7 @@ hipError_t build_sym(const DevArgs &a)
     return with_acc(a, [&](auto acc) -> hipError_t {
         const unsigned nb = blocks_for(L.NC, 256);
         k_sym_count<<<nb, 256, 0, a.st>>>(acc, (int)L.NC, at<int>(a, L.start), at<int>(a, L.nact),
-                                          a.sym_blocks, W,
+                                          a.sym_blocks, W, a.sym_rounds,
                                           at<int>(a, L.sym_pref), at<int>(a, L.sym_tot),
                                           at<uint32_t>(a, L.sym_info), hdr, L.magic());
         hipError_t e2 = hipGetLastError();
@@ -2657,7 +2683,7 @@ void launch_force_sym_v(const DevArgs &a, Acc acc, unsigned grid)
     k_force_sym<Acc, kSoft, kW, kOcc><<<grid, kWave, 0, a.st>>>(
         acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
         at<int>(a, L.sym_base), at<int>(a, L.sym_pref), src_of(a), at<float>(a, L.sym_pool), a.sym_blocks,
-        a.pull_limit);
+        a.sym_rounds, a.pull_limit);
 }
 
 template <class Acc, bool kSoft>
@@ -2683,7 +2709,7 @@ void launch_vjp_sym_v(const DevArgs &a, Acc acc, unsigned grid)
     k_vjp_sym<Acc, kSoft, kW, kOcc><<<grid, kWave, 0, a.st>>>(
         acc, at<int4>(a, L.sym_items), at<uint32_t>(a, L.hdr), at<int>(a, L.start), at<int>(a, L.nact),
         at<int>(a, L.sym_base), at<int>(a, L.sym_pref), src_of(a), at<float>(a, L.gx), at<float>(a, L.gy),
-        at<float>(a, L.gz), at<float>(a, L.sym_pool), a.sym_blocks, a.pull_limit);
+        at<float>(a, L.gz), at<float>(a, L.sym_pool), a.sym_blocks, a.sym_rounds, a.pull_limit);
 }
 
 template <class Acc, bool kSoft>
